@@ -1,0 +1,294 @@
+"""Pins that tie the CPU oracle to something other than itself.
+
+Each ``pin_*`` takes an oracle module (the real one, or a copy with a planted
+mistake) and raises AssertionError if the module disagrees with:
+
+* the hand-worked fixtures in tests/golden/hand_cases.json,
+* the exact rational brute force (index) and exactly rounded sums,
+* SciPy's ``binned_statistic_2d`` and NumPy's ``histogram2d``,
+* invariants and metamorphic relations of the binning definition.
+
+The real oracle must pass all of them; every planted mistake must fail at
+least one (tests/test_oracle_mutants.py).
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+ALL = 31
+
+
+def _num(v):
+    if isinstance(v, str):
+        return {"nan": math.nan, "inf": math.inf, "-inf": -math.inf, "-0": -0.0}[v]
+    return float(v)
+
+
+def _arr(nested):
+    if isinstance(nested, list):
+        return np.array([_arr(x) for x in nested])
+    return _num(nested)
+
+
+def same_bits(a, b) -> bool:
+    """Equal as binary64 bit patterns, any NaN equal to any NaN."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    if a.shape != b.shape:
+        return False
+    nan = np.isnan(a) & np.isnan(b)
+    return bool(np.all(nan | (a.view(np.int64) == b.view(np.int64))))
+
+
+def golden_cases():
+    with open(os.path.join(HERE, "golden", "hand_cases.json")) as f:
+        return json.load(f)["cases"]
+
+
+def pin_golden(orc):
+    for case in golden_cases():
+        cols = [np.array([_num(v) for v in case[c]]) for c in ("x", "y", "z") if c in case]
+        attrs = [np.array([_num(v) for v in case[c]]) for c in ("a", "b") if c in case]
+        r = orc.bin_particles(cols, attrs, tuple(case["axes"]), tuple(case["bounds"]),
+                              case["nx"], case["ny"], ALL)
+        name = case["name"]
+        assert r["inside"] == case["inside"], name
+        assert np.array_equal(r["count"], np.array(case["count"])), name
+        for j in range(len(attrs)):
+            assert np.array_equal(r["sum"][j], _arr(case["sum"][j])), (name, "sum", j)
+            assert same_bits(r["min"][j], _arr(case["min"][j])), (name, "min", j)
+            assert same_bits(r["max"][j], _arr(case["max"][j])), (name, "max", j)
+            assert same_bits(r["avg"][j], _arr(case["avg"][j])), (name, "avg", j)
+
+
+def _compare_to_bruteforce(orc, coords, attrs, axes, bounds, nx, ny, sum_rel=1e-13):
+    r = orc.bin_particles(coords, attrs, axes, bounds, nx, ny, ALL)
+    bf = orc_bruteforce(coords, attrs, axes, bounds, nx, ny)
+    assert r["inside"] == bf["inside"]
+    assert np.array_equal(r["count"], bf["count"])
+    for j in range(len(attrs)):
+        assert np.all(np.abs(r["sum"][j] - bf["sum"][j]) <= sum_rel * bf["abs_sum"][j]), "sum"
+        assert np.allclose(r["abs_sum"][j], bf["abs_sum"][j], rtol=1e-13, atol=0)
+        assert same_bits(r["min"][j], bf["min"][j]), "min"
+        assert same_bits(r["max"][j], bf["max"][j]), "max"
+        cnt = bf["count"]
+        ok = np.where(cnt == 0, np.isnan(r["avg"][j]),
+                      np.abs(r["avg"][j] - bf["avg"][j]) <= sum_rel * bf["abs_sum"][j] / np.maximum(cnt, 1))
+        assert np.all(ok), "avg"
+
+
+def orc_bruteforce(coords, attrs, axes, bounds, nx, ny):
+    # The brute force is always the unmodified one: it is the independent side.
+    from oracle import binning_oracle as real
+    return real.bin_particles_bruteforce(coords, attrs, axes, bounds, nx, ny)
+
+
+def pin_bruteforce_random(orc):
+    """Random particles incl. outside ones and signed values, dyadic meshes
+    (where the binary64 index formula is exact), against the rational brute force."""
+    rng = np.random.default_rng(123)
+    for (nx, ny, bounds, n) in [(8, 4, (0.0, 1.0, 0.0, 1.0), 600),
+                                (16, 16, (-2.0, 2.0, -1.0, 1.0), 900),
+                                (1, 1, (0.0, 1.0, 0.0, 1.0), 200),
+                                (32, 2, (0.0, 0.5, 0.25, 0.75), 700)]:
+        x = rng.uniform(bounds[0] - 0.1, bounds[1] + 0.1, n)
+        y = rng.uniform(bounds[2] - 0.1, bounds[3] + 0.1, n)
+        z = rng.uniform(-1, 1, n)
+        a = rng.standard_normal(n) * 10
+        m = rng.lognormal(0, 2, n)
+        _compare_to_bruteforce(orc, [x, y, z], [a, m], (0, 1), bounds, nx, ny)
+        _compare_to_bruteforce(orc, [x, y, z], [m], (1, 0), (bounds[2], bounds[3], bounds[0], bounds[1]), ny, nx)
+
+
+def pin_bruteforce_edges(orc):
+    """Every bin edge, its one-ulp neighbours, the bounds, NaN and +-Inf, on
+    dyadic meshes: the binary64 formula must give the exact rational bin."""
+    # lo = 0 keeps x - lo exact; hi - lo and n powers of two keep the scale exact.
+    for (nx, lo, hi, dt) in [(8, 0.0, 1.0, np.float64), (64, 0.0, 1.0, np.float32),
+                             (4, 0.0, 4.0, np.float64), (16, 0.0, 0.5, np.float64),
+                             (1024, 0.0, 1.0, np.float32)]:
+        dtn = np.dtype(dt)
+        e = (lo + (hi - lo) * np.arange(nx + 1) / nx).astype(dtn)
+        pts = np.concatenate([e, np.nextafter(e, dtn.type(-np.inf)), np.nextafter(e, dtn.type(np.inf)),
+                              np.array([np.nan, np.inf, -np.inf], dtype=dtn)])
+        n = pts.size
+        ys = np.full(n, (lo + hi) / 2, dtype=dtn)
+        vals = np.arange(1, n + 1, dtype=np.float64)
+        _compare_to_bruteforce(orc, [pts, ys], [vals], (0, 1), (lo, hi, lo, hi), nx, 1)
+        _compare_to_bruteforce(orc, [ys, pts], [vals], (0, 1), (lo, hi, lo, hi), 1, nx)
+
+
+def pin_general_bounds_near_edges(orc):
+    """Non-dyadic meshes: the binary64 formula may differ from the exact
+    rational bin only for points within a few ulps of a bin edge."""
+    rng = np.random.default_rng(7)
+    for (nx, lo, hi) in [(3, 0.0, 1.0), (10, -0.3, 0.7), (7, 1.0, 1.1), (1000, -5.0, 3.0)]:
+        x = rng.uniform(lo, hi, 3000)
+        edges = [lo + (hi - lo) * i / nx for i in range(nx + 1)]
+        x = np.concatenate([x, np.array(edges), np.nextafter(np.array(edges), np.inf),
+                            np.nextafter(np.array(edges), -np.inf)])
+        ins, idx = orc.axis_index(x, lo, hi, nx)
+        from oracle import binning_oracle as real
+        for i, v in enumerate(x):
+            ex = real._exact_index(float(v), lo, hi, nx)
+            assert (ex is not None) == bool(ins[i])
+            if ex is None or ex == idx[i]:
+                continue
+            # a disagreement must be at an edge between the two candidate bins
+            edge = lo + (hi - lo) * max(ex, int(idx[i])) / nx
+            assert abs(ex - int(idx[i])) == 1
+            assert abs(v - edge) <= 8 * np.spacing(max(abs(edge), abs(v), abs(lo), abs(hi)))
+
+
+def pin_scipy(orc):
+    """SciPy binned_statistic_2d (count/sum/min/max/mean) on dyadic meshes,
+    where its linspace edges equal the binary64 index formula."""
+    from scipy.stats import binned_statistic_2d
+    rng = np.random.default_rng(5)
+    n = 20000
+    nx, ny = 32, 16
+    x = rng.random(n)
+    y = rng.random(n)
+    x[:50] = 1.0           # closed upper edge
+    y[50:100] = 1.0
+    a = rng.standard_normal(n) + 0.5
+    r = orc.bin_particles([x, y], [a], (0, 1), (0.0, 1.0, 0.0, 1.0), nx, ny, ALL)
+    ex = np.linspace(0, 1, nx + 1)
+    ey = np.linspace(0, 1, ny + 1)
+    # SciPy's statistic arrays are [x][y]; ours are [y][x].
+    cnt = binned_statistic_2d(x, y, None, "count", bins=[ex, ey]).statistic.T
+    assert np.array_equal(r["count"], cnt.astype(np.int64))
+    s = binned_statistic_2d(x, y, a, "sum", bins=[ex, ey]).statistic.T
+    assert np.allclose(r["sum"][0], s, rtol=1e-12, atol=1e-12)
+    mn = binned_statistic_2d(x, y, a, "min", bins=[ex, ey]).statistic.T
+    mx = binned_statistic_2d(x, y, a, "max", bins=[ex, ey]).statistic.T
+    mean = binned_statistic_2d(x, y, a, "mean", bins=[ex, ey]).statistic.T
+    full = cnt > 0
+    assert np.array_equal(r["min"][0][full], mn[full])
+    assert np.array_equal(r["max"][0][full], mx[full])
+    assert np.allclose(r["avg"][0][full], mean[full], rtol=1e-12, atol=1e-12)
+    h, _, _ = np.histogram2d(x, y, bins=[ex, ey])
+    assert np.array_equal(r["count"], h.T.astype(np.int64))
+
+
+def pin_invariants(orc):
+    rng = np.random.default_rng(11)
+    n = 50000
+    x = rng.uniform(-0.1, 1.1, n)
+    y = rng.uniform(-0.1, 1.1, n)
+    a = rng.standard_normal(n)
+    m = rng.lognormal(0, 1, n)
+    nx, ny = 20, 30
+    r = orc.bin_particles([x, y], [a, m], (0, 1), (0.0, 1.0, 0.0, 1.0), nx, ny, ALL)
+    inside = int(np.sum((x >= 0) & (x <= 1) & (y >= 0) & (y <= 1)))
+    assert r["inside"] == inside
+    assert int(r["count"].sum()) == inside
+    cnt = r["count"]
+    full = cnt > 0
+    for j in range(2):
+        mn, mx, av, s = r["min"][j], r["max"][j], r["avg"][j], r["sum"][j]
+        tol = 1e-12 * r["abs_sum"][j] / np.maximum(cnt, 1)
+        assert np.all(mn[full] <= av[full] + tol[full])
+        assert np.all(av[full] <= mx[full] + tol[full])
+        assert np.all(np.abs(s - av * cnt)[full] <= 1e-12 * r["abs_sum"][j][full])
+        assert np.all(np.isposinf(mn[~full])) and np.all(np.isneginf(mx[~full]))
+        assert np.all(s[~full] == 0) and np.all(np.isnan(av[~full]))
+        # the attribute total over inside particles is preserved
+        keep = (x >= 0) & (x <= 1) & (y >= 0) & (y <= 1)
+        assert math.isclose(s.sum(), math.fsum([a, m][j][keep]), rel_tol=1e-11)
+
+
+def pin_metamorphic(orc):
+    rng = np.random.default_rng(17)
+    n = 30000
+    x = rng.uniform(-0.05, 1.05, n)
+    y = rng.uniform(-0.05, 1.05, n)
+    a = rng.standard_normal(n)
+    b = rng.lognormal(0, 1, n)
+    nx, ny = 24, 10
+    bnd = (0.0, 1.0, 0.0, 1.0)
+    base = orc.bin_particles([x, y], [a, b], (0, 1), bnd, nx, ny, ALL)
+    # permutation invariance: count/min/max bit-identical, sums to rounding
+    p = rng.permutation(n)
+    r = orc.bin_particles([x[p], y[p]], [a[p], b[p]], (0, 1), bnd, nx, ny, ALL)
+    assert np.array_equal(r["count"], base["count"])
+    for j in range(2):
+        assert same_bits(r["min"][j], base["min"][j]) and same_bits(r["max"][j], base["max"][j])
+        assert np.all(np.abs(r["sum"][j] - base["sum"][j]) <= 1e-12 * base["abs_sum"][j])
+    # attribute order: results follow the attribute list
+    r = orc.bin_particles([x, y], [b, a], (0, 1), bnd, nx, ny, ALL)
+    assert same_bits(r["max"][0], base["max"][1]) and same_bits(r["min"][1], base["min"][0])
+    # merge law over a split
+    cut = n // 3
+    p1 = orc.bin_particles([x[:cut], y[:cut]], [a[:cut], b[:cut]], (0, 1), bnd, nx, ny, ALL)
+    p2 = orc.bin_particles([x[cut:], y[cut:]], [a[cut:], b[cut:]], (0, 1), bnd, nx, ny, ALL)
+    mg = orc.merge([p1, p2])
+    assert np.array_equal(mg["count"], base["count"])
+    for j in range(2):
+        assert same_bits(mg["min"][j], base["min"][j]) and same_bits(mg["max"][j], base["max"][j])
+        assert np.all(np.abs(mg["sum"][j] - base["sum"][j]) <= 1e-12 * base["abs_sum"][j])
+    # swapping the axes (and the bounds and sides with them) transposes the mesh
+    r = orc.bin_particles([x, y], [a, b], (1, 0), bnd, ny, nx, ALL)
+    assert np.array_equal(r["count"], base["count"].T)
+    for j in range(2):
+        assert same_bits(r["min"][j], base["min"][j].T) and same_bits(r["max"][j], base["max"][j].T)
+    # a 1x1 mesh is the global reduction over the inside particles
+    r = orc.bin_particles([x, y], [a, b], (0, 1), bnd, 1, 1, ALL)
+    keep = (x >= 0) & (x <= 1) & (y >= 0) & (y <= 1)
+    assert r["count"][0, 0] == keep.sum()
+    for j, v in enumerate([a, b]):
+        assert r["min"][j][0, 0] == v[keep].min() and r["max"][j][0, 0] == v[keep].max()
+        assert math.isclose(r["sum"][j][0, 0], math.fsum(v[keep]), rel_tol=1e-12)
+
+
+def pin_lattice(orc):
+    """One particle at every bin centre, value = its flat index: count 1 and
+    sum = min = max = avg = that value everywhere."""
+    nx, ny = 13, 7
+    lo_x, hi_x, lo_y, hi_y = -1.0, 2.0, 0.5, 4.0
+    ix, iy = np.meshgrid(np.arange(nx), np.arange(ny))
+    x = lo_x + (ix.ravel() + 0.5) * (hi_x - lo_x) / nx
+    y = lo_y + (iy.ravel() + 0.5) * (hi_y - lo_y) / ny
+    v = (iy * nx + ix).ravel().astype(np.float64) - 40.0
+    r = orc.bin_particles([x, y], [v], (0, 1), (lo_x, hi_x, lo_y, hi_y), nx, ny, ALL)
+    assert np.array_equal(r["count"], np.ones((ny, nx), np.int64))
+    want = v.reshape(ny, nx)
+    for key in ("sum", "min", "max", "avg"):
+        assert np.array_equal(r[key][0], want), key
+
+
+def pin_signed_zero_order(orc):
+    """min/max follow totalOrder: -0 < +0, regardless of arrival order."""
+    x = np.array([0.1, 0.2, 0.3, 0.4])
+    y = np.array([0.1, 0.1, 0.1, 0.1])
+    for vals in ([0.0, -0.0, 0.0, -0.0], [-0.0, 0.0, -0.0, 0.0], [0.0, 0.0, 0.0, -0.0]):
+        r = orc.bin_particles([x, y], [np.array(vals)], (0, 1), (0.0, 1.0, 0.0, 1.0), 1, 1, ALL)
+        assert np.signbit(r["min"][0][0, 0]) and not np.signbit(r["max"][0][0, 0])
+    r = orc.bin_particles([x, y], [np.array([0.0, 0.0, 0.0, 0.0])], (0, 1), (0.0, 1.0, 0.0, 1.0), 1, 1, ALL)
+    assert not np.signbit(r["min"][0][0, 0])
+
+
+def pin_f32_columns(orc):
+    """f32 coordinates and attributes are widened exactly: the result equals
+    the one from the same values given as f64."""
+    rng = np.random.default_rng(3)
+    n = 5000
+    x = rng.random(n, dtype=np.float32)
+    y = rng.random(n, dtype=np.float32)
+    a = rng.standard_normal(n, dtype=np.float32)
+    r32 = orc.bin_particles([x, y], [a], (0, 1), (0.0, 1.0, 0.0, 1.0), 16, 16, ALL)
+    r64 = orc.bin_particles([x.astype(np.float64), y.astype(np.float64)], [a.astype(np.float64)],
+                            (0, 1), (0.0, 1.0, 0.0, 1.0), 16, 16, ALL)
+    assert np.array_equal(r32["count"], r64["count"])
+    assert same_bits(r32["min"][0], r64["min"][0]) and same_bits(r32["sum"][0], r64["sum"][0])
+
+
+ALL_PINS = [pin_golden, pin_bruteforce_random, pin_bruteforce_edges, pin_general_bounds_near_edges,
+            pin_scipy, pin_invariants, pin_metamorphic, pin_lattice, pin_signed_zero_order,
+            pin_f32_columns]
