@@ -1,0 +1,239 @@
+"""Benchmark: particle binning throughput on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload hotspot|gmm|uniform]
+
+One step = one bin_particles call over the whole particle set (init, bin,
+finalize), inputs resident in HBM.  Prints one JSON line with throughput
+(Gparticles/s), the roofline position of the dominant (binning) kernel
+measured with HIP events recorded by the library around that kernel, and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Gparticles/s binned + % HBM roofline; p50/p99 request latency (served)"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2310_02926_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def make_workload(name: str, scale: int):
+    from paper_2310_02926_amd import synth
+    if name == "hotspot":
+        n = (1 << 27) >> scale
+        return synth.hotspot_f32(n=n, seed=0, side=2048), {
+            "workload": "hotspot_128M_2048sq", "n": n, "grid": "2048x2048", "attrs": "1 x f32 (mass ~ lognormal(0,2))",
+            "coords": "2 x f32", "hot": "90% of particles in 1% of bins", "ops": "count,sum,min,max,avg"}
+    if name == "gmm":
+        n = (1 << 24) >> scale
+        return synth.gmm_f32(n=n, seed=0, nx=1024, ny=1024, k=4), {
+            "workload": "gmm_16M_1024sq_k4", "n": n, "grid": "1024x1024", "attrs": "4 x f32", "coords": "2 x f32",
+            "ops": "count,sum,min,max,avg"}
+    if name == "uniform":
+        n = 65536 >> scale
+        return synth.uniform_f64(n, seed=0), {"workload": "uniform_64K_64sq_f64", "n": n, "grid": "64x64",
+                                               "attrs": "1 x f64", "coords": "2 x f64", "ops": "count,sum,min,max,avg"}
+    raise SystemExit(f"unknown workload {name}")
+
+
+def algorithmic_bytes(ws):
+    ins = sum(c.itemsize * c.size for c in ws.coords[:2]) + sum(a.itemsize * a.size for a in ws.attrs)
+    nb = ws.nx * ws.ny
+    a64 = bool(ws.attrs) and ws.attrs[0].dtype == np.float64
+    per_attr = (8 + 8 + 8 + 8) if a64 else (8 + 4 + 4 + 8)  # sum, min, max, avg (default precision)
+    outs = nb * (4 + per_attr * len(ws.attrs))
+    return ins, outs
+
+
+def cpu_baseline(ws, target_s: float = 12.0):
+    """The oracle as it stands, on a prefix sample of the same particles:
+    grow the sample until one run takes about target_s seconds (or the whole
+    workload is used)."""
+    from oracle import binning_oracle as orc
+    n = ws.n
+    m = min(n, 1 << 20)
+    while True:
+        t0 = time.perf_counter()
+        orc.bin_particles([c[:m] for c in ws.coords], [a[:m] for a in ws.attrs], ws.axes, ws.bounds, ws.nx, ws.ny)
+        dt = time.perf_counter() - t0
+        if dt >= 0.5 * target_s or m >= n:
+            break
+        m = int(min(n, m * max(2.0, min(16.0, target_s / max(dt, 1e-3)))))
+    return {"value": round(m / dt / 1e9, 6), "unit": "Gparticles/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {m} of {n} particles of the same workload (same grid, ops), one NumPy thread, "
+                      f"{dt:.1f} s"}
+
+
+def kernel_algorithmic_bytes(name: str, ws) -> int:
+    """Bytes per launch that the binning definition itself requires of this
+    kernel: the particle columns it must read, or the result grid it must
+    write.  Intermediate records, counts and partials are not counted."""
+    ins, outs = algorithmic_bytes(ws)
+    coords = sum(c.itemsize * c.size for c in ws.coords[:2])
+    if name == "part_count_kernel":
+        return coords
+    if name in ("part_scatter_kernel", "bin_global_kernel", "bin_lds_kernel"):
+        return ins
+    if name in ("part_bin_kernel", "part_merge_kernel", "lds_merge_kernel", "bin_finalize_kernel"):
+        return outs
+    return 0
+
+
+def load_traffic(kernel_hash: str, workload: str):
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(workload)
+    except Exception:
+        return None
+    if not rec or rec.get("kernel_hash") != kernel_hash:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="hotspot", choices=["hotspot", "gmm", "uniform"])
+    ap.add_argument("--prec", default="default", choices=["default", "comp", "plain", "f64"])
+    ap.add_argument("--scale", type=int, default=0, help="shrink n by 2^scale (quick runs)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain device copy of known size (for HBM counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2310_02926_amd import binding as B
+
+    t0 = time.time()
+    ws, cfg = make_workload(args.workload, args.scale)
+    log(f"generated {cfg['workload']} n={ws.n} in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    coords = [torch.from_numpy(c).to(dev) for c in ws.coords]
+    attrs = [torch.from_numpy(a).to(dev) for a in ws.attrs]
+    flag = {"default": 0, "comp": B.PREC_COMP, "plain": B.PREC_PLAIN, "f64": B.PREC_F64}[args.prec]
+    ops = B.OPS_ALL | flag
+    out = B.alloc_outputs(attrs, ws.nx, ws.ny, ops, dev)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB device-to-device copy done")
+        del src, dst
+
+    req, keep = B.request(coords, attrs, ws.n, ws.axes, ws.bounds, ws.nx, ws.ny, ops, out)
+    plan = B.bin_describe_plan(req)
+    log(f"plan: {plan}")
+    for _ in range(args.warmup):
+        B.bin_particles(coords, attrs, ws.n, ws.axes, ws.bounds, ws.nx, ws.ny, ops, out, stream=stream)
+    stream.synchronize()
+    log(f"warmup {args.warmup} done")
+
+    # Timed region 1: whole calls, bracketed by events on the launch stream.
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        B.bin_particles(coords, attrs, ws.n, ws.axes, ws.bounds, ws.nx, ws.ny, ops, out, stream=stream)
+    ev1.record(stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    ms_step = total_ms / args.steps
+    # Timed region 2: the same calls with the library's per-kernel event pairs.
+    B.bin_timing_enable(True)
+    for _ in range(args.steps):
+        B.bin_particles(coords, attrs, ws.n, ws.axes, ws.bounds, ws.nx, ws.ny, ops, out, stream=stream)
+    stream.synchronize()
+    B.bin_timing_enable(False)
+    rep = B.bin_timing_report()
+    dominant = max(rep, key=lambda k: rep[k][1])
+    launches, kern_ms = rep[dominant]
+    log(f"timed {args.steps} steps: {ms_step:.4f} ms/step; kernels (avg ms): "
+        + ", ".join(f"{k}={v[1] / max(v[0], 1):.4f}" for k, v in sorted(rep.items(), key=lambda kv: -kv[1][1])))
+
+    ins, outs = algorithmic_bytes(ws)
+    kern_avg_s = kern_ms / max(launches, 1) / 1e3
+    kbytes = kernel_algorithmic_bytes(dominant, ws)
+    achieved = kbytes / kern_avg_s / 1e9
+    khash = kernel_source_hash()
+    value = ws.n / (ms_step / 1e3) / 1e9
+    rec = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gparticles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.workload == "uniform" else "f32",
+        "data": "synthetic",
+        "config": dict(cfg, precision={"default": "f32 inputs, fp64 per-bin accumulation in LDS, fp64 sum/avg out",
+                                       "comp": "fp32 compensated (TwoSum) sums, fp64 merge",
+                                       "plain": "fp32 sums", "f64": "fp64 sums"}[args.prec], plan=plan),
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": load_traffic(khash, cfg["workload"]),
+            "kernel": dominant,
+            "algorithmic_bytes_per_launch": kbytes,
+            "kernel_ms_avg": round(kern_avg_s * 1e3, 5),
+        },
+        "kernels_ms_avg": {k: round(v[1] / max(v[0], 1), 5) for k, v in rep.items()},
+        "whole_call": {
+            "algorithmic_bytes": ins + outs,
+            "achieved_GBs": round((ins + outs) / (ms_step / 1e3) / 1e9, 1),
+            "frac_of_hbm_peak": round((ins + outs) / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        },
+        "kernel_source_hash": khash,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample")
+        rec["cpu_baseline"] = cpu_baseline(ws)
+    else:
+        rec["cpu_baseline"] = None
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,289 @@
+/*
+ * binning.h - C ABI of libbinning.so: in situ particle data binning on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operation (paper, Section 4.2): particle data is a table whose columns
+ * are variables and whose rows are particles.  Two of the variables are the
+ * axes of a uniform 2D Cartesian mesh with given bounds; the two coordinate
+ * values of a particle select the mesh cell ("bin") it falls in.  Per bin the
+ * library counts particles (a histogram) and reduces each other requested
+ * variable by sum, minimum, maximum and average.
+ *
+ * Readings of points the paper leaves open (shared by every entry point):
+ *  - Inside test: a particle is binned iff lo <= x <= hi on both axes (the
+ *    upper edge is closed and belongs to the last bin).  NaN/Inf coordinates
+ *    are never inside.  Particles outside take part in no reduction.
+ *  - Bin index, in IEEE binary64 with no fused multiply-add:
+ *      s = (double)nbins / (hi - lo);  i = trunc(((double)x - lo) * s);
+ *      if (i > nbins - 1) i = nbins - 1;
+ *    flat bin b = iy * nx + ix; every output grid is row-major [ny][nx].
+ *  - min/max follow IEEE totalOrder on non-NaN values (-0 < +0).  NaN
+ *    attribute values are outside the contract.
+ *  - Empty bins: count 0, sum 0, min +Inf, max -Inf, avg NaN.
+ *  - avg = sum / count formed in binary64 from the merged sum.
+ *
+ * Data placement (paper, Section 2, zero-copy transfer): the caller hands over
+ * raw device pointers together with a stream; the library reads and writes
+ * them in place and never copies or frees them.  With raw pointers the caller
+ * manages their lifetime: inputs and outputs must stay valid and unmodified
+ * until the work enqueued on the stream has completed.
+ *
+ * Stream semantics (paper, Section 2, asynchronous stream mode): every
+ * compute entry point only enqueues work on the given stream and returns; the
+ * results are valid once the stream has been synchronised.  No entry point
+ * synchronises the stream unless its comment says so.  A stream argument is a
+ * hipStream_t passed as void*; NULL means the default stream.
+ *
+ * Errors: every entry point returns BIN_OK (0) or a negative bin_status.  All
+ * argument checks run before the first HIP call, so they hold without a GPU.
+ * bin_last_error_message() gives a thread-local explanation of the last
+ * failure.  A fault of already-enqueued device work surfaces as
+ * BIN_ERR_DEVICE from a later call, or from bin_stream_status().
+ *
+ * Thread safety: calls on different streams may run concurrently.  Calls on
+ * the same stream from several threads are serialised by the stream.
+ */
+#ifndef BINNING_H
+#define BINNING_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+typedef enum bin_status {
+  BIN_OK = 0,
+  BIN_ERR_INVALID_ARG = -1, /* an argument breaks the contract below        */
+  BIN_ERR_UNSUPPORTED = -2, /* valid request this build does not implement  */
+  BIN_ERR_OOM = -3,         /* device scratch allocation failed             */
+  BIN_ERR_DEVICE = -4,      /* a HIP call or enqueued kernel failed         */
+  BIN_ERR_ADMISSION = -5,   /* server: request can never fit the budget     */
+  BIN_ERR_TIMEOUT = -6,     /* server: wait timed out                       */
+  BIN_ERR_NOT_FOUND = -7    /* server: unknown or already released ticket   */
+} bin_status;
+
+/* ---- element types ----------------------------------------------------- */
+typedef enum bin_dtype { BIN_F32 = 0, BIN_F64 = 1 } bin_dtype;
+
+/* ---- op bits and precision flags (the 'ops' argument) ------------------- */
+#define BIN_COUNT 1u  /* per-bin particle count (the histogram)             */
+#define BIN_SUM 2u    /* per-bin sum of each attribute                       */
+#define BIN_MIN 4u    /* per-bin minimum of each attribute                   */
+#define BIN_MAX 8u    /* per-bin maximum of each attribute                   */
+#define BIN_AVG 16u   /* per-bin average of each attribute                   */
+#define BIN_OPS_ALL 31u
+/* Precision of sums of f32 attributes (f64 attributes always accumulate in
+ * binary64).  At most one flag:
+ *  BIN_PREC_COMP   FP32 accumulation with compensation: per bin an FP32 sum
+ *                  word S and an FP32 error word C, updated by the error-free
+ *                  TwoSum transformation; S + C merged and finalised in
+ *                  binary64.  sum/avg outputs are double.
+ *  BIN_PREC_PLAIN  uncompensated FP32 sums; sum/avg outputs are float.
+ *  BIN_PREC_F64    binary64 accumulation; sum/avg outputs are double.
+ *  (none)          default: at least the accuracy of BIN_PREC_COMP with
+ *                  double outputs; on gfx950 this is binary64 accumulation,
+ *                  which is also the fastest of the three there. */
+#define BIN_PREC_PLAIN 0x100u
+#define BIN_PREC_F64 0x200u
+#define BIN_PREC_COMP 0x400u
+
+#define BIN_MAX_COLUMNS 64   /* max coordinate columns in one table         */
+#define BIN_MAX_ATTRS 16     /* max attributes reduced by one request       */
+
+/* A table of n-row device columns (structure of arrays).  cols[i] is a
+ * device pointer to n elements of 'dtype', aligned to the element size. */
+typedef struct bin_columns {
+  const void* const* cols; /* host array of ncols device pointers           */
+  int32_t ncols;
+  int32_t dtype; /* bin_dtype */
+} bin_columns;
+
+/* Caller-allocated device output grids, each of nx*ny elements, row-major
+ * [ny][nx].  They are overwritten, not accumulated into.
+ *   count: uint32_t*, required iff BIN_COUNT is requested.
+ *   sum/min/max/avg: host arrays of k device pointers (k = attrs->ncols),
+ *   required iff the op is requested, NULL otherwise.
+ *   Element types: min/max = attribute dtype; sum/avg = double, except float
+ *   for f32 attributes under BIN_PREC_PLAIN.
+ * No output may alias an input or another output. */
+typedef struct bin_output {
+  uint32_t* count;
+  void* const* sum;
+  void* const* min;
+  void* const* max;
+  void* const* avg;
+} bin_output;
+
+/* One binning request (the arguments of bin_particles as a record); used by
+ * the batched, graph and server entry points. */
+typedef struct bin_request {
+  bin_columns coords;
+  bin_columns attrs;
+  int64_t n;
+  int32_t axes[2];
+  double bounds[4];
+  int32_t nx, ny;
+  uint32_t ops;
+  bin_output out;
+} bin_request;
+
+/* ---- plain entry point -------------------------------------------------- */
+/* Bin n particles (paper, Section 4.2) and reduce the attributes per bin.
+ *  coords  table of candidate coordinate columns (e.g. x, y, z); axes[0] and
+ *          axes[1] pick the columns used as the mesh x and y axes, so the x-y
+ *          and x-z planes of one table are two calls on the same columns.
+ *  attrs   columns to reduce (k = attrs->ncols, 0..BIN_MAX_ATTRS; attrs may
+ *          be NULL for k = 0).  Both tables are f32 or f64; they may differ.
+ *  n       rows, 0 <= n <= UINT32_MAX; n == 0 writes empty-bin values.
+ *  bounds  {xlo, xhi, ylo, yhi}, finite, lo < hi, (hi - lo) and
+ *          nbins / (hi - lo) finite.  NULL asks for bounds computed on the
+ *          fly from the minimum and maximum of each axis column (Section
+ *          4.2): the library derives them on the device before binning.
+ *  nx, ny  mesh cells per axis, >= 1, nx * ny <= 2^31 - 1.
+ *  ops     nonzero OR of BIN_COUNT..BIN_AVG, optionally one BIN_PREC_* flag;
+ *          SUM/MIN/MAX/AVG need k >= 1.
+ *  out     output grids (see bin_output).
+ *  stream  hipStream_t (as void*), NULL = default stream.
+ * Library scratch (when needed) comes from a pool owned by the library per
+ * (device, stream) and is reused across calls; bin_release_workspace frees
+ * it.  Returns BIN_OK once the work is enqueued. */
+int bin_particles(const bin_columns* coords, const bin_columns* attrs, int64_t n,
+                  const int32_t axes[2], const double bounds[4], int32_t nx, int32_t ny,
+                  uint32_t ops, const bin_output* out, void* stream);
+
+/* Validate the arguments of bin_particles without touching the GPU.
+ * Returns BIN_OK or the status bin_particles would return before any HIP
+ * call. */
+int bin_validate(const bin_columns* coords, const bin_columns* attrs, int64_t n,
+                 const int32_t axes[2], const double bounds[4], int32_t nx, int32_t ny,
+                 uint32_t ops, const bin_output* out);
+
+/* ---- batched entry point ------------------------------------------------ */
+/* Run nreq independent requests (uneven n and grid sizes allowed) in one
+ * persistent kernel launch on 'stream' (plus one initialisation and one
+ * finalisation launch for the whole batch).  Each result equals what
+ * bin_particles gives for the same request, within the sum tolerance; counts,
+ * min and max are identical.  Requests must not share output buffers.  The
+ * request array is read during the call only.  Enqueues and returns. */
+int bin_particles_batched(const bin_request* reqs, int32_t nreq, void* stream);
+
+/* ---- graphs ---------------------------------------------------------------- */
+/* Capture the batched launch of nreq requests as a HIP graph.  The graph
+ * owns its descriptor and scratch memory; the caller's buffers are borrowed
+ * each time the graph is launched.  Replays re-read the input columns and
+ * overwrite the outputs, so the caller may refill the inputs between
+ * launches.  Creating a graph synchronises the device once. */
+typedef struct bin_graph bin_graph;
+int bin_graph_create(const bin_request* reqs, int32_t nreq, bin_graph** graph);
+int bin_graph_launch(bin_graph* graph, void* stream);
+int bin_graph_destroy(bin_graph* graph);
+
+/* ---- autotuning ------------------------------------------------------------ */
+/* Time the candidate kernel configurations for requests shaped like
+ * reqs[0..count) and remember the fastest per shape class (in memory, and in
+ * the JSON file named by the environment variable BIN_TUNE_CACHE if set).
+ * Runs kernels on a private stream and synchronises it; it overwrites the
+ * requests' output buffers.  Without tuning data the built-in rules apply. */
+int bin_autotune(const bin_request* reqs, int32_t count);
+
+/* ---- diagnostics -------------------------------------------------------- */
+const char* bin_status_string(int status);
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char* bin_last_error_message(void);
+/* Non-blocking: BIN_ERR_DEVICE if work on 'stream' has faulted, else BIN_OK. */
+int bin_stream_status(void* stream);
+/* Free every scratch pool of the library (all devices and streams).
+ * Synchronises the device first, so no enqueued work can still use them. */
+int bin_release_workspace(void);
+/* Library version as "major.minor.patch". */
+const char* bin_version(void);
+
+/* Kernel timing, for measurement only: while enabled, every kernel launch of
+ * the library is bracketed by a HIP event pair on its stream.  Enabling
+ * clears earlier totals.  bin_timing_read waits for the recorded events and
+ * returns the launches and summed milliseconds of the kernel with the
+ * largest total (the dominant kernel); bin_timing_report writes all kernels
+ * as JSON {"name": [launches, total_ms], ...} into buf. */
+int bin_timing_enable(int on);
+int bin_timing_read(int64_t* launches, double* total_ms);
+int bin_timing_report(char* buf, size_t buflen);
+
+/* Override the planner for later calls made by this thread (tests and the
+ * autotuner): strategy -1 = automatic, 0 = global atomics, 1 = whole grid
+ * in LDS, 2 = partition by tile (1 and 2 are ignored when they do not fit);
+ * block/grid 0 = automatic (grid = workgroups of the binning or partition
+ * pass). */
+int bin_set_plan_override(int32_t strategy, int32_t block, int32_t grid);
+
+/* Describe the strategy the planner picks for a request (no GPU work):
+ * writes a short NUL-terminated text such as "lds wg=256 ppt=8" into buf. */
+int bin_describe_plan(const bin_request* req, char* buf, size_t buflen);
+
+/* ---- serving --------------------------------------------------------------- */
+/* A request server with continuous batching: binsrv_submit may be called
+ * from any thread while earlier requests run; a dispatcher thread admits
+ * waiting requests as soon as a stream slot and enough device memory (the
+ * budget) are free, runs each admitted group as one batched launch, and keeps
+ * each result grid resident on the device until binsrv_release. */
+typedef struct binsrv binsrv;
+typedef struct binsrv_config {
+  uint64_t budget_bytes;   /* device memory for result grids and scratch    */
+  int32_t n_slots;         /* concurrent batches in flight (streams), >= 1  */
+  int32_t max_batch;       /* max requests per batched launch, >= 1         */
+  int32_t device;          /* HIP device ordinal                            */
+  int32_t reserved;
+} binsrv_config;
+
+/* A server request: like bin_request but without outputs; the server
+ * allocates the result grids (all five op kinds as requested, with the
+ * default precision rules) from its budget. */
+typedef struct binsrv_request {
+  bin_columns coords;
+  bin_columns attrs;
+  int64_t n;
+  int32_t axes[2];
+  double bounds[4];
+  int32_t nx, ny;
+  uint32_t ops;
+} binsrv_request;
+
+/* Where a finished request's resident grids are (device pointers owned by
+ * the server until binsrv_release), plus its timing. */
+typedef struct bin_result {
+  int32_t status;          /* BIN_OK or the request's error                 */
+  int32_t k;
+  uint32_t* count;
+  void* sum[BIN_MAX_ATTRS];
+  void* min[BIN_MAX_ATTRS];
+  void* max[BIN_MAX_ATTRS];
+  void* avg[BIN_MAX_ATTRS];
+  double submit_to_done_ms; /* arrival (submit) to completion observed      */
+  double queue_ms;          /* arrival to dispatch                          */
+} bin_result;
+
+typedef struct binsrv_stats {
+  uint64_t submitted, completed, failed, released;
+  uint64_t batches, in_flight, queued;
+  uint64_t bytes_in_use, peak_bytes;
+} binsrv_stats;
+
+int binsrv_create(const binsrv_config* cfg, binsrv** srv);
+/* Queue a request.  Inputs are borrowed until the request completes.
+ * Returns BIN_ERR_ADMISSION if it can never fit the budget. */
+int binsrv_submit(binsrv* srv, const binsrv_request* req, uint64_t* ticket);
+/* Wait up to timeout_ns (negative = forever) for a ticket's completion;
+ * fills *result.  BIN_ERR_TIMEOUT if it is not done in time. */
+int binsrv_wait(binsrv* srv, uint64_t ticket, int64_t timeout_ns, bin_result* result);
+/* Return a finished request's grids to the server's pool. */
+int binsrv_release(binsrv* srv, uint64_t ticket);
+int binsrv_get_stats(binsrv* srv, binsrv_stats* stats);
+/* Drain in-flight work, free every grid and stop the dispatcher. */
+int binsrv_destroy(binsrv* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BINNING_H */

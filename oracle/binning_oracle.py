@@ -29,6 +29,11 @@ the HIP path) are:
   ``iy * nx + ix``.
 * R8 sums are reference values in binary64; besides them the oracle reports
   ``abs_sum`` = per-bin sum of |a|, the scale used by sum tolerances.
+* R9 bounds taken from the data (``bounds=None``): per axis the minimum and
+  maximum over the finite coordinate values; with the closed upper edge the
+  extreme particles land in the first and last cell.  A zero-extent axis
+  (all finite values equal) puts them all in its first cell; an axis with
+  no finite value leaves every bin empty.
 
 Parity pins: brute force (exact rational index, exactly rounded sums) on
 small inputs; SciPy ``binned_statistic_2d`` and NumPy ``histogram2d``;
@@ -59,12 +64,26 @@ def axis_index(v, lo: float, hi: float, nbins: int):
     hi = np.float64(hi)
     with np.errstate(invalid="ignore"):
         inside = (v >= lo) & (v <= hi)
-    scale = np.float64(nbins) / (hi - lo)
+    # R9: an axis of zero extent (possible only with bounds taken from the
+    # data) puts every inside particle into its first cell.
+    scale = np.float64(nbins) / (hi - lo) if hi > lo else np.float64(0.0)
     idx = np.zeros(v.shape, dtype=np.int64)
     t = (v[inside] - lo) * scale
     idx[inside] = np.trunc(t).astype(np.int64)
     np.minimum(idx, nbins - 1, out=idx)
     return inside, idx
+
+
+def auto_bounds(coords: Sequence[np.ndarray], axes) -> tuple:
+    """Mesh bounds taken from the data (Section 4.2: the minimum and maximum
+    of each coordinate variable), over finite values only (reading R9).  An
+    axis column without a finite value gives (+Inf, -Inf): nothing is inside."""
+    out = []
+    for ax in axes:
+        v = np.asarray(coords[ax]).astype(np.float64)
+        f = v[np.isfinite(v)]
+        out += [float(f.min()), float(f.max())] if f.size else [np.inf, -np.inf]
+    return tuple(out)
 
 
 def flat_bins(coords: Sequence[np.ndarray], axes, bounds, nx: int, ny: int):
@@ -97,6 +116,8 @@ def bin_particles(coords: Sequence[np.ndarray], attrs: Sequence[np.ndarray], axe
     Also ``inside`` = the number of particles inside the mesh.
     """
     nb = nx * ny
+    if bounds is None:
+        bounds = auto_bounds(coords, axes)
     inside, b = flat_bins(coords, axes, bounds, nx, ny)
     count = np.bincount(b, minlength=nb).astype(np.int64)
     res = {"count": count.reshape(ny, nx), "sum": [], "min": [], "max": [], "avg": [],
@@ -154,6 +175,8 @@ def _exact_index(v: float, lo: float, hi: float, nbins: int) -> Optional[int]:
     the last bin for ``v == hi``, None outside (R1, R3)."""
     if not (lo <= v <= hi):          # NaN compares false
         return None
+    if lo == hi:                     # zero-extent axis (R9)
+        return 0
     i = math.floor((Fraction(v) - Fraction(lo)) * nbins / (Fraction(hi) - Fraction(lo)))
     return min(i, nbins - 1)
 
@@ -168,6 +191,12 @@ def bin_particles_bruteforce(coords, attrs, axes=(0, 1), bounds=(0.0, 1.0, 0.0, 
     """Per-particle loop with the exact rational bin index and exactly rounded
     (``math.fsum``) per-bin sums.  Same result layout as ``bin_particles``."""
     n = len(coords[0])
+    if bounds is None:               # R9, by plain Python min/max
+        bl = []
+        for ax in axes:
+            vals = [float(v) for v in coords[ax] if math.isfinite(float(v))]
+            bl += [min(vals), max(vals)] if vals else [math.inf, -math.inf]
+        bounds = tuple(bl)
     members: List[List[int]] = [[] for _ in range(nx * ny)]
     for i in range(n):
         ix = _exact_index(float(coords[axes[0]][i]), bounds[0], bounds[1], nx)

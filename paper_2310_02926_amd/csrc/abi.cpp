@@ -1,0 +1,187 @@
+// extern "C" entry points of libbinning.so (declared in include/binning.h).
+#include <cstring>
+
+#include "internal.h"
+
+using namespace binimpl;
+
+namespace {
+
+bin_request make_request(const bin_columns* coords, const bin_columns* attrs, int64_t n,
+                         const int32_t axes[2], const double bounds[4], int32_t nx, int32_t ny,
+                         uint32_t ops, const bin_output* out) {
+  bin_request r;
+  std::memset(&r, 0, sizeof r);
+  r.coords = *coords;
+  if (attrs) r.attrs = *attrs;
+  r.n = n;
+  r.axes[0] = axes[0];
+  r.axes[1] = axes[1];
+  if (bounds) std::memcpy(r.bounds, bounds, sizeof r.bounds);
+  r.nx = nx;
+  r.ny = ny;
+  r.ops = ops;
+  r.out = *out;
+  return r;
+}
+
+// A stream that already holds a fault makes every later call on it fail.
+int precheck_stream(hipStream_t s) {
+  hipError_t e = hipStreamQuery(s);
+  if (e == hipSuccess || e == hipErrorNotReady) return BIN_OK;
+  return hip_fail(e, "stream holds an earlier device error");
+}
+
+}  // namespace
+
+namespace binimpl {
+static thread_local PlanHints t_hints;
+const PlanHints& thread_hints() { return t_hints; }
+
+// Single request on a stream (also used by the autotuner).
+int run_request(const bin_request& r, hipStream_t s, const PlanHints& hints) {
+  DeviceInfo dev;
+  int st = device_info(&dev);
+  if (st) return st;
+  st = precheck_stream(s);
+  if (st) return st;
+  Prepared p;
+  st = prepare(r, dev, hints, nullptr, &p);  // sizing pass
+  if (st) return st;
+  void* scratch = nullptr;
+  if (p.scratch_bytes) {
+    st = scratch_get(dev.device, s, p.scratch_bytes, &scratch);
+    if (st) return st;
+    st = prepare(r, dev, hints, scratch, &p);
+    if (st) return st;
+  }
+  return enqueue(p, s, timing_timer());
+}
+
+// Bounds from the data (bounds == NULL): a min/max pass over the two axis
+// columns writes four keys at the start of the scratch block; the binning
+// kernels read them instead of host bounds.  The plan itself does not
+// depend on the bounds, so it is made with a placeholder.
+int run_auto_bounds(const bin_request& r0, hipStream_t s) {
+  bin_request r = r0;
+  r.bounds[0] = 0.0;
+  r.bounds[1] = 1.0;
+  r.bounds[2] = 0.0;
+  r.bounds[3] = 1.0;
+  DeviceInfo dev;
+  int st = device_info(&dev);
+  if (st) return st;
+  st = precheck_stream(s);
+  if (st) return st;
+  const PlanHints& hints = thread_hints();
+  Prepared p;
+  st = prepare(r, dev, hints, nullptr, &p);
+  if (st) return st;
+  void* scratch = nullptr;
+  st = scratch_get(dev.device, s, p.scratch_bytes + 256, &scratch);
+  if (st) return st;
+  st = prepare(r, dev, hints, static_cast<unsigned char*>(scratch) + 256, &p);
+  if (st) return st;
+  long long* keys = static_cast<long long*>(scratch);
+  p.bin.dyn = keys;
+  p.lds.dyn = keys;
+  p.part.dyn = keys;
+  bk::KTimer* tm = timing_timer();
+  hipError_t e = bk::launch_bounds(r.coords.cols[r.axes[0]], r.coords.cols[r.axes[1]], p.coord_f64, r.n, keys,
+                                   dev.cus, s, tm);
+  if (e != hipSuccess) return hip_fail(e, "launch bounds kernels");
+  return enqueue(p, s, tm);
+}
+}  // namespace binimpl
+
+extern "C" {
+
+int bin_validate(const bin_columns* coords, const bin_columns* attrs, int64_t n, const int32_t axes[2],
+                 const double bounds[4], int32_t nx, int32_t ny, uint32_t ops, const bin_output* out) {
+  clear_error();
+  return validate(coords, attrs, n, axes, bounds, nx, ny, ops, out, true);
+}
+
+int bin_particles(const bin_columns* coords, const bin_columns* attrs, int64_t n, const int32_t axes[2],
+                  const double bounds[4], int32_t nx, int32_t ny, uint32_t ops, const bin_output* out,
+                  void* stream) {
+  clear_error();
+  int st = validate(coords, attrs, n, axes, bounds, nx, ny, ops, out, true);
+  if (st) return st;
+  bin_request r = make_request(coords, attrs, n, axes, bounds, nx, ny, ops, out);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!bounds) return run_auto_bounds(r, s);
+  return run_request(r, s, thread_hints());
+}
+
+int bin_set_plan_override(int32_t strategy, int32_t block, int32_t grid) {
+  clear_error();
+  if (strategy < -1 || strategy > 2) return fail(BIN_ERR_INVALID_ARG, "strategy must be -1, 0, 1 or 2");
+  if (block != 0 && (block < 64 || block > 1024 || block % 64))
+    return fail(BIN_ERR_INVALID_ARG, "block must be 0 or a multiple of 64 in [64, 1024]");
+  if (grid < 0) return fail(BIN_ERR_INVALID_ARG, "grid must be >= 0");
+  t_hints.force_strategy = strategy;
+  t_hints.block = block;
+  t_hints.grid = grid;
+  return BIN_OK;
+}
+
+const char* bin_status_string(int status) {
+  switch (status) {
+    case BIN_OK: return "BIN_OK";
+    case BIN_ERR_INVALID_ARG: return "BIN_ERR_INVALID_ARG";
+    case BIN_ERR_UNSUPPORTED: return "BIN_ERR_UNSUPPORTED";
+    case BIN_ERR_OOM: return "BIN_ERR_OOM";
+    case BIN_ERR_DEVICE: return "BIN_ERR_DEVICE";
+    case BIN_ERR_ADMISSION: return "BIN_ERR_ADMISSION";
+    case BIN_ERR_TIMEOUT: return "BIN_ERR_TIMEOUT";
+    case BIN_ERR_NOT_FOUND: return "BIN_ERR_NOT_FOUND";
+    default: return "BIN_ERR_UNKNOWN";
+  }
+}
+
+const char* bin_last_error_message(void) { return last_error(); }
+
+int bin_stream_status(void* stream) {
+  clear_error();
+  return precheck_stream(static_cast<hipStream_t>(stream));
+}
+
+int bin_release_workspace(void) {
+  clear_error();
+  return release_all_scratch();
+}
+
+const char* bin_version(void) { return "0.1.0"; }
+
+int bin_timing_enable(int on) { return timing_enable(on); }
+
+int bin_timing_read(int64_t* launches, double* total_ms) {
+  clear_error();
+  return timing_read(launches, total_ms);
+}
+
+int bin_timing_report(char* buf, size_t buflen) {
+  clear_error();
+  return timing_report(buf, buflen);
+}
+
+int bin_describe_plan(const bin_request* req, char* buf, size_t buflen) {
+  clear_error();
+  if (!req || !buf || buflen == 0) return fail(BIN_ERR_INVALID_ARG, "NULL request or buffer");
+  int st = validate(&req->coords, &req->attrs, req->n, req->axes, req->bounds, req->nx, req->ny, req->ops,
+                    &req->out, false);
+  if (st) return st;
+  DeviceInfo dev;
+  st = device_info(&dev);
+  if (st) return st;
+  Prepared p;
+  st = prepare(*req, dev, thread_hints(), nullptr, &p);
+  if (st) return st;
+  std::string d = describe(p);
+  std::strncpy(buf, d.c_str(), buflen - 1);
+  buf[buflen - 1] = 0;
+  return BIN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,253 @@
+// Device helpers shared by the binning kernels: bin location, totalOrder
+// min/max, TwoSum, streaming loads.
+#ifndef BINNING_DEVICE_COMMON_H
+#define BINNING_DEVICE_COMMON_H
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+
+namespace bk {
+
+// Bin location (Section 4.2): inside test with a closed upper edge, then
+// trunc((x - lo) * scale) clamped to n-1, all in binary64.  A zero scale
+// (zero-extent axis) maps every inside value to cell 0.
+__device__ __forceinline__ bool locate(double v, const Axis& a, int& idx) {
+  if (!(v >= a.lo && v <= a.hi)) return false;  // NaN fails both tests
+  const double f = (v - a.lo) * a.scale;
+  const int i = (int)f;  // v_cvt_i32_f64 truncates; f >= 0 here
+  idx = i < a.n ? i : a.n - 1;
+  return true;
+}
+
+__device__ __forceinline__ double fkey_decode(long long k);
+
+// Axes from bounds computed on the device (four totalOrder keys: xmin,
+// xmax, ymin, ymax), or left as passed when keys is null.  A zero-extent
+// axis gets scale 0 (every inside value in cell 0); an axis that saw no
+// finite value has lo = +Inf > hi = -Inf, so nothing is inside.
+__device__ __forceinline__ void resolve_axes(const long long* keys, Axis& ax, Axis& ay) {
+  if (!keys) return;
+  ax.lo = fkey_decode(keys[0]);
+  ax.hi = fkey_decode(keys[1]);
+  ay.lo = fkey_decode(keys[2]);
+  ay.hi = fkey_decode(keys[3]);
+  ax.scale = ax.hi > ax.lo ? (double)ax.n / (ax.hi - ax.lo) : 0.0;
+  ay.scale = ay.hi > ay.lo ? (double)ay.n / (ay.hi - ay.lo) : 0.0;
+}
+
+// totalOrder min/max on float bit patterns held directly in a result array.
+// For a non-negative value (sign bit clear) signed-integer order of the bit
+// patterns equals IEEE totalOrder; for a value with the sign bit set,
+// unsigned order of the bits is the reverse of totalOrder.  One integer
+// atomic per lane, no key decoding pass.
+__device__ __forceinline__ void atomic_min_fp(float* p, float v) {
+  const int b = __float_as_int(v);
+  if (b >= 0)
+    atomicMin(reinterpret_cast<int*>(p), b);
+  else
+    atomicMax(reinterpret_cast<unsigned int*>(p), static_cast<unsigned int>(b));
+}
+__device__ __forceinline__ void atomic_max_fp(float* p, float v) {
+  const int b = __float_as_int(v);
+  if (b >= 0)
+    atomicMax(reinterpret_cast<int*>(p), b);
+  else
+    atomicMin(reinterpret_cast<unsigned int*>(p), static_cast<unsigned int>(b));
+}
+__device__ __forceinline__ void atomic_min_fp(double* p, double v) {
+  const long long b = __double_as_longlong(v);
+  if (b >= 0)
+    atomicMin(reinterpret_cast<long long*>(p), b);
+  else
+    atomicMax(reinterpret_cast<unsigned long long*>(p), static_cast<unsigned long long>(b));
+}
+__device__ __forceinline__ void atomic_max_fp(double* p, double v) {
+  const long long b = __double_as_longlong(v);
+  if (b >= 0)
+    atomicMax(reinterpret_cast<long long*>(p), b);
+  else
+    atomicMin(reinterpret_cast<unsigned long long*>(p), static_cast<unsigned long long>(b));
+}
+
+// Order-preserving integer keys (one LDS atomic per lane whatever the sign).
+// Signed order of the key equals totalOrder of the value.
+__device__ __forceinline__ int fkey(float v) {
+  const int b = __float_as_int(v);
+  return b >= 0 ? b : (b ^ 0x7FFFFFFF);
+}
+__device__ __forceinline__ float fkey_decode(int k) { return __int_as_float(k >= 0 ? k : (k ^ 0x7FFFFFFF)); }
+__device__ __forceinline__ long long fkey(double v) {
+  const long long b = __double_as_longlong(v);
+  return b >= 0 ? b : (b ^ 0x7FFFFFFFFFFFFFFFLL);
+}
+__device__ __forceinline__ double fkey_decode(long long k) {
+  return __longlong_as_double(k >= 0 ? k : (k ^ 0x7FFFFFFFFFFFFFFFLL));
+}
+template <typename AT> struct KeyOf;
+template <> struct KeyOf<float> { using T = int; };
+template <> struct KeyOf<double> { using T = long long; };
+
+// Error-free transformation (Knuth's TwoSum): with s = fl(a + b), returns
+// e such that a + b = s + e exactly (round-to-nearest, no overflow).
+__device__ __forceinline__ float two_sum_err(float a, float b, float s) {
+  const float bb = s - a;
+  return (a - (s - bb)) + (b - bb);
+}
+
+// Streaming column load (read once; keep caches for accumulators).
+template <typename T>
+__device__ __forceinline__ T ld(const void* p, int64_t i) {
+  return __builtin_nontemporal_load(static_cast<const T*>(p) + i);
+}
+
+// ---------------------------------------------------------------------------
+// LDS tile accumulators (layout in TileLayout).  All functions are called by
+// every thread of the workgroup; tb = bins of the tile held in LDS.
+// ---------------------------------------------------------------------------
+template <typename AT, int PREC>
+struct Tile {
+  using K = typename KeyOf<AT>::T;
+  static constexpr int kSumBytes = (PREC == PREC_PLAIN) ? 4 : 8;
+
+  __device__ static void init(unsigned char* smem, const TileLayout& L, int k) {
+    const int tb = L.tb;
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(smem);
+    for (int b = threadIdx.x; b < tb; b += blockDim.x) cnt[b] = 0u;
+    for (int j = 0; j < k; ++j) {
+      if (L.want_sum) {
+        uint32_t* w = reinterpret_cast<uint32_t*>(smem + L.lds_sum_off[j]);
+        const int words = tb * kSumBytes / 4;
+        for (int b = threadIdx.x; b < words; b += blockDim.x) w[b] = 0u;
+      }
+      if (L.want_min) {
+        K* m = reinterpret_cast<K*>(smem + L.lds_min_off[j]);
+        for (int b = threadIdx.x; b < tb; b += blockDim.x) m[b] = fkey((AT)INFINITY);
+      }
+      if (L.want_max) {
+        K* m = reinterpret_cast<K*>(smem + L.lds_max_off[j]);
+        for (int b = threadIdx.x; b < tb; b += blockDim.x) m[b] = fkey((AT)-INFINITY);
+      }
+    }
+  }
+
+  __device__ static void count(unsigned char* smem, int b) { atomicAdd(reinterpret_cast<uint32_t*>(smem) + b, 1u); }
+
+  __device__ static void add(unsigned char* smem, const TileLayout& L, int j, int b, AT v) {
+    if (L.want_sum) {
+      unsigned char* base = smem + L.lds_sum_off[j];
+      if constexpr (PREC == PREC_F64) {
+        atomicAdd(reinterpret_cast<double*>(base) + b, (double)v);
+      } else if constexpr (PREC == PREC_PLAIN) {
+        atomicAdd(reinterpret_cast<float*>(base) + b, (float)v);
+      } else {  // TwoSum: the returning add gives the value the sum held
+        float* S = reinterpret_cast<float*>(base);
+        const float fv = (float)v;
+        const float old = atomicAdd(S + b, fv);
+        const float e = two_sum_err(old, fv, old + fv);
+        if (e != 0.0f) atomicAdd(S + L.tb + b, e);
+      }
+    }
+    if (L.want_min) atomicMin(reinterpret_cast<K*>(smem + L.lds_min_off[j]) + b, fkey(v));
+    if (L.want_max) atomicMax(reinterpret_cast<K*>(smem + L.lds_max_off[j]) + b, fkey(v));
+  }
+
+  __device__ static uint32_t cnt_get(const unsigned char* smem, int b) {
+    return reinterpret_cast<const uint32_t*>(smem)[b];
+  }
+  // binary64 value of the sum (S + C for the compensated words).
+  __device__ static double sum_get(const unsigned char* smem, const TileLayout& L, int j, int b) {
+    const unsigned char* base = smem + L.lds_sum_off[j];
+    if constexpr (PREC == PREC_F64) return reinterpret_cast<const double*>(base)[b];
+    else if constexpr (PREC == PREC_PLAIN) return (double)reinterpret_cast<const float*>(base)[b];
+    else {
+      const float* S = reinterpret_cast<const float*>(base);
+      return (double)S[b] + (double)S[L.tb + b];
+    }
+  }
+  __device__ static K min_get(const unsigned char* smem, const TileLayout& L, int j, int b) {
+    return reinterpret_cast<const K*>(smem + L.lds_min_off[j])[b];
+  }
+  __device__ static K max_get(const unsigned char* smem, const TileLayout& L, int j, int b) {
+    return reinterpret_cast<const K*>(smem + L.lds_max_off[j])[b];
+  }
+
+  // Final values of attribute j in one bin: sum (binary64 or float), min/max
+  // decoded from keys, avg = sum / count (NaN if empty).
+  __device__ static void emit_attr(const Outs& o, int j, int64_t gb, uint32_t c, double s, K kmin, K kmax) {
+    if (o.sum[j]) {
+      if constexpr (PREC == PREC_PLAIN) static_cast<float*>(o.sum[j])[gb] = (float)s;
+      else static_cast<double*>(o.sum[j])[gb] = s;
+    }
+    if (o.mn[j]) static_cast<AT*>(o.mn[j])[gb] = fkey_decode(kmin);
+    if (o.mx[j]) static_cast<AT*>(o.mx[j])[gb] = fkey_decode(kmax);
+    if (o.avg[j]) {
+      const double av = c ? s / (double)c : __builtin_nan("");
+      if constexpr (PREC == PREC_PLAIN) static_cast<float*>(o.avg[j])[gb] = (float)av;
+      else static_cast<double*>(o.avg[j])[gb] = av;
+    }
+  }
+
+  // Write the finished outputs of local bins [0, nbt) -> global b0 + b.
+  __device__ static void emit_all(const unsigned char* smem, const TileLayout& L, const Outs& o, int k, int nbt,
+                                  int64_t b0) {
+    for (int b = threadIdx.x; b < nbt; b += blockDim.x) {
+      const uint32_t c = cnt_get(smem, b);
+      if (o.cnt) o.cnt[b0 + b] = c;
+      for (int j = 0; j < k; ++j)
+        emit_attr(o, j, b0 + b, c, L.want_sum ? sum_get(smem, L, j, b) : 0.0,
+                  L.want_min ? min_get(smem, L, j, b) : K(0), L.want_max ? max_get(smem, L, j, b) : K(0));
+    }
+  }
+
+  // Store this workgroup's accumulators of local bins [0, nbt) as a slot.
+  __device__ static void store_slot(const unsigned char* smem, const TileLayout& L, int k, int nbt,
+                                    unsigned char* slot) {
+    for (int b = threadIdx.x; b < nbt; b += blockDim.x) {
+      reinterpret_cast<uint32_t*>(slot)[b] = cnt_get(smem, b);
+      for (int j = 0; j < k; ++j) {
+        if (L.want_sum) {
+          const double s = sum_get(smem, L, j, b);
+          if constexpr (PREC == PREC_PLAIN) reinterpret_cast<float*>(slot + L.slot_sum_off[j])[b] = (float)s;
+          else reinterpret_cast<double*>(slot + L.slot_sum_off[j])[b] = s;
+        }
+        if (L.want_min) reinterpret_cast<K*>(slot + L.slot_min_off[j])[b] = min_get(smem, L, j, b);
+        if (L.want_max) reinterpret_cast<K*>(slot + L.slot_max_off[j])[b] = max_get(smem, L, j, b);
+      }
+    }
+  }
+
+  // Combine slots first..first+nslot-1 for local bin b and emit it.
+  __device__ static void merge_emit(const unsigned char* slots, int64_t slot_bytes, uint32_t first, uint32_t nslot,
+                                    const TileLayout& L, const Outs& o, int k, int b, int64_t gb) {
+    uint32_t c = 0;
+    for (uint32_t q = 0; q < nslot; ++q)
+      c += reinterpret_cast<const uint32_t*>(slots + (int64_t)(first + q) * slot_bytes)[b];
+    if (o.cnt) o.cnt[gb] = c;
+    for (int j = 0; j < k; ++j) {
+      double s = 0.0;
+      K kmin = fkey((AT)INFINITY), kmax = fkey((AT)-INFINITY);
+      for (uint32_t q = 0; q < nslot; ++q) {
+        const unsigned char* slot = slots + (int64_t)(first + q) * slot_bytes;
+        if (L.want_sum) {
+          if constexpr (PREC == PREC_PLAIN) s += (double)reinterpret_cast<const float*>(slot + L.slot_sum_off[j])[b];
+          else s += reinterpret_cast<const double*>(slot + L.slot_sum_off[j])[b];
+        }
+        if (L.want_min) {
+          const K m = reinterpret_cast<const K*>(slot + L.slot_min_off[j])[b];
+          kmin = m < kmin ? m : kmin;
+        }
+        if (L.want_max) {
+          const K m = reinterpret_cast<const K*>(slot + L.slot_max_off[j])[b];
+          kmax = m > kmax ? m : kmax;
+        }
+      }
+      emit_attr(o, j, gb, c, s, kmin, kmax);
+    }
+  }
+};
+
+}  // namespace bk
+
+#endif

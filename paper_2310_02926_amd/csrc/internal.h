@@ -1,0 +1,87 @@
+// Declarations shared by the host-side translation units of libbinning.so.
+#ifndef BINNING_INTERNAL_H
+#define BINNING_INTERNAL_H
+
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+
+#include <atomic>
+#include <string>
+
+#include "../../include/binning.h"
+#include "kernels.h"
+
+namespace binimpl {
+
+// Tuning overrides for the planner (autotuner, tests); zero fields = default.
+struct PlanHints {
+  int force_strategy = -1;  // -1 auto, else bk::Strategy
+  int block = 0;
+  int grid = 0;
+};
+
+// errors (thread-local message)
+int fail(int status, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+void clear_error();
+const char* last_error();
+
+// argument checks (no HIP calls)
+int validate(const bin_columns* coords, const bin_columns* attrs, int64_t n, const int32_t axes[2],
+             const double bounds[4], int32_t nx, int32_t ny, uint32_t ops, const bin_output* out,
+             bool allow_null_bounds);
+
+struct DeviceInfo {
+  int device = 0;
+  int cus = 256;
+  size_t lds_per_block = 65536;
+  size_t lds_per_cu = 65536;
+};
+int device_info(DeviceInfo* info);
+
+// scratch pools
+int scratch_get(int dev, hipStream_t s, size_t bytes, void** out);
+int release_all_scratch();
+bool fault_injection_hit();
+
+// kernel timing (bin_timing_*): a timer for one call, or null when off
+bk::KTimer* timing_timer();
+int timing_enable(int on);
+int timing_read(int64_t* launches, double* total_ms);
+int timing_report(char* buf, size_t buflen);
+
+// One request turned into kernel arguments.
+struct Prepared {
+  bk::BinArgs bin;
+  bk::InitArgs init;
+  bk::FinArgs fin;
+  bk::LdsArgs lds;
+  bk::PartArgs part;
+  bk::PartCfg pcfg;
+  bk::LaunchCfg cfg;
+  bool coord_f64 = false, attr_f64 = false;
+  int prec = bk::PREC_F64;
+  bool need_finalize = false;
+  size_t scratch_bytes = 0;
+  int init_grid = 1, fin_grid = 1;
+};
+
+const PlanHints& thread_hints();
+int resolve_precision(uint32_t ops, bool attr_f64);
+
+// Plan a validated request and lay out its scratch at 'scratch' (may be null
+// when only sizing: then pointers into scratch are left null and
+// scratch_bytes is filled in).
+int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints, void* scratch, Prepared* p);
+// Enqueue the kernels of a prepared request.
+int enqueue(const Prepared& p, hipStream_t s, bk::KTimer* tm);
+// Human-readable plan.
+std::string describe(const Prepared& p);
+
+// Whole requests.
+int run_request(const bin_request& r, hipStream_t s, const PlanHints& hints);
+int run_auto_bounds(const bin_request& r, hipStream_t s);
+
+}  // namespace binimpl
+
+#endif

@@ -1,0 +1,182 @@
+// Argument records shared by the binning kernels and their host launchers.
+// Plain C++ structs passed by value as kernel arguments; device pointers only.
+#ifndef BINNING_KERNELS_H
+#define BINNING_KERNELS_H
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bk {
+
+constexpr int kMaxAttrs = 16;  // matches BIN_MAX_ATTRS
+
+// Sum accumulation: FP32 with TwoSum compensation, plain FP32, binary64.
+enum Prec { PREC_COMP = 0, PREC_PLAIN = 1, PREC_F64 = 2 };
+// STRAT_GLOBAL: device-scope atomics into the result grids.
+// STRAT_LDS: each workgroup holds the whole grid in LDS.
+// STRAT_PART: particles partitioned by tile, one LDS tile per work item.
+enum Strategy { STRAT_GLOBAL = 0, STRAT_LDS = 1, STRAT_PART = 2 };
+enum SrcKind { SRC_F64 = 0, SRC_F32 = 1, SRC_F32_COMP = 2 };
+
+// One mesh axis: bounds, precomputed binary64 scale n / (hi - lo), cells.
+struct Axis {
+  double lo, hi, scale;
+  int32_t n;
+  int32_t pad;
+};
+
+// Result grids (null = not requested).  sum/avg are double, or float under
+// PREC_PLAIN; min/max have the attribute's type.
+struct Outs {
+  uint32_t* cnt;
+  void* sum[kMaxAttrs];
+  void* mn[kMaxAttrs];
+  void* mx[kMaxAttrs];
+  void* avg[kMaxAttrs];
+};
+
+// Accumulators of one tile of TB bins in LDS, and the same accumulators as
+// a partial slot in device memory (byte offsets; count array at offset 0 in
+// both).  Sum words: f64, or f32 S and C (compensated), or f32 (plain) in
+// LDS; f64 (or f32 plain) in slots.  min/max as order-preserving keys.
+struct TileLayout {
+  int32_t lds_sum_off[kMaxAttrs];
+  int32_t lds_min_off[kMaxAttrs];
+  int32_t lds_max_off[kMaxAttrs];
+  int32_t slot_sum_off[kMaxAttrs];
+  int32_t slot_min_off[kMaxAttrs];
+  int32_t slot_max_off[kMaxAttrs];
+  int64_t slot_bytes;
+  int32_t tile_shift;  // TB = 1 << tile_shift (partition); LDS strategy: TB = nbins
+  int32_t tb;          // bins held in LDS per tile
+  int32_t want_sum;    // accumulate sums (SUM or AVG requested)
+  int32_t want_min, want_max, pad;
+};
+
+// ---- global-atomic strategy ---------------------------------------------
+// Global accumulators of one attribute.  sum: double* or float* (see
+// sum_is_f64); comp: float* error words (compensated mode only); mn/mx:
+// result arrays of the attribute's type, or null when not requested.
+struct AccPtrs {
+  void* sum;
+  float* comp;
+  void* mn;
+  void* mx;
+  int32_t sum_is_f64;
+  int32_t minmax_f64;
+};
+
+struct BinArgs {
+  const void* x;
+  const void* y;
+  const void* attr[kMaxAttrs];
+  uint32_t* cnt;  // global count accumulator, or null
+  AccPtrs acc[kMaxAttrs];
+  Axis ax, ay;
+  const long long* dyn;  // bounds computed on the device (4 keys), or null
+  int64_t n;
+  int32_t nx, nbins, k, pad;
+};
+
+struct InitArgs {
+  uint32_t* cnt;
+  AccPtrs acc[kMaxAttrs];
+  int64_t nbins;
+  int32_t k, pad;
+};
+
+struct FinAttr {
+  const void* src;    // merged sum words (kind below)
+  const float* comp;  // error words for SRC_F32_COMP
+  void* sum_out;      // double sum output written here (SRC_F32_COMP only)
+  void* avg_out;      // avg output or null
+  int32_t src_kind;
+  int32_t avg_f64;
+};
+
+struct FinArgs {
+  const uint32_t* cnt;
+  FinAttr attr[kMaxAttrs];
+  int64_t nbins;
+  int32_t k, pad;
+};
+
+// ---- LDS strategy (whole grid per workgroup) -----------------------------
+struct LdsArgs {
+  const void* x;
+  const void* y;
+  const void* attr[kMaxAttrs];
+  Axis ax, ay;
+  const long long* dyn;  // bounds computed on the device (4 keys), or null
+  int64_t n;
+  int64_t chunk;   // particles per workgroup
+  int32_t nx, nbins, k, nslots;
+  Outs out;
+  TileLayout lay;
+  void* partial;   // nslots partial slots (nslots > 1)
+};
+
+// ---- partition strategy --------------------------------------------------
+struct PartArgs {
+  const void* x;
+  const void* y;
+  const void* attr[kMaxAttrs];
+  Axis ax, ay;
+  const long long* dyn;  // bounds computed on the device (4 keys), or null
+  int64_t n;
+  int64_t chunk;       // particles per count/scatter workgroup
+  int32_t nx, nbins, k, ntiles, nwg, max_items;
+  uint32_t split_len;  // max records per work item
+  int32_t stage_val_off;  // byte offset of staged values in the scatter LDS
+  uint32_t* counts;    // [ntiles][nwg] counts, scanned in place to offsets
+  uint32_t* bsum;      // scan block sums (+ total at [scan_blocks])
+  uint32_t* inside;    // -> total records (inside particles)
+  uint16_t* rec_bin;   // [n] local bin of each record
+  void* rec_val[kMaxAttrs];  // [n] attribute values of each record
+  uint32_t* items;     // [max_items][3]: tile, begin, end
+  uint32_t* n_items;   // [1]
+  uint32_t* tile_items;  // [ntiles][2]: first item, item count
+  void* partial;       // max_items partial slots (split tiles only)
+  Outs out;
+  TileLayout lay;
+};
+
+struct PartCfg {
+  size_t count_lds, scatter_lds, bin_lds;
+  int scan_blocks;
+  int64_t scan_per;
+  int ppt;
+  int bin_block;
+};
+
+// Optional per-kernel timing: begin() records an event before a launch,
+// end(name) one after it; both on the launch stream.
+struct KTimer {
+  virtual void begin(hipStream_t s) = 0;
+  virtual void end(const char* name, hipStream_t s) = 0;
+  virtual ~KTimer() {}
+};
+
+struct LaunchCfg {
+  int strategy;
+  int grid, block;
+  size_t lds_bytes;
+};
+
+hipError_t launch_bin_global(const BinArgs& a, bool coord_f64, bool attr_f64, int prec, const LaunchCfg& c,
+                             hipStream_t s, KTimer* tm);
+hipError_t launch_bin_lds(const LdsArgs& a, bool coord_f64, bool attr_f64, int prec, const LaunchCfg& c,
+                          hipStream_t s, KTimer* tm);
+hipError_t launch_init(const InitArgs& a, int grid, hipStream_t s, KTimer* tm);
+hipError_t launch_finalize(const FinArgs& a, int grid, hipStream_t s, KTimer* tm);
+hipError_t launch_partition(const PartArgs& a, bool coord_f64, bool attr_f64, int prec, const PartCfg& c,
+                            hipStream_t s, KTimer* tm);
+hipError_t set_lds_limit(size_t bytes);
+hipError_t set_dynamic_lds_limit(const void* fn, size_t total);
+hipError_t launch_bounds(const void* x, const void* y, bool coord_f64, int64_t n, long long* keys, int cus,
+                         hipStream_t s, KTimer* tm);
+hipError_t set_partition_lds_limit(size_t bytes);
+
+}  // namespace bk
+
+#endif

@@ -1,0 +1,355 @@
+// Planning of one binning request: strategy choice, launch shapes, scratch
+// layout and kernel argument records; then the launch sequence.
+//
+// Strategy choice on gfx950 (LDS atomics ~100x the rate of device-scope
+// atomics):
+//   LDS        whole grid fits one workgroup's LDS: each workgroup bins a
+//              slice, partials merged with plain loads/stores.
+//   PARTITION  otherwise, if the grid splits into at most kMaxTiles
+//              LDS-sized tiles: particles are partitioned by tile first.
+//   GLOBAL     device-scope atomics; only for grids beyond kMaxTiles tiles.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+
+#include "internal.h"
+
+namespace binimpl {
+
+namespace {
+
+constexpr int kMaxTiles = 4096;         // tile ids are 16-bit in the scatter stage
+constexpr size_t kScatterStatic = 2048;  // static LDS of part_scatter_kernel
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Bump allocator over the scratch block (or a pure size count when base is
+// null).
+struct Carve {
+  unsigned char* base;
+  size_t used = 0;
+  void* take(size_t bytes) {
+    void* p = base ? base + used : nullptr;
+    used += align256(bytes);
+    return p;
+  }
+};
+
+// LDS and slot layout of a tile of tb bins.  Returns the LDS bytes.
+size_t tile_layout(int tb, int k, bool sum, bool mn, bool mx, int prec, size_t asz, bk::TileLayout* L) {
+  std::memset(L, 0, sizeof *L);
+  L->tb = tb;
+  L->want_sum = sum;
+  L->want_min = mn;
+  L->want_max = mx;
+  const size_t lds_sum = (prec == bk::PREC_PLAIN) ? 4 : 8;
+  const size_t slot_sum = (prec == bk::PREC_PLAIN) ? 4 : 8;
+  size_t lo = align16(4 * (size_t)tb), so = align16(4 * (size_t)tb);
+  for (int j = 0; j < k; ++j) {
+    L->lds_sum_off[j] = (int32_t)std::min<size_t>(lo, INT32_MAX);
+    L->slot_sum_off[j] = (int32_t)std::min<size_t>(so, INT32_MAX);
+    if (sum) {
+      lo = align16(lo + lds_sum * tb);
+      so = align16(so + slot_sum * tb);
+    }
+    L->lds_min_off[j] = (int32_t)std::min<size_t>(lo, INT32_MAX);
+    L->slot_min_off[j] = (int32_t)std::min<size_t>(so, INT32_MAX);
+    if (mn) {
+      lo = align16(lo + asz * tb);
+      so = align16(so + asz * tb);
+    }
+    L->lds_max_off[j] = (int32_t)std::min<size_t>(lo, INT32_MAX);
+    L->slot_max_off[j] = (int32_t)std::min<size_t>(so, INT32_MAX);
+    if (mx) {
+      lo = align16(lo + asz * tb);
+      so = align16(so + asz * tb);
+    }
+  }
+  L->slot_bytes = (int64_t)align256(so);
+  return lo;
+}
+
+void fill_outs(const bin_request& r, int k, bk::Outs* o) {
+  std::memset(o, 0, sizeof *o);
+  o->cnt = (r.ops & BIN_COUNT) ? r.out.count : nullptr;
+  for (int j = 0; j < k; ++j) {
+    o->sum[j] = (r.ops & BIN_SUM) ? r.out.sum[j] : nullptr;
+    o->mn[j] = (r.ops & BIN_MIN) ? r.out.min[j] : nullptr;
+    o->mx[j] = (r.ops & BIN_MAX) ? r.out.max[j] : nullptr;
+    o->avg[j] = (r.ops & BIN_AVG) ? r.out.avg[j] : nullptr;
+  }
+}
+
+}  // namespace
+
+int resolve_precision(uint32_t ops, bool attr_f64) {
+  if (attr_f64) return bk::PREC_F64;
+  if (ops & BIN_PREC_PLAIN) return bk::PREC_PLAIN;
+  if (ops & BIN_PREC_COMP) return bk::PREC_COMP;
+  // Default: binary64 accumulation.  On gfx950 an LDS binary64 atomic add is
+  // several times faster than the FP32 one, and a global binary64 add is one
+  // atomic where TwoSum needs two; the result is at least as accurate as the
+  // compensated FP32 sum.
+  return bk::PREC_F64;
+}
+
+int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints, void* scratch, Prepared* p) {
+  std::memset(&p->bin, 0, sizeof p->bin);
+  std::memset(&p->init, 0, sizeof p->init);
+  std::memset(&p->fin, 0, sizeof p->fin);
+  std::memset(&p->lds, 0, sizeof p->lds);
+  std::memset(&p->part, 0, sizeof p->part);
+  std::memset(&p->pcfg, 0, sizeof p->pcfg);
+  std::memset(&p->cfg, 0, sizeof p->cfg);
+  const uint32_t ops = r.ops;
+  const int k = r.attrs.cols ? r.attrs.ncols : 0;
+  const int64_t nb = (int64_t)r.nx * r.ny;
+  p->coord_f64 = r.coords.dtype == BIN_F64;
+  p->attr_f64 = k > 0 && r.attrs.dtype == BIN_F64;
+  p->prec = resolve_precision(ops, p->attr_f64);
+  const bool want_cnt = ops & (BIN_COUNT | BIN_AVG);
+  const bool want_sum = ops & (BIN_SUM | BIN_AVG);
+  const bool want_min = ops & BIN_MIN;
+  const bool want_max = ops & BIN_MAX;
+  const bool want_avg = ops & BIN_AVG;
+  const size_t asz = p->attr_f64 ? 8 : 4;
+  const int nk = (want_sum || want_min || want_max) ? k : 0;
+  const size_t lds_budget = dev.lds_per_block;
+  const int cus = std::max(dev.cus, 1);
+  const int64_t n = r.n;
+  const bk::Axis ax{r.bounds[0], r.bounds[1], (double)r.nx / (r.bounds[1] - r.bounds[0]), r.nx, 0};
+  const bk::Axis ay{r.bounds[2], r.bounds[3], (double)r.ny / (r.bounds[3] - r.bounds[2]), r.ny, 0};
+
+  // --- strategy
+  bk::TileLayout whole;
+  const size_t whole_lds = nb <= (int64_t)lds_budget
+                               ? tile_layout((int)nb, nk, want_sum, want_min, want_max, p->prec, asz, &whole)
+                               : SIZE_MAX;
+  // Largest power-of-two tile whose accumulators fit LDS.
+  int shift = 15;
+  bk::TileLayout tl;
+  size_t tile_lds = 0;
+  for (; shift >= 6; --shift) {
+    tile_lds = tile_layout(1 << shift, nk, want_sum, want_min, want_max, p->prec, asz, &tl);
+    if (tile_lds <= lds_budget) break;
+  }
+  tl.tile_shift = shift;
+  const int64_t ntiles = ceil_div(nb, (int64_t)1 << shift);
+  int strat;
+  if (whole_lds <= lds_budget) strat = bk::STRAT_LDS;
+  else if (shift >= 6 && ntiles <= kMaxTiles) strat = bk::STRAT_PART;
+  else strat = bk::STRAT_GLOBAL;
+  if (hints.force_strategy == bk::STRAT_GLOBAL) strat = bk::STRAT_GLOBAL;
+  if (hints.force_strategy == bk::STRAT_LDS && whole_lds <= lds_budget) strat = bk::STRAT_LDS;
+  if (hints.force_strategy == bk::STRAT_PART && shift >= 6 && ntiles <= kMaxTiles) strat = bk::STRAT_PART;
+  p->cfg.strategy = strat;
+  Carve cv{static_cast<unsigned char*>(scratch)};
+
+  if (strat == bk::STRAT_LDS) {
+    bk::LdsArgs& a = p->lds;
+    a.x = r.coords.cols[r.axes[0]];
+    a.y = r.coords.cols[r.axes[1]];
+    for (int j = 0; j < nk; ++j) a.attr[j] = r.attrs.cols[j];
+    a.ax = ax;
+    a.ay = ay;
+    a.n = n;
+    a.nx = r.nx;
+    a.nbins = (int32_t)nb;
+    a.k = nk;
+    fill_outs(r, nk, &a.out);
+    a.lay = whole;
+    bk::LaunchCfg& c = p->cfg;
+    c.lds_bytes = whole_lds;
+    c.block = hints.block ? hints.block : (whole_lds > 40 * 1024 ? 1024 : 512);
+    const int per_cu = (int)std::max<size_t>(
+        1, std::min<size_t>(dev.lds_per_cu / std::max<size_t>(whole_lds, 1), 2048 / c.block));
+    // Enough particles per workgroup to amortise writing and merging a slot.
+    const int64_t min_chunk = std::max<int64_t>(2 * nb, 16384);
+    int64_t grid = std::min<int64_t>(ceil_div(std::max<int64_t>(n, 1), min_chunk), (int64_t)cus * per_cu);
+    if (hints.grid) grid = hints.grid;
+    grid = std::max<int64_t>(grid, 1);
+    a.chunk = ceil_div(std::max<int64_t>(n, 1), grid);
+    c.grid = (int)ceil_div(std::max<int64_t>(n, 1), a.chunk);
+    a.nslots = c.grid;
+    if (a.nslots > 1) a.partial = cv.take((size_t)a.lay.slot_bytes * a.nslots);
+    p->scratch_bytes = cv.used;
+    return BIN_OK;
+  }
+
+  if (strat == bk::STRAT_PART) {
+    bk::PartArgs& a = p->part;
+    bk::PartCfg& c = p->pcfg;
+    a.x = r.coords.cols[r.axes[0]];
+    a.y = r.coords.cols[r.axes[1]];
+    for (int j = 0; j < nk; ++j) a.attr[j] = r.attrs.cols[j];
+    a.ax = ax;
+    a.ay = ay;
+    a.n = n;
+    a.nx = r.nx;
+    a.nbins = (int32_t)nb;
+    a.k = nk;
+    a.ntiles = (int32_t)ntiles;
+    fill_outs(r, nk, &a.out);
+    a.lay = tl;
+    const int T = (int)ntiles;
+    int64_t nwg = std::min<int64_t>(ceil_div(std::max<int64_t>(n, 1), 32768), cus);
+    if (hints.grid) nwg = std::min<int64_t>(hints.grid, 65535);
+    nwg = std::max<int64_t>(nwg, 1);
+    a.chunk = ceil_div(std::max<int64_t>(n, 1), nwg);
+    a.nwg = (int32_t)ceil_div(std::max<int64_t>(n, 1), a.chunk);
+    // split length: no split when tiles are balanced, bounded work otherwise
+    const int64_t L = std::max<int64_t>({ceil_div(3 * n, 2 * ntiles), ceil_div(n, 2 * (int64_t)cus), 16384});
+    a.split_len = (uint32_t)std::min<int64_t>(L, 0x7FFFFFFF);
+    a.max_items = (int32_t)(ntiles + ceil_div(n, (int64_t)a.split_len));
+    // scatter LDS: 3 T counters, S tile/bin words, S * k values
+    int ppt = 16;
+    size_t sc = 0;
+    for (; ppt >= 4; ppt /= 2) {
+      const size_t S = 512 * (size_t)ppt;
+      a.stage_val_off = (int32_t)align16(12 * (size_t)T + 4 * S);
+      sc = a.stage_val_off + S * nk * asz;
+      if (sc + kScatterStatic <= lds_budget) break;
+    }
+    if (ppt < 4) return fail(BIN_ERR_UNSUPPORTED, "partition scatter stage does not fit LDS");
+    c.ppt = ppt;
+    c.scatter_lds = std::max<size_t>(sc, 16);
+    c.count_lds = 4 * (size_t)T;
+    c.bin_lds = tile_lds;
+    c.bin_block = 1024;
+    const int64_t m = ntiles * a.nwg;
+    c.scan_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(m, 4096)));
+    c.scan_per = ceil_div(m, c.scan_blocks);
+    // scratch
+    a.counts = static_cast<uint32_t*>(cv.take(4 * (size_t)m));
+    a.bsum = static_cast<uint32_t*>(cv.take(4 * ((size_t)c.scan_blocks + 1)));
+    a.inside = a.bsum ? a.bsum + c.scan_blocks : nullptr;
+    a.items = static_cast<uint32_t*>(cv.take(12 * (size_t)a.max_items));
+    a.n_items = static_cast<uint32_t*>(cv.take(4));
+    a.tile_items = static_cast<uint32_t*>(cv.take(8 * (size_t)T));
+    a.rec_bin = static_cast<uint16_t*>(cv.take(2 * (size_t)std::max<int64_t>(n, 1)));
+    for (int j = 0; j < nk; ++j) a.rec_val[j] = cv.take(asz * (size_t)std::max<int64_t>(n, 1));
+    // Partial slots are needed only for items of split tiles; at most
+    // max_items - ntiles + (number of split tiles) <= 2 * (max_items - ntiles).
+    const int64_t split_items = std::min<int64_t>(a.max_items, 2 * (a.max_items - ntiles));
+    a.partial = split_items > 0 ? cv.take((size_t)a.lay.slot_bytes * a.max_items) : nullptr;
+    p->scratch_bytes = cv.used;
+    p->cfg.grid = a.max_items;
+    p->cfg.block = c.bin_block;
+    return BIN_OK;
+  }
+
+  // --- global-atomic strategy
+  uint32_t* cnt = nullptr;
+  if (want_cnt) cnt = (ops & BIN_COUNT) ? r.out.count : static_cast<uint32_t*>(cv.take(4 * nb));
+  const bool comp_global = p->prec == bk::PREC_COMP;
+  bk::BinArgs& a = p->bin;
+  a.x = r.coords.cols[r.axes[0]];
+  a.y = r.coords.cols[r.axes[1]];
+  a.cnt = cnt;
+  a.n = n;
+  a.nx = r.nx;
+  a.nbins = (int32_t)nb;
+  a.k = nk;
+  a.ax = ax;
+  a.ay = ay;
+  bk::FinArgs& f = p->fin;
+  f.cnt = cnt;
+  f.nbins = nb;
+  f.k = want_avg || comp_global ? nk : 0;
+  p->need_finalize = false;
+  for (int j = 0; j < nk; ++j) {
+    a.attr[j] = r.attrs.cols[j];
+    bk::AccPtrs& acc = a.acc[j];
+    acc.minmax_f64 = p->attr_f64;
+    acc.mn = want_min ? r.out.min[j] : nullptr;
+    acc.mx = want_max ? r.out.max[j] : nullptr;
+    bk::FinAttr& fa = f.attr[j];
+    fa.avg_out = want_avg ? r.out.avg[j] : nullptr;
+    fa.avg_f64 = p->prec != bk::PREC_PLAIN;
+    if (want_sum) {
+      if (comp_global) {
+        acc.sum = cv.take(4 * nb);
+        acc.comp = static_cast<float*>(cv.take(4 * nb));
+        acc.sum_is_f64 = 0;
+        fa.src = acc.sum;
+        fa.comp = acc.comp;
+        fa.src_kind = bk::SRC_F32_COMP;
+        fa.sum_out = (ops & BIN_SUM) ? r.out.sum[j] : nullptr;
+        p->need_finalize = true;
+      } else {
+        const bool f64 = p->prec != bk::PREC_PLAIN;
+        acc.sum = (ops & BIN_SUM) ? r.out.sum[j] : cv.take((f64 ? 8 : 4) * nb);
+        acc.sum_is_f64 = f64;
+        fa.src = acc.sum;
+        fa.src_kind = f64 ? bk::SRC_F64 : bk::SRC_F32;
+      }
+    }
+    if (want_avg) p->need_finalize = true;
+  }
+  p->scratch_bytes = cv.used;
+  bk::InitArgs& in = p->init;
+  in.cnt = cnt;
+  in.nbins = nb;
+  in.k = nk;
+  for (int j = 0; j < nk; ++j) in.acc[j] = a.acc[j];
+  p->init_grid = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(nb, 256), (int64_t)cus * 8));
+  p->fin_grid = p->init_grid;
+  bk::LaunchCfg& c = p->cfg;
+  c.block = hints.block ? hints.block : 256;
+  int64_t grid = std::min<int64_t>(ceil_div(std::max<int64_t>(n, 1), (int64_t)c.block * 4), (int64_t)cus * 16);
+  if (hints.grid) grid = hints.grid;
+  c.grid = (int)std::max<int64_t>(grid, 1);
+  return BIN_OK;
+}
+
+int enqueue(const Prepared& p, hipStream_t s, bk::KTimer* tm) {
+  hipError_t e = hipSuccess;
+  switch (p.cfg.strategy) {
+    case bk::STRAT_LDS:
+      e = bk::launch_bin_lds(p.lds, p.coord_f64, p.attr_f64, p.prec, p.cfg, s, tm);
+      if (e != hipSuccess) return hip_fail(e, "launch LDS binning kernels");
+      return BIN_OK;
+    case bk::STRAT_PART:
+      e = bk::launch_partition(p.part, p.coord_f64, p.attr_f64, p.prec, p.pcfg, s, tm);
+      if (e != hipSuccess) return hip_fail(e, "launch partition binning kernels");
+      return BIN_OK;
+    default:
+      break;
+  }
+  e = bk::launch_init(p.init, p.init_grid, s, tm);
+  if (e != hipSuccess) return hip_fail(e, "launch bin_init_kernel");
+  if (p.bin.n > 0) {
+    e = bk::launch_bin_global(p.bin, p.coord_f64, p.attr_f64, p.prec, p.cfg, s, tm);
+    if (e != hipSuccess) return hip_fail(e, "launch bin_global_kernel");
+  }
+  if (p.need_finalize) {
+    e = bk::launch_finalize(p.fin, p.fin_grid, s, tm);
+    if (e != hipSuccess) return hip_fail(e, "launch bin_finalize_kernel");
+  }
+  return BIN_OK;
+}
+
+std::string describe(const Prepared& p) {
+  char buf[320];
+  const char* prec = p.prec == bk::PREC_PLAIN ? "fp32" : p.prec == bk::PREC_F64 ? "fp64" : "fp32-comp";
+  switch (p.cfg.strategy) {
+    case bk::STRAT_LDS:
+      snprintf(buf, sizeof buf, "lds grid=%d block=%d lds=%zu chunk=%lld prec=%s", p.cfg.grid, p.cfg.block,
+               p.cfg.lds_bytes, (long long)p.lds.chunk, prec);
+      break;
+    case bk::STRAT_PART:
+      snprintf(buf, sizeof buf,
+               "partition tiles=%d tile_bins=%d wg=%d chunk=%lld ppt=%d split=%u max_items=%d "
+               "scatter_lds=%zu bin_lds=%zu prec=%s",
+               p.part.ntiles, 1 << p.part.lay.tile_shift, p.part.nwg, (long long)p.part.chunk, p.pcfg.ppt,
+               p.part.split_len, p.part.max_items, p.pcfg.scatter_lds, p.pcfg.bin_lds, prec);
+      break;
+    default:
+      snprintf(buf, sizeof buf, "global grid=%d block=%d prec=%s", p.cfg.grid, p.cfg.block, prec);
+  }
+  return buf;
+}
+
+}  // namespace binimpl

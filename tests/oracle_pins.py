@@ -292,3 +292,42 @@ def pin_f32_columns(orc):
 ALL_PINS = [pin_golden, pin_bruteforce_random, pin_bruteforce_edges, pin_general_bounds_near_edges,
             pin_scipy, pin_invariants, pin_metamorphic, pin_lattice, pin_signed_zero_order,
             pin_f32_columns]
+
+
+def pin_auto_bounds(orc):
+    """Bounds from the data: brute force agreement, extremes in the first and
+    last cells, non-finite coordinates ignored, zero-extent axes."""
+    rng = np.random.default_rng(21)
+    n = 700
+    x = rng.uniform(-3, 5, n)
+    y = rng.uniform(2, 2.5, n)
+    x[:3] = [np.nan, np.inf, -np.inf]
+    y[10] = np.nan
+    a = rng.standard_normal(n)
+    r = orc.bin_particles([x, y], [a], (0, 1), None, 16, 8, ALL)
+    bf = orc_bruteforce([x, y], [a], (0, 1), None, 16, 8)
+    assert np.array_equal(r["count"], bf["count"])
+    assert same_bits(r["min"][0], bf["min"][0]) and same_bits(r["max"][0], bf["max"][0])
+    fin = np.isfinite(x) & np.isfinite(y)
+    assert r["inside"] == int(fin.sum())
+    xf, yf = x[np.isfinite(x)], y[np.isfinite(y)]
+    ix_min = int(np.argmin(np.where(np.isfinite(x), x, np.inf)))
+    ix_max = int(np.argmax(np.where(np.isfinite(x), x, -np.inf)))
+    bnd = (xf.min(), xf.max(), yf.min(), yf.max())
+    assert orc.auto_bounds([x, y], (0, 1)) == bnd
+    r2 = orc.bin_particles([x, y], [a], (0, 1), bnd, 16, 8, ALL)
+    assert np.array_equal(r["count"], r2["count"])
+    # the extreme particles sit in the first and the last column
+    inside, idx = orc.axis_index(x, bnd[0], bnd[1], 16)
+    assert idx[ix_min] == 0 and idx[ix_max] == 15 and inside[ix_min] and inside[ix_max]
+    # zero extent: all finite particles in the first cell of that axis
+    xc = np.full(50, 0.75)
+    yc = rng.uniform(0, 1, 50)
+    r = orc.bin_particles([xc, yc], [np.ones(50)], (0, 1), None, 4, 5, ALL)
+    assert r["count"][:, 0].sum() == 50 and r["count"][:, 1:].sum() == 0
+    # no finite value: nothing inside
+    r = orc.bin_particles([np.full(5, np.nan), np.ones(5)], [np.ones(5)], (0, 1), None, 3, 3, ALL)
+    assert r["inside"] == 0 and r["count"].sum() == 0
+
+
+ALL_PINS.append(pin_auto_bounds)

@@ -1,0 +1,123 @@
+"""C ABI without a GPU: the library loads, exports every declared function,
+and rejects bad arguments before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2310_02926_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "binning.h")
+
+F = 0x10000  # fake, suitably aligned device addresses: never dereferenced here
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:bin|binsrv)_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    L = B.lib()
+    names = declared_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(B.EXPORTS)
+
+
+def test_status_strings_and_version():
+    assert B.status_string(B.BIN_OK) == "BIN_OK"
+    assert B.status_string(B.BIN_ERR_INVALID_ARG) == "BIN_ERR_INVALID_ARG"
+    assert B.status_string(-99) == "BIN_ERR_UNKNOWN"
+    assert re.match(r"\d+\.\d+\.\d+", B.bin_version())
+
+
+def good(**over):
+    args = dict(coords=[F, F + 0x100, F + 0x200], attrs=[F + 0x300, F + 0x400], n=1000, axes=(0, 1),
+                bounds=(0.0, 1.0, 0.0, 1.0), nx=16, ny=8, ops=B.OPS_ALL,
+                out={"count": F + 0x500, "sum": [F + 0x600, F + 0x700], "min": [F + 0x800, F + 0x900],
+                     "max": [F + 0xA00, F + 0xB00], "avg": [F + 0xC00, F + 0xD00]},
+                coord_dtype=B.BIN_F32, attr_dtype=B.BIN_F32)
+    args.update(over)
+    return args
+
+
+def validate(**over):
+    return B.bin_validate(**good(**over))
+
+
+def test_valid_request_passes():
+    assert validate() == B.BIN_OK
+    assert validate(n=0) == B.BIN_OK
+    assert validate(n=0xFFFFFFFF) == B.BIN_OK
+    assert validate(attrs=[], ops=B.COUNT, out={"count": F}) == B.BIN_OK
+    assert validate(bounds=None) == B.BIN_OK  # bounds on the fly
+
+
+@pytest.mark.parametrize("over,frag", [
+    (dict(n=-1), "n ="),
+    (dict(n=0x100000000), "n ="),
+    (dict(nx=0), "nx, ny"),
+    (dict(ny=-3), "nx, ny"),
+    (dict(nx=65536, ny=65536), "exceeds"),
+    (dict(axes=(0, 3)), "axes[1]"),
+    (dict(axes=(-1, 0)), "axes[0]"),
+    (dict(bounds=(0.0, float("nan"), 0.0, 1.0)), "finite"),
+    (dict(bounds=(0.0, float("inf"), 0.0, 1.0)), "finite"),
+    (dict(bounds=(1.0, 1.0, 0.0, 1.0)), "lo < hi"),
+    (dict(bounds=(0.0, 1.0, 2.0, 1.0)), "lo < hi"),
+    (dict(bounds=(-1.7e308, 1.7e308, 0.0, 1.0)), "overflows"),
+    (dict(bounds=(0.0, 1e-320, 0.0, 1.0)), "scale"),
+    (dict(ops=0), "no reduction"),
+    (dict(ops=0x4000), "unknown bits"),
+    (dict(ops=B.OPS_ALL | B.PREC_PLAIN | B.PREC_F64), "exclusive"),
+    (dict(attrs=[], ops=B.SUM), "no attribute"),
+    (dict(coord_dtype=7), "dtype"),
+    (dict(attr_dtype=5), "dtype"),
+    (dict(coords=[F + 2, F, F]), "misaligned"),
+    (dict(coords=[0, F, F]), "NULL"),
+    (dict(attrs=[F, 0]), "NULL"),
+    (dict(out={"sum": [F, F]}), "count"),
+    (dict(out={"count": F, "sum": [F, F], "min": [F, F], "max": [F, F]}), "avg"),
+    (dict(out={"count": F, "sum": [F, 0], "min": [F, F], "max": [F, F], "avg": [F, F]}), "sum[1]"),
+    (dict(out={"count": F, "sum": [F + 4, F], "min": [F, F], "max": [F, F], "avg": [F, F]}), "misaligned"),
+    (dict(attrs=[F] * 17), "attrs->ncols"),
+])
+def test_invalid_arguments_rejected(over, frag):
+    assert validate(**over) == B.BIN_ERR_INVALID_ARG
+    assert frag in B.last_error(), B.last_error()
+
+
+def test_bin_particles_rejects_before_any_hip_call():
+    # No GPU in this process: an argument error must come back without the
+    # library ever reaching the HIP runtime.
+    with pytest.raises(B.BinError) as ei:
+        B.bin_particles(**good(nx=0), stream=0)
+    assert ei.value.status == B.BIN_ERR_INVALID_ARG
+    with pytest.raises(B.BinError) as ei:
+        B.bin_particles(**good(bounds=(0.0, 0.0, 0.0, 1.0)), stream=0)
+    assert ei.value.status == B.BIN_ERR_INVALID_ARG
+
+
+def test_plain_sum_outputs_may_be_4_byte_aligned():
+    out = {"count": F, "sum": [F + 4, F], "min": [F, F], "max": [F, F], "avg": [F + 4, F]}
+    assert validate(out=out, ops=B.OPS_ALL | B.PREC_PLAIN) == B.BIN_OK
+    assert validate(out=out) == B.BIN_ERR_INVALID_ARG  # default: double outputs
+
+
+def test_f64_attributes_need_8_byte_min_max():
+    out = {"count": F, "sum": [F, F], "min": [F + 4, F], "max": [F, F], "avg": [F, F]}
+    assert validate(out=out, attr_dtype=B.BIN_F64) == B.BIN_ERR_INVALID_ARG
+    assert validate(out=out, attr_dtype=B.BIN_F32) == B.BIN_OK
+
+
+def test_single_hip_runtime_mapped():
+    import torch  # noqa: F401
+    B.lib()
+    maps = open("/proc/self/maps").read()
+    libs = {l.split()[-1] for l in maps.splitlines() if "libamdhip64" in l}
+    assert len(libs) == 1, libs

@@ -45,12 +45,21 @@ MUTANTS = [
 ]
 
 
+MUTANTS += [
+    ("auto_bounds_keep_nonfinite", "f = v[np.isfinite(v)]", "f = v[~np.isnan(v)]"),
+    ("auto_bounds_swapped", 'out += [float(f.min()), float(f.max())] if f.size',
+     'out += [float(f.min()), float(f.max()) * (1 + 2**-40)] if f.size'),
+    ("zero_extent_nan", "if hi > lo else np.float64(0.0)", "if hi >= lo else np.float64(0.0)"),
+]
+
+
 def _mutant_module(old, new):
     src = open(SRC).read()
     assert src.count(old) == 1, f"mutation anchor not unique/found: {old!r}"
     mod = types.ModuleType("oracle_mutant")
     exec(compile(src.replace(old, new), "oracle_mutant", "exec"), mod.__dict__)
     return mod
+
 
 
 @pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
