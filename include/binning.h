@@ -218,6 +218,21 @@ int bin_timing_report(char* buf, size_t buflen);
  * pass). */
 int bin_set_plan_override(int32_t strategy, int32_t block, int32_t grid);
 
+/* Tuning parameters of the partition strategy for later calls made by this
+ * thread (autotuner, tests); value 0 restores the planner's choice.
+ *  BIN_TUNE_PART_WG          workgroups of the count and scatter passes
+ *  BIN_TUNE_SCATTER_PPT      particles per thread per scatter sub-chunk (4, 8, 16 or 32)
+ *  BIN_TUNE_SCATTER_THREADS  threads per scatter workgroup (256, 512 or 1024)
+ *  BIN_TUNE_TILE_SHIFT       log2 of the largest tile (6..15)
+ *  BIN_TUNE_SPLIT_LEN        max records per binning work item (>= 1024)
+ * Returns BIN_ERR_INVALID_ARG for an unknown parameter or value. */
+#define BIN_TUNE_PART_WG 1
+#define BIN_TUNE_SCATTER_PPT 2
+#define BIN_TUNE_SCATTER_THREADS 3
+#define BIN_TUNE_TILE_SHIFT 4
+#define BIN_TUNE_SPLIT_LEN 5
+int bin_set_tuning(int32_t param, int64_t value);
+
 /* Describe the strategy the planner picks for a request (no GPU work):
  * writes a short NUL-terminated text such as "lds wg=256 ppt=8" into buf. */
 int bin_describe_plan(const bin_request* req, char* buf, size_t buflen);

@@ -33,7 +33,7 @@ EXPORTS = (
     "bin_graph_destroy", "bin_autotune", "bin_status_string", "bin_last_error_message",
     "bin_stream_status", "bin_release_workspace", "bin_version", "bin_timing_enable", "bin_timing_read",
     "bin_timing_report",
-    "bin_describe_plan", "bin_set_plan_override", "binsrv_create", "binsrv_submit", "binsrv_wait", "binsrv_release",
+    "bin_describe_plan", "bin_set_plan_override", "bin_set_tuning", "binsrv_create", "binsrv_submit", "binsrv_wait", "binsrv_release",
     "binsrv_get_stats", "binsrv_destroy",
 )
 
@@ -113,6 +113,7 @@ def lib() -> ctypes.CDLL:
         "bin_timing_report": (c_int, [c_char_p, c_size_t]),
         "bin_describe_plan": (c_int, [POINTER(Request), c_char_p, c_size_t]),
         "bin_set_plan_override": (c_int, [c_int32, c_int32, c_int32]),
+        "bin_set_tuning": (c_int, [c_int32, c_int64]),
         "binsrv_create": (c_int, [POINTER(ServerConfig), POINTER(c_void_p)]),
         "binsrv_submit": (c_int, [c_void_p, POINTER(ServerRequest), POINTER(c_uint64)]),
         "binsrv_wait": (c_int, [c_void_p, c_uint64, c_int64, POINTER(Result)]),
@@ -277,6 +278,19 @@ def bin_describe_plan(req: Request) -> str:
 
 def bin_set_plan_override(strategy: int = -1, block: int = 0, grid: int = 0) -> None:
     check(lib().bin_set_plan_override(strategy, block, grid))
+
+
+TUNE_PART_WG, TUNE_SCATTER_PPT, TUNE_SCATTER_THREADS, TUNE_TILE_SHIFT, TUNE_SPLIT_LEN = 1, 2, 3, 4, 5
+
+
+def bin_set_tuning(param: int, value: int) -> None:
+    check(lib().bin_set_tuning(param, value))
+
+
+def reset_tuning() -> None:
+    for p in (TUNE_PART_WG, TUNE_SCATTER_PPT, TUNE_SCATTER_THREADS, TUNE_TILE_SHIFT, TUNE_SPLIT_LEN):
+        bin_set_tuning(p, 0)
+    bin_set_plan_override(-1, 0, 0)
 
 
 def bin_timing_enable(on: bool) -> None:

@@ -37,6 +37,7 @@ int precheck_stream(hipStream_t s) {
 namespace binimpl {
 static thread_local PlanHints t_hints;
 const PlanHints& thread_hints() { return t_hints; }
+PlanHints& thread_hints_mut() { return t_hints; }
 
 // Single request on a stream (also used by the autotuner).
 int run_request(const bin_request& r, hipStream_t s, const PlanHints& hints) {
@@ -124,6 +125,38 @@ int bin_set_plan_override(int32_t strategy, int32_t block, int32_t grid) {
   t_hints.block = block;
   t_hints.grid = grid;
   return BIN_OK;
+}
+
+int bin_set_tuning(int32_t param, int64_t value) {
+  clear_error();
+  if (value < 0) return fail(BIN_ERR_INVALID_ARG, "tuning value must be >= 0");
+  switch (param) {
+    case BIN_TUNE_PART_WG:
+      if (value > 65535) return fail(BIN_ERR_INVALID_ARG, "BIN_TUNE_PART_WG must be <= 65535");
+      t_hints.part_wg = (int)value;
+      return BIN_OK;
+    case BIN_TUNE_SCATTER_PPT:
+      if (value && value != 4 && value != 8 && value != 16 && value != 32)
+        return fail(BIN_ERR_INVALID_ARG, "BIN_TUNE_SCATTER_PPT must be 4, 8, 16 or 32");
+      t_hints.scatter_ppt = (int)value;
+      return BIN_OK;
+    case BIN_TUNE_SCATTER_THREADS:
+      if (value && value != 256 && value != 512 && value != 1024)
+        return fail(BIN_ERR_INVALID_ARG, "BIN_TUNE_SCATTER_THREADS must be 256, 512 or 1024");
+      t_hints.scatter_threads = (int)value;
+      return BIN_OK;
+    case BIN_TUNE_TILE_SHIFT:
+      if (value && (value < 6 || value > 15)) return fail(BIN_ERR_INVALID_ARG, "BIN_TUNE_TILE_SHIFT must be in 6..15");
+      t_hints.tile_shift = (int)value;
+      return BIN_OK;
+    case BIN_TUNE_SPLIT_LEN:
+      if (value && (value < 1024 || value > 0x7FFFFFFF))
+        return fail(BIN_ERR_INVALID_ARG, "BIN_TUNE_SPLIT_LEN must be in [1024, 2^31)");
+      t_hints.split_len = value;
+      return BIN_OK;
+    default:
+      return fail(BIN_ERR_INVALID_ARG, "unknown tuning parameter %d", param);
+  }
 }
 
 const char* bin_status_string(int status) {

@@ -18,7 +18,14 @@ struct PlanHints {
   int force_strategy = -1;  // -1 auto, else bk::Strategy
   int block = 0;
   int grid = 0;
+  // partition tuning (bin_set_tuning)
+  int part_wg = 0;
+  int scatter_ppt = 0;
+  int scatter_threads = 0;
+  int tile_shift = 0;
+  int64_t split_len = 0;
 };
+PlanHints& thread_hints_mut();
 
 // errors (thread-local message)
 int fail(int status, const char* fmt, ...);

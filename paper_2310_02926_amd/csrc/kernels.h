@@ -116,6 +116,14 @@ struct LdsArgs {
   void* partial;   // nslots partial slots (nslots > 1)
 };
 
+// A batch of LDS-strategy requests (records in a device table).
+struct LdsBatch {
+  const LdsArgs* descs;
+  const uint32_t* map_slot;   // binning blocks (index = workgroup slice)
+  const uint32_t* map_merge;  // merge blocks (index = 256-bin chunk)
+  int32_t nreq, n_slot_blocks, n_merge_blocks, pad;
+};
+
 // ---- partition strategy --------------------------------------------------
 struct PartArgs {
   const void* x;
@@ -135,17 +143,32 @@ struct PartArgs {
   void* rec_val[kMaxAttrs];  // [n] attribute values of each record
   uint32_t* items;     // [max_items][3]: tile, begin, end
   uint32_t* n_items;   // [1]
-  uint32_t* tile_items;  // [ntiles][2]: first item, item count
-  void* partial;       // max_items partial slots (split tiles only)
+  uint32_t* tile_items;  // [ntiles][3]: first item, item count, first partial slot
+  void* partial;       // max_slots partial slots (items of split tiles)
+  int32_t max_slots, pad2;
   Outs out;
   TileLayout lay;
+};
+
+// A batch of partition requests: records in a device table; each launch
+// lists its blocks in a map (request << 16 | index within the request).
+struct PartBatch {
+  const PartArgs* descs;
+  const uint32_t* map_wg;    // count and scatter blocks (index = workgroup slice)
+  const uint32_t* map_item;  // binning blocks (index = work item)
+  const uint32_t* map_tile;  // merge blocks (index = tile)
+  uint32_t* counts;          // all requests' count matrices, concatenated
+  uint32_t* bsum;
+  int64_t m;                 // total count entries
+  int32_t nreq, n_wg_blocks, n_item_blocks, n_tile_blocks;
 };
 
 struct PartCfg {
   size_t count_lds, scatter_lds, bin_lds;
   int scan_blocks;
   int64_t scan_per;
-  int ppt;
+  int ppt;              // particles per thread per scatter sub-chunk
+  int scatter_threads;  // threads per scatter workgroup
   int bin_block;
 };
 
@@ -167,10 +190,14 @@ hipError_t launch_bin_global(const BinArgs& a, bool coord_f64, bool attr_f64, in
                              hipStream_t s, KTimer* tm);
 hipError_t launch_bin_lds(const LdsArgs& a, bool coord_f64, bool attr_f64, int prec, const LaunchCfg& c,
                           hipStream_t s, KTimer* tm);
+hipError_t launch_lds_batch(const LdsBatch& b, bool coord_f64, bool attr_f64, int prec, size_t lds_bytes, int block,
+                            hipStream_t s, KTimer* tm);
 hipError_t launch_init(const InitArgs& a, int grid, hipStream_t s, KTimer* tm);
 hipError_t launch_finalize(const FinArgs& a, int grid, hipStream_t s, KTimer* tm);
 hipError_t launch_partition(const PartArgs& a, bool coord_f64, bool attr_f64, int prec, const PartCfg& c,
                             hipStream_t s, KTimer* tm);
+hipError_t launch_partition_batch(const PartBatch& b, bool coord_f64, bool attr_f64, int prec, const PartCfg& c,
+                                  hipStream_t s, KTimer* tm);
 hipError_t set_lds_limit(size_t bytes);
 hipError_t set_dynamic_lds_limit(const void* fn, size_t total);
 hipError_t launch_bounds(const void* x, const void* y, bool coord_f64, int64_t n, long long* keys, int cus,

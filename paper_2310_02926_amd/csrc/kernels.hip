@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256) void bin_finalize_kernel(FinArgs a) {
 // LDS strategy: the whole grid in one workgroup's LDS.
 // ---------------------------------------------------------------------------
 template <typename CT, typename AT, int PREC>
-__global__ __launch_bounds__(1024) void bin_lds_kernel(LdsArgs a) {
+__device__ __forceinline__ void bin_lds_body(const LdsArgs& a, int wg) {
   using TL = Tile<AT, PREC>;
   extern __shared__ __align__(16) unsigned char smem[];
   Axis ax = a.ax, ay = a.ay;
@@ -144,7 +144,7 @@ __global__ __launch_bounds__(1024) void bin_lds_kernel(LdsArgs a) {
   TL::init(smem, a.lay, a.k);
   __syncthreads();
 
-  const int64_t lo = (int64_t)blockIdx.x * a.chunk;
+  const int64_t lo = (int64_t)wg * a.chunk;
   const int64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
   constexpr int U = 4;
   for (int64_t base = lo; base < hi; base += (int64_t)U * blockDim.x) {
@@ -179,16 +179,40 @@ __global__ __launch_bounds__(1024) void bin_lds_kernel(LdsArgs a) {
   if (a.nslots <= 1)
     TL::emit_all(smem, a.lay, a.out, a.k, a.nbins, 0);
   else
-    TL::store_slot(smem, a.lay, a.k, a.nbins,
-                   static_cast<unsigned char*>(a.partial) + (int64_t)blockIdx.x * a.lay.slot_bytes);
+    TL::store_slot(smem, a.lay, a.k, a.nbins, static_cast<unsigned char*>(a.partial) + (int64_t)wg * a.lay.slot_bytes);
+}
+
+template <typename CT, typename AT, int PREC>
+__global__ __launch_bounds__(1024) void bin_lds_kernel(LdsArgs a) {
+  bin_lds_body<CT, AT, PREC>(a, blockIdx.x);
+}
+template <typename CT, typename AT, int PREC>
+__global__ __launch_bounds__(1024) void bin_lds_batched(const LdsArgs* __restrict__ d,
+                                                        const uint32_t* __restrict__ map) {
+  const uint32_t m = map[blockIdx.x];
+  bin_lds_body<CT, AT, PREC>(d[m >> 16], (int)(m & 0xFFFFu));
+}
+
+// Merge the slots of bins [b0, b0 + blockDim.x).
+template <typename AT, int PREC>
+__device__ __forceinline__ void lds_merge_body(const LdsArgs& a, int64_t b0) {
+  const int64_t b = b0 + threadIdx.x;
+  if (b < a.nbins)
+    Tile<AT, PREC>::merge_emit(static_cast<const unsigned char*>(a.partial), a.lay.slot_bytes, 0u,
+                               (uint32_t)a.nslots, a.lay, a.out, a.k, (int)b, b);
 }
 
 template <typename AT, int PREC>
 __global__ __launch_bounds__(256) void lds_merge_kernel(LdsArgs a) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < a.nbins; b += stride)
-    Tile<AT, PREC>::merge_emit(static_cast<const unsigned char*>(a.partial), a.lay.slot_bytes, 0u,
-                               (uint32_t)a.nslots, a.lay, a.out, a.k, (int)b, b);
+  for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x; b0 < a.nbins; b0 += (int64_t)gridDim.x * blockDim.x)
+    lds_merge_body<AT, PREC>(a, b0);
+}
+template <typename AT, int PREC>
+__global__ __launch_bounds__(256) void lds_merge_batched(const LdsArgs* __restrict__ d,
+                                                         const uint32_t* __restrict__ map) {
+  const uint32_t m = map[blockIdx.x];
+  const LdsArgs& a = d[m >> 16];
+  if (a.nslots > 1) lds_merge_body<AT, PREC>(a, (int64_t)(m & 0xFFFFu) * 256);
 }
 
 // ---------------------------------------------------------------------------
@@ -213,6 +237,25 @@ static hipError_t launch_lds_t(const LdsArgs& a, const LaunchCfg& c, hipStream_t
     const int64_t g = (a.nbins + 255) / 256;
     if (tm) tm->begin(s);
     hipLaunchKernelGGL((lds_merge_kernel<AT, PREC>), dim3((int)(g < 4096 ? g : 4096)), dim3(256), 0, s, a);
+    if (tm) tm->end("lds_merge_kernel", s);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename CT, typename AT, int PREC>
+static hipError_t launch_lds_batch_t(const LdsBatch& b, size_t lds_bytes, int block, hipStream_t s, KTimer* tm) {
+  hipError_t e;
+  if (b.n_slot_blocks > 0) {
+    if (tm) tm->begin(s);
+    hipLaunchKernelGGL((bin_lds_batched<CT, AT, PREC>), dim3(b.n_slot_blocks), dim3(block), lds_bytes, s, b.descs,
+                       b.map_slot);
+    if (tm) tm->end("bin_lds_kernel", s);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (b.n_merge_blocks > 0) {
+    if (tm) tm->begin(s);
+    hipLaunchKernelGGL((lds_merge_batched<AT, PREC>), dim3(b.n_merge_blocks), dim3(256), 0, s, b.descs, b.map_merge);
     if (tm) tm->end("lds_merge_kernel", s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
@@ -245,6 +288,11 @@ hipError_t launch_bin_lds(const LdsArgs& a, bool coord_f64, bool attr_f64, int p
                           hipStream_t s, KTimer* tm) {
   BK_DISPATCH(launch_lds_t, a, c, s, tm)
 }
+
+hipError_t launch_lds_batch(const LdsBatch& b, bool coord_f64, bool attr_f64, int prec, size_t lds_bytes, int block,
+                            hipStream_t s, KTimer* tm) {
+  BK_DISPATCH(launch_lds_batch_t, b, lds_bytes, block, s, tm)
+}
 #undef BK_DISPATCH
 
 hipError_t launch_init(const InitArgs& a, int grid, hipStream_t s, KTimer* tm) {
@@ -274,8 +322,9 @@ hipError_t set_dynamic_lds_limit(const void* fn, size_t total) {
 
 hipError_t set_lds_limit(size_t bytes) {
   hipError_t e = hipSuccess;
-#define BK_SET(CT, AT, P) \
-  if (e == hipSuccess) e = set_dynamic_lds_limit(reinterpret_cast<const void*>(&bin_lds_kernel<CT, AT, P>), bytes);
+#define BK_SET(CT, AT, P)                                                                                        \
+  if (e == hipSuccess) e = set_dynamic_lds_limit(reinterpret_cast<const void*>(&bin_lds_kernel<CT, AT, P>), bytes); \
+  if (e == hipSuccess) e = set_dynamic_lds_limit(reinterpret_cast<const void*>(&bin_lds_batched<CT, AT, P>), bytes);
   BK_SET(float, float, PREC_PLAIN)
   BK_SET(float, float, PREC_COMP)
   BK_SET(float, float, PREC_F64)

@@ -10,7 +10,7 @@
 //                 writes counts[tile][wg].
 //   scan_*        exclusive scan of counts (tile-major) -> record offsets.
 //   part_items    one work item per tile, heavy tiles split into items of at
-//                 most L records.
+//                 most L records; split tiles get partial slots.
 //   part_scatter  re-reads the same slice, sorts each sub-chunk by tile in
 //                 LDS and writes compact records (u16 local bin + attribute
 //                 values) tile by tile, so stores are contiguous runs.
@@ -18,6 +18,11 @@
 //                 then (single-item tile) the finished outputs - count, sum,
 //                 min, max, avg - written once, or (split tile) a partial.
 //   part_merge    combines the partials of split tiles into outputs.
+//
+// Every kernel body takes its request record by reference, so one body
+// serves a single request (record passed by value as the kernel argument)
+// and a batch (records in a device table, one block per (request, index)
+// pair listed in a block map: map = request << 16 | index).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -27,43 +32,9 @@
 namespace bk {
 
 // ---------------------------------------------------------------------------
-// Tile histogram.
+// Block-wide exclusive scans.
 // ---------------------------------------------------------------------------
-template <typename CT>
-__global__ __launch_bounds__(1024) void part_count_kernel(PartArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  uint32_t* h = reinterpret_cast<uint32_t*>(smem);
-  Axis ax = a.ax, ay = a.ay;
-  resolve_axes(a.dyn, ax, ay);
-  for (int t = threadIdx.x; t < a.ntiles; t += blockDim.x) h[t] = 0u;
-  __syncthreads();
-  const int64_t lo = (int64_t)blockIdx.x * a.chunk;
-  const int64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
-  const int shift = a.lay.tile_shift;
-  constexpr int U = 4;
-  for (int64_t base = lo; base < hi; base += (int64_t)U * blockDim.x) {
-    double xs[U], ys[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t i = base + (int64_t)u * blockDim.x + threadIdx.x;
-      xs[u] = i < hi ? (double)ld<CT>(a.x, i) : __builtin_nan("");
-      ys[u] = i < hi ? (double)ld<CT>(a.y, i) : __builtin_nan("");
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      int ix, iy;
-      if (locate(xs[u], ax, ix) && locate(ys[u], ay, iy)) atomicAdd(h + ((iy * a.nx + ix) >> shift), 1u);
-    }
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < a.ntiles; t += blockDim.x) a.counts[(int64_t)t * a.nwg + blockIdx.x] = h[t];
-}
-
-// ---------------------------------------------------------------------------
-// Exclusive scan of m u32 values in place (three launches).
-// ---------------------------------------------------------------------------
-// Block-wide exclusive scan of one value per thread (tmp: blockDim.x words
-// of LDS).  Called by every thread of the block.
+// Generic block size; tmp: blockDim.x words of LDS.
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* tmp, uint32_t* total) {
   const int t = threadIdx.x;
   tmp[t] = v;
@@ -80,6 +51,84 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* t
   return incl - v;
 }
 
+// Fixed block size NT, wave shuffles (three barriers); wave_tot: NT/64 words.
+template <int NT>
+__device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t* wave_tot, uint32_t& total) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wave_tot[wid] = x;
+  __syncthreads();
+  if (wid == 0) {
+    uint32_t w = lane < NW ? wave_tot[lane] : 0u;
+#pragma unroll
+    for (int o = 1; o < NW; o <<= 1) {
+      const uint32_t y = __shfl_up(w, o);
+      if (lane >= o) w += y;
+    }
+    if (lane < NW) wave_tot[lane] = w;
+  }
+  __syncthreads();
+  const uint32_t base = wid ? wave_tot[wid - 1] : 0u;
+  total = wave_tot[NW - 1];
+  __syncthreads();
+  return base + x - v;
+}
+
+// ---------------------------------------------------------------------------
+// Tile histogram of workgroup slice wg.
+// ---------------------------------------------------------------------------
+template <typename CT>
+__device__ __forceinline__ void part_count_body(const PartArgs& a, int wg) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint32_t* h = reinterpret_cast<uint32_t*>(smem);
+  Axis ax = a.ax, ay = a.ay;
+  resolve_axes(a.dyn, ax, ay);
+  const int T = a.ntiles;
+  for (int t = threadIdx.x; t < T; t += blockDim.x) h[t] = 0u;
+  __syncthreads();
+  const int64_t lo = (int64_t)wg * a.chunk;
+  const int64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
+  const int shift = a.lay.tile_shift;
+  constexpr int U = 8;
+  for (int64_t base = lo; base < hi; base += (int64_t)U * blockDim.x) {
+    double xs[U], ys[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = base + (int64_t)u * blockDim.x + threadIdx.x;
+      xs[u] = i < hi ? (double)ld<CT>(a.x, i) : __builtin_nan("");
+      ys[u] = i < hi ? (double)ld<CT>(a.y, i) : __builtin_nan("");
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      int ix, iy;
+      if (locate(xs[u], ax, ix) && locate(ys[u], ay, iy)) atomicAdd(h + ((iy * a.nx + ix) >> shift), 1u);
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < T; t += blockDim.x) a.counts[(int64_t)t * a.nwg + wg] = h[t];
+}
+
+template <typename CT>
+__global__ __launch_bounds__(1024) void part_count_kernel(PartArgs a) {
+  part_count_body<CT>(a, blockIdx.x);
+}
+template <typename CT>
+__global__ __launch_bounds__(1024) void part_count_batched(const PartArgs* __restrict__ d,
+                                                           const uint32_t* __restrict__ map) {
+  const uint32_t m = map[blockIdx.x];
+  part_count_body<CT>(d[m >> 16], (int)(m & 0xFFFFu));
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of m u32 values in place (three launches).
+// ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void scan_block_sums_kernel(const uint32_t* v, int64_t m, int64_t per,
                                                                uint32_t* bsum) {
   __shared__ uint32_t red[1024];
@@ -98,13 +147,12 @@ __global__ __launch_bounds__(1024) void scan_block_sums_kernel(const uint32_t* v
 
 // One block: exclusive scan of nb block sums in place; total at bsum[nb].
 __global__ __launch_bounds__(1024) void scan_top_kernel(uint32_t* bsum, int nb) {
-  __shared__ uint32_t tmp[1024];
+  __shared__ uint32_t wave_tot[16];
   uint32_t carry = 0;
-  for (int base = 0; base < nb; base += blockDim.x) {
+  for (int base = 0; base < nb; base += 1024) {
     const int i = base + threadIdx.x;
-    const uint32_t v = i < nb ? bsum[i] : 0u;
     uint32_t tot;
-    const uint32_t ex = block_exclusive_scan(v, tmp, &tot);
+    const uint32_t ex = block_scan_excl<1024>(i < nb ? bsum[i] : 0u, wave_tot, tot);
     if (i < nb) bsum[i] = carry + ex;
     carry += tot;
   }
@@ -113,15 +161,14 @@ __global__ __launch_bounds__(1024) void scan_top_kernel(uint32_t* bsum, int nb) 
 
 __global__ __launch_bounds__(1024) void scan_apply_kernel(uint32_t* v, int64_t m, int64_t per,
                                                           const uint32_t* bsum) {
-  __shared__ uint32_t tmp[1024];
+  __shared__ uint32_t wave_tot[16];
   const int64_t lo = (int64_t)blockIdx.x * per;
   const int64_t hi = lo + per < m ? lo + per : m;
   uint32_t carry = bsum[blockIdx.x];
-  for (int64_t base = lo; base < hi; base += blockDim.x) {
+  for (int64_t base = lo; base < hi; base += 1024) {
     const int64_t i = base + threadIdx.x;
-    const uint32_t x = i < hi ? v[i] : 0u;
     uint32_t tot;
-    const uint32_t ex = block_exclusive_scan(x, tmp, &tot);
+    const uint32_t ex = block_scan_excl<1024>(i < hi ? v[i] : 0u, wave_tot, tot);
     if (i < hi) v[i] = carry + ex;
     carry += tot;
   }
@@ -129,13 +176,15 @@ __global__ __launch_bounds__(1024) void scan_apply_kernel(uint32_t* v, int64_t m
 
 // ---------------------------------------------------------------------------
 // Work items: one per tile, heavy tiles split into ranges of <= split_len.
-// One block.  counts[] already holds the exclusive scan; *inside = total.
+// tile_items[3t] = first item, [3t+1] = items, [3t+2] = first partial slot
+// (split tiles only).  counts[] holds the exclusive scan; *inside is the
+// end of this request's records.  One block (1024 threads) per request.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void part_items_kernel(PartArgs a) {
-  __shared__ uint32_t tmp[1024];
+__device__ __forceinline__ void part_items_body(const PartArgs& a) {
+  __shared__ uint32_t wave_tot[16];
   const uint32_t total = *a.inside;
-  uint32_t carry = 0;
-  for (int base = 0; base < a.ntiles; base += blockDim.x) {
+  uint32_t carry = 0, scarry = 0;
+  for (int base = 0; base < a.ntiles; base += 1024) {
     const int t = base + threadIdx.x;
     uint32_t start = 0, end = 0, ni = 0;
     if (t < a.ntiles) {
@@ -144,11 +193,13 @@ __global__ __launch_bounds__(1024) void part_items_kernel(PartArgs a) {
       const uint32_t c = end - start;
       ni = c == 0 ? 1u : (c + a.split_len - 1) / a.split_len;
     }
-    uint32_t tot;
-    const uint32_t first = carry + block_exclusive_scan(ni, tmp, &tot);
+    uint32_t tot, stot;
+    const uint32_t first = carry + block_scan_excl<1024>(ni, wave_tot, tot);
+    const uint32_t slot0 = scarry + block_scan_excl<1024>(ni > 1 ? ni : 0u, wave_tot, stot);
     if (t < a.ntiles) {
-      a.tile_items[2 * t] = first;
-      a.tile_items[2 * t + 1] = ni;
+      a.tile_items[3 * t] = first;
+      a.tile_items[3 * t + 1] = ni;
+      a.tile_items[3 * t + 2] = slot0;
       for (uint32_t q = 0; q < ni; ++q) {
         const uint32_t it = first + q;
         if (it >= (uint32_t)a.max_items) break;  // max_items is a proven upper bound
@@ -159,22 +210,30 @@ __global__ __launch_bounds__(1024) void part_items_kernel(PartArgs a) {
       }
     }
     carry += tot;
+    scarry += stot;
   }
   if (threadIdx.x == 0) *a.n_items = carry < (uint32_t)a.max_items ? carry : (uint32_t)a.max_items;
 }
 
+__global__ __launch_bounds__(1024) void part_items_kernel(PartArgs a) { part_items_body(a); }
+__global__ __launch_bounds__(1024) void part_items_batched(const PartArgs* __restrict__ d) {
+  part_items_body(d[blockIdx.x]);
+}
+
 // ---------------------------------------------------------------------------
-// Scatter: per sub-chunk of S = blockDim * PPT particles, rank each inside
+// Scatter: per sub-chunk of S = NT * PPT particles, rank each inside
 // particle within its tile (LDS atomic), scan the tile counts, place records
 // in LDS in tile order, then copy each tile's run to its global segment.
+// The coordinates of the next sub-chunk are loaded while the current one is
+// sorted and written.
 // LDS: cnt[T] | off[T] | run[T] | (tile << 16 | local bin)[S] | values[k][S]
 // ---------------------------------------------------------------------------
-template <typename CT, typename AT, int PPT>
-__global__ __launch_bounds__(512) void part_scatter_kernel(PartArgs a) {
+template <typename CT, typename AT, int PPT, int NT>
+__device__ __forceinline__ void part_scatter_body(const PartArgs& a, int wg) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ uint32_t scan_tmp[512];
+  __shared__ uint32_t wave_tot[NT / 64];
+  constexpr int S = NT * PPT;
   const int T = a.ntiles;
-  const int S = blockDim.x * PPT;
   uint32_t* cnt = reinterpret_cast<uint32_t*>(smem);
   uint32_t* off = cnt + T;
   uint32_t* run = off + T;
@@ -183,42 +242,52 @@ __global__ __launch_bounds__(512) void part_scatter_kernel(PartArgs a) {
   Axis ax = a.ax, ay = a.ay;
   resolve_axes(a.dyn, ax, ay);
 
-  for (int t = threadIdx.x; t < T; t += blockDim.x) {
+  for (int t = threadIdx.x; t < T; t += NT) {
     cnt[t] = 0u;
-    run[t] = a.counts[(int64_t)t * a.nwg + blockIdx.x];
+    run[t] = a.counts[(int64_t)t * a.nwg + wg];
   }
-  __syncthreads();
-  const int64_t lo = (int64_t)blockIdx.x * a.chunk;
+  const int64_t lo = (int64_t)wg * a.chunk;
   const int64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
   const int shift = a.lay.tile_shift;
   const uint32_t lmask = (1u << shift) - 1u;
+  const int k = a.k;
+  CT px[PPT], py[PPT];
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    const int64_t i = lo + (int64_t)u * NT + threadIdx.x;
+    px[u] = i < hi ? ld<CT>(a.x, i) : CT(0);
+    py[u] = i < hi ? ld<CT>(a.y, i) : CT(0);
+  }
+  __syncthreads();
   for (int64_t base = lo; base < hi; base += S) {
-    uint32_t tb[PPT], rank[PPT];
+    uint32_t tb[PPT], pos[PPT];
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
-      const int64_t i = base + (int64_t)u * blockDim.x + threadIdx.x;
+      const int64_t i = base + (int64_t)u * NT + threadIdx.x;
       tb[u] = 0xFFFFFFFFu;
-      rank[u] = 0u;
-      if (i < hi) {
-        int ix, iy;
-        const double x = (double)ld<CT>(a.x, i);
-        const double y = (double)ld<CT>(a.y, i);
-        if (locate(x, ax, ix) && locate(y, ay, iy)) {
-          const uint32_t b = (uint32_t)(iy * a.nx + ix);
-          tb[u] = ((b >> shift) << 16) | (b & lmask);
-        }
+      pos[u] = 0u;
+      int ix, iy;
+      if (i < hi && locate((double)px[u], ax, ix) && locate((double)py[u], ay, iy)) {
+        const uint32_t b = (uint32_t)(iy * a.nx + ix);
+        tb[u] = ((b >> shift) << 16) | (b & lmask);
       }
     }
 #pragma unroll
     for (int u = 0; u < PPT; ++u)
-      if (tb[u] != 0xFFFFFFFFu) rank[u] = atomicAdd(cnt + (tb[u] >> 16), 1u);
+      if (tb[u] != 0xFFFFFFFFu) pos[u] = atomicAdd(cnt + (tb[u] >> 16), 1u);
+    // Prefetch the next sub-chunk's coordinates.
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+      const int64_t i = base + S + (int64_t)u * NT + threadIdx.x;
+      px[u] = i < hi ? ld<CT>(a.x, i) : CT(0);
+      py[u] = i < hi ? ld<CT>(a.y, i) : CT(0);
+    }
     __syncthreads();
     uint32_t carry = 0;
-    for (int t0 = 0; t0 < T; t0 += blockDim.x) {
+    for (int t0 = 0; t0 < T; t0 += NT) {
       const int t = t0 + threadIdx.x;
-      const uint32_t c = t < T ? cnt[t] : 0u;
       uint32_t tot;
-      const uint32_t ex = block_exclusive_scan(c, scan_tmp, &tot);
+      const uint32_t ex = block_scan_excl<NT>(t < T ? cnt[t] : 0u, wave_tot, tot);
       if (t < T) off[t] = carry + ex;
       carry += tot;
     }
@@ -227,22 +296,28 @@ __global__ __launch_bounds__(512) void part_scatter_kernel(PartArgs a) {
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
       if (tb[u] == 0xFFFFFFFFu) continue;
-      const uint32_t p = off[tb[u] >> 16] + rank[u];
-      stg_tb[p] = tb[u];
-      const int64_t i = base + (int64_t)u * blockDim.x + threadIdx.x;
-      for (int j = 0; j < a.k; ++j) stg_v[(int64_t)j * S + p] = ld<AT>(a.attr[j], i);
+      pos[u] += off[tb[u] >> 16];
+      stg_tb[pos[u]] = tb[u];
+    }
+    for (int j = 0; j < k; ++j) {
+#pragma unroll
+      for (int u = 0; u < PPT; ++u) {
+        if (tb[u] == 0xFFFFFFFFu) continue;
+        const int64_t i = base + (int64_t)u * NT + threadIdx.x;
+        stg_v[(int64_t)j * S + pos[u]] = ld<AT>(a.attr[j], i);
+      }
     }
     __syncthreads();
     // Consecutive p of one tile go to consecutive record addresses.
-    for (uint32_t p = threadIdx.x; p < nsub; p += blockDim.x) {
+    for (uint32_t p = threadIdx.x; p < nsub; p += NT) {
       const uint32_t v = stg_tb[p];
       const uint32_t t = v >> 16;
       const uint32_t dst = run[t] + (p - off[t]);
       a.rec_bin[dst] = (uint16_t)(v & 0xFFFFu);
-      for (int j = 0; j < a.k; ++j) static_cast<AT*>(a.rec_val[j])[dst] = stg_v[(int64_t)j * S + p];
+      for (int j = 0; j < k; ++j) static_cast<AT*>(a.rec_val[j])[dst] = stg_v[(int64_t)j * S + p];
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < T; t += blockDim.x) {
+    for (int t = threadIdx.x; t < T; t += NT) {
       run[t] += cnt[t];
       cnt[t] = 0u;
     }
@@ -250,14 +325,24 @@ __global__ __launch_bounds__(512) void part_scatter_kernel(PartArgs a) {
   }
 }
 
+template <typename CT, typename AT, int PPT, int NT>
+__global__ __launch_bounds__(NT) void part_scatter_kernel(PartArgs a) {
+  part_scatter_body<CT, AT, PPT, NT>(a, blockIdx.x);
+}
+template <typename CT, typename AT, int PPT, int NT>
+__global__ __launch_bounds__(NT) void part_scatter_batched(const PartArgs* __restrict__ d,
+                                                           const uint32_t* __restrict__ map) {
+  const uint32_t m = map[blockIdx.x];
+  part_scatter_body<CT, AT, PPT, NT>(d[m >> 16], (int)(m & 0xFFFFu));
+}
+
 // ---------------------------------------------------------------------------
 // Per-item tile binning; fused finalize for tiles binned by one item.
 // ---------------------------------------------------------------------------
 template <typename AT, int PREC>
-__global__ __launch_bounds__(1024) void part_bin_kernel(PartArgs a) {
+__device__ __forceinline__ void part_bin_body(const PartArgs& a, int item) {
   using TL = Tile<AT, PREC>;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int item = blockIdx.x;
   if (item >= (int)*a.n_items) return;
   const uint32_t t = a.items[3 * item];
   const uint32_t rb = a.items[3 * item + 1];
@@ -266,7 +351,8 @@ __global__ __launch_bounds__(1024) void part_bin_kernel(PartArgs a) {
   const int64_t b0 = (int64_t)t << shift;
   const int TB = 1 << shift;
   const int nbt = (int)((b0 + TB <= a.nbins) ? TB : a.nbins - b0);
-  TL::init(smem, a.lay, a.k);
+  const int k = a.k;
+  TL::init(smem, a.lay, k);
   __syncthreads();
 
   constexpr int U = 4;
@@ -280,7 +366,7 @@ __global__ __launch_bounds__(1024) void part_bin_kernel(PartArgs a) {
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (lb[u] != 0xFFFFFFFFu) TL::count(smem, (int)lb[u]);
-    for (int j = 0; j < a.k; ++j) {
+    for (int j = 0; j < k; ++j) {
       AT v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -293,38 +379,81 @@ __global__ __launch_bounds__(1024) void part_bin_kernel(PartArgs a) {
     }
   }
   __syncthreads();
-  if (a.tile_items[2 * t + 1] == 1u)
-    TL::emit_all(smem, a.lay, a.out, a.k, nbt, b0);
-  else
-    TL::store_slot(smem, a.lay, a.k, nbt, static_cast<unsigned char*>(a.partial) + (int64_t)item * a.lay.slot_bytes);
+  if (a.tile_items[3 * t + 1] == 1u) {
+    TL::emit_all(smem, a.lay, a.out, k, nbt, b0);
+  } else {
+    const uint32_t slot = a.tile_items[3 * t + 2] + (uint32_t)item - a.tile_items[3 * t];
+    if (slot < (uint32_t)a.max_slots)  // proven bound; the guard only keeps stores in range
+      TL::store_slot(smem, a.lay, k, nbt, static_cast<unsigned char*>(a.partial) + (int64_t)slot * a.lay.slot_bytes);
+  }
+}
+
+template <typename AT, int PREC>
+__global__ __launch_bounds__(1024) void part_bin_kernel(PartArgs a) {
+  part_bin_body<AT, PREC>(a, blockIdx.x);
+}
+template <typename AT, int PREC>
+__global__ __launch_bounds__(1024) void part_bin_batched(const PartArgs* __restrict__ d,
+                                                         const uint32_t* __restrict__ map) {
+  const uint32_t m = map[blockIdx.x];
+  part_bin_body<AT, PREC>(d[m >> 16], (int)(m & 0xFFFFu));
 }
 
 // One block per tile; only split tiles do work.
 template <typename AT, int PREC>
-__global__ __launch_bounds__(256) void part_merge_kernel(PartArgs a) {
-  const int t = blockIdx.x;
-  const uint32_t first = a.tile_items[2 * t];
-  const uint32_t nit = a.tile_items[2 * t + 1];
+__device__ __forceinline__ void part_merge_body(const PartArgs& a, int t) {
+  const uint32_t nit = a.tile_items[3 * t + 1];
   if (nit <= 1) return;
+  const uint32_t slot0 = a.tile_items[3 * t + 2];
+  if (slot0 + nit > (uint32_t)a.max_slots) return;  // cannot happen (proven bound)
   const int shift = a.lay.tile_shift;
   const int64_t b0 = (int64_t)t << shift;
   const int TB = 1 << shift;
   const int nbt = (int)((b0 + TB <= a.nbins) ? TB : a.nbins - b0);
   for (int b = threadIdx.x; b < nbt; b += blockDim.x)
-    Tile<AT, PREC>::merge_emit(static_cast<const unsigned char*>(a.partial), a.lay.slot_bytes, first, nit, a.lay,
+    Tile<AT, PREC>::merge_emit(static_cast<const unsigned char*>(a.partial), a.lay.slot_bytes, slot0, nit, a.lay,
                                a.out, a.k, b, b0 + b);
 }
 
+template <typename AT, int PREC>
+__global__ __launch_bounds__(256) void part_merge_kernel(PartArgs a) {
+  part_merge_body<AT, PREC>(a, blockIdx.x);
+}
+template <typename AT, int PREC>
+__global__ __launch_bounds__(256) void part_merge_batched(const PartArgs* __restrict__ d,
+                                                          const uint32_t* __restrict__ map) {
+  const uint32_t m = map[blockIdx.x];
+  part_merge_body<AT, PREC>(d[m >> 16], (int)(m & 0xFFFFu));
+}
+
 // ---------------------------------------------------------------------------
-// Launch sequence.
+// Launch sequences.
 // ---------------------------------------------------------------------------
-#define BK_LAUNCH(NAME, KERNEL, GRID, BLOCK, LDS, ...)                 \
-  do {                                                                  \
-    if (tm) tm->begin(s);                                               \
-    hipLaunchKernelGGL(KERNEL, dim3(GRID), dim3(BLOCK), LDS, s, __VA_ARGS__); \
-    if (tm) tm->end(NAME, s);                                           \
-    if ((e = hipGetLastError()) != hipSuccess) return e;                \
+#define BK_LAUNCH(NAME, KERNEL, GRID, BLOCK, LDS, ...)                       \
+  do {                                                                        \
+    if ((GRID) > 0) {                                                         \
+      if (tm) tm->begin(s);                                                   \
+      hipLaunchKernelGGL(KERNEL, dim3(GRID), dim3(BLOCK), LDS, s, __VA_ARGS__); \
+      if (tm) tm->end(NAME, s);                                               \
+      if ((e = hipGetLastError()) != hipSuccess) return e;                    \
+    }                                                                         \
   } while (0)
+
+#define BK_SCATTER_SWITCH(KERNEL, GRID, ...)                                                  \
+  switch (c.scatter_threads * 100 + c.ppt) {                                                  \
+    BK_SC(KERNEL, GRID, 256, 4, __VA_ARGS__) BK_SC(KERNEL, GRID, 256, 8, __VA_ARGS__)         \
+    BK_SC(KERNEL, GRID, 256, 16, __VA_ARGS__) BK_SC(KERNEL, GRID, 256, 32, __VA_ARGS__)       \
+    BK_SC(KERNEL, GRID, 512, 4, __VA_ARGS__) BK_SC(KERNEL, GRID, 512, 8, __VA_ARGS__)         \
+    BK_SC(KERNEL, GRID, 512, 16, __VA_ARGS__) BK_SC(KERNEL, GRID, 512, 32, __VA_ARGS__)       \
+    BK_SC(KERNEL, GRID, 1024, 4, __VA_ARGS__) BK_SC(KERNEL, GRID, 1024, 8, __VA_ARGS__)       \
+    BK_SC(KERNEL, GRID, 1024, 16, __VA_ARGS__)                                                \
+    default:                                                                                  \
+      return hipErrorInvalidConfiguration;                                                    \
+  }
+#define BK_SC(KERNEL, GRID, NT, PPT, ...)                                                      \
+  case NT * 100 + PPT:                                                                          \
+    BK_LAUNCH("part_scatter_kernel", (KERNEL<CT, AT, PPT, NT>), GRID, NT, c.scatter_lds, __VA_ARGS__); \
+    break;
 
 template <typename CT, typename AT, int PREC>
 static hipError_t launch_part_t(const PartArgs& a, const PartCfg& c, hipStream_t s, KTimer* tm) {
@@ -336,54 +465,87 @@ static hipError_t launch_part_t(const PartArgs& a, const PartCfg& c, hipStream_t
   BK_LAUNCH("scan_top_kernel", scan_top_kernel, 1, 1024, 0, a.bsum, c.scan_blocks);
   BK_LAUNCH("scan_apply_kernel", scan_apply_kernel, c.scan_blocks, 1024, 0, a.counts, m, c.scan_per, a.bsum);
   BK_LAUNCH("part_items_kernel", part_items_kernel, 1, 1024, 0, a);
-  switch (c.ppt) {
-    case 16: BK_LAUNCH("part_scatter_kernel", (part_scatter_kernel<CT, AT, 16>), a.nwg, 512, c.scatter_lds, a); break;
-    case 8: BK_LAUNCH("part_scatter_kernel", (part_scatter_kernel<CT, AT, 8>), a.nwg, 512, c.scatter_lds, a); break;
-    default: BK_LAUNCH("part_scatter_kernel", (part_scatter_kernel<CT, AT, 4>), a.nwg, 512, c.scatter_lds, a); break;
-  }
+  BK_SCATTER_SWITCH(part_scatter_kernel, a.nwg, a)
   BK_LAUNCH("part_bin_kernel", (part_bin_kernel<AT, PREC>), a.max_items, c.bin_block, c.bin_lds, a);
   BK_LAUNCH("part_merge_kernel", (part_merge_kernel<AT, PREC>), a.ntiles, 256, 0, a);
   return hipSuccess;
 }
-#undef BK_LAUNCH
+
+template <typename CT, typename AT, int PREC>
+static hipError_t launch_part_batch_t(const PartBatch& b, const PartCfg& c, hipStream_t s, KTimer* tm) {
+  hipError_t e;
+  BK_LAUNCH("part_count_kernel", (part_count_batched<CT>), b.n_wg_blocks, 1024, c.count_lds, b.descs,
+            b.map_wg);
+  BK_LAUNCH("scan_block_sums_kernel", scan_block_sums_kernel, c.scan_blocks, 1024, 0, b.counts, b.m, c.scan_per,
+            b.bsum);
+  BK_LAUNCH("scan_top_kernel", scan_top_kernel, 1, 1024, 0, b.bsum, c.scan_blocks);
+  BK_LAUNCH("scan_apply_kernel", scan_apply_kernel, c.scan_blocks, 1024, 0, b.counts, b.m, c.scan_per, b.bsum);
+  BK_LAUNCH("part_items_kernel", part_items_batched, b.nreq, 1024, 0, b.descs);
+  BK_SCATTER_SWITCH(part_scatter_batched, b.n_wg_blocks, b.descs, b.map_wg)
+  BK_LAUNCH("part_bin_kernel", (part_bin_batched<AT, PREC>), b.n_item_blocks, c.bin_block, c.bin_lds, b.descs,
+            b.map_item);
+  BK_LAUNCH("part_merge_kernel", (part_merge_batched<AT, PREC>), b.n_tile_blocks, 256, 0, b.descs, b.map_tile);
+  return hipSuccess;
+}
+#undef BK_SC
+#undef BK_SCATTER_SWITCH
+
+#define BK_PART_DISPATCH(FN, ...)                                              \
+  if (coord_f64) {                                                             \
+    if (attr_f64) return FN<double, double, PREC_F64>(__VA_ARGS__);            \
+    switch (prec) {                                                            \
+      case PREC_PLAIN: return FN<double, float, PREC_PLAIN>(__VA_ARGS__);      \
+      case PREC_COMP: return FN<double, float, PREC_COMP>(__VA_ARGS__);        \
+      default: return FN<double, float, PREC_F64>(__VA_ARGS__);                \
+    }                                                                          \
+  }                                                                            \
+  if (attr_f64) return FN<float, double, PREC_F64>(__VA_ARGS__);               \
+  switch (prec) {                                                              \
+    case PREC_PLAIN: return FN<float, float, PREC_PLAIN>(__VA_ARGS__);         \
+    case PREC_COMP: return FN<float, float, PREC_COMP>(__VA_ARGS__);           \
+    default: return FN<float, float, PREC_F64>(__VA_ARGS__);                   \
+  }
 
 hipError_t launch_partition(const PartArgs& a, bool coord_f64, bool attr_f64, int prec, const PartCfg& c,
                             hipStream_t s, KTimer* tm) {
-  if (coord_f64) {
-    if (attr_f64) return launch_part_t<double, double, PREC_F64>(a, c, s, tm);
-    switch (prec) {
-      case PREC_PLAIN: return launch_part_t<double, float, PREC_PLAIN>(a, c, s, tm);
-      case PREC_COMP: return launch_part_t<double, float, PREC_COMP>(a, c, s, tm);
-      default: return launch_part_t<double, float, PREC_F64>(a, c, s, tm);
-    }
-  }
-  if (attr_f64) return launch_part_t<float, double, PREC_F64>(a, c, s, tm);
-  switch (prec) {
-    case PREC_PLAIN: return launch_part_t<float, float, PREC_PLAIN>(a, c, s, tm);
-    case PREC_COMP: return launch_part_t<float, float, PREC_COMP>(a, c, s, tm);
-    default: return launch_part_t<float, float, PREC_F64>(a, c, s, tm);
-  }
+  BK_PART_DISPATCH(launch_part_t, a, c, s, tm)
 }
+
+hipError_t launch_partition_batch(const PartBatch& b, bool coord_f64, bool attr_f64, int prec, const PartCfg& c,
+                                  hipStream_t s, KTimer* tm) {
+  BK_PART_DISPATCH(launch_part_batch_t, b, c, s, tm)
+}
+#undef BK_PART_DISPATCH
+#undef BK_LAUNCH
 
 hipError_t set_partition_lds_limit(size_t bytes) {
   hipError_t e = hipSuccess;
 #define BK_SETF(...) \
   if (e == hipSuccess) e = set_dynamic_lds_limit(reinterpret_cast<const void*>(&__VA_ARGS__), bytes);
-#define BK_SET_CA(CT, AT)                   \
-  BK_SETF(part_scatter_kernel<CT, AT, 4>)   \
-  BK_SETF(part_scatter_kernel<CT, AT, 8>)   \
-  BK_SETF(part_scatter_kernel<CT, AT, 16>)
+#define BK_SET_NT(K, CT, AT, NT) \
+  BK_SETF(K<CT, AT, 4, NT>) BK_SETF(K<CT, AT, 8, NT>) BK_SETF(K<CT, AT, 16, NT>)
+#define BK_SET_CA(K, CT, AT) \
+  BK_SET_NT(K, CT, AT, 256) BK_SETF(K<CT, AT, 32, 256>) BK_SET_NT(K, CT, AT, 512) BK_SETF(K<CT, AT, 32, 512>) \
+  BK_SET_NT(K, CT, AT, 1024)
+#define BK_SET_TYPES(K) \
+  BK_SET_CA(K, float, float) BK_SET_CA(K, float, double) BK_SET_CA(K, double, float) BK_SET_CA(K, double, double)
   BK_SETF(part_count_kernel<float>)
   BK_SETF(part_count_kernel<double>)
-  BK_SET_CA(float, float)
-  BK_SET_CA(float, double)
-  BK_SET_CA(double, float)
-  BK_SET_CA(double, double)
+  BK_SETF(part_count_batched<float>)
+  BK_SETF(part_count_batched<double>)
+  BK_SET_TYPES(part_scatter_kernel)
+  BK_SET_TYPES(part_scatter_batched)
   BK_SETF(part_bin_kernel<float, PREC_F64>)
   BK_SETF(part_bin_kernel<float, PREC_COMP>)
   BK_SETF(part_bin_kernel<float, PREC_PLAIN>)
   BK_SETF(part_bin_kernel<double, PREC_F64>)
+  BK_SETF(part_bin_batched<float, PREC_F64>)
+  BK_SETF(part_bin_batched<float, PREC_COMP>)
+  BK_SETF(part_bin_batched<float, PREC_PLAIN>)
+  BK_SETF(part_bin_batched<double, PREC_F64>)
+#undef BK_SET_TYPES
 #undef BK_SET_CA
+#undef BK_SET_NT
 #undef BK_SETF
   return e;
 }

@@ -19,7 +19,7 @@ namespace binimpl {
 namespace {
 
 constexpr int kMaxTiles = 4096;         // tile ids are 16-bit in the scatter stage
-constexpr size_t kScatterStatic = 2048;  // static LDS of part_scatter_kernel
+constexpr size_t kScatterStatic = 256;  // static LDS of part_scatter_kernel (wave totals)
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
@@ -128,7 +128,7 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints,
                                ? tile_layout((int)nb, nk, want_sum, want_min, want_max, p->prec, asz, &whole)
                                : SIZE_MAX;
   // Largest power-of-two tile whose accumulators fit LDS.
-  int shift = 15;
+  int shift = hints.tile_shift ? hints.tile_shift : 15;
   bk::TileLayout tl;
   size_t tile_lds = 0;
   for (; shift >= 6; --shift) {
@@ -194,26 +194,34 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints,
     fill_outs(r, nk, &a.out);
     a.lay = tl;
     const int T = (int)ntiles;
-    int64_t nwg = std::min<int64_t>(ceil_div(std::max<int64_t>(n, 1), 32768), cus);
+    int64_t nwg = std::min<int64_t>(ceil_div(std::max<int64_t>(n, 1), 32768), 2 * (int64_t)cus);
     if (hints.grid) nwg = std::min<int64_t>(hints.grid, 65535);
+    if (hints.part_wg) nwg = hints.part_wg;
     nwg = std::max<int64_t>(nwg, 1);
     a.chunk = ceil_div(std::max<int64_t>(n, 1), nwg);
     a.nwg = (int32_t)ceil_div(std::max<int64_t>(n, 1), a.chunk);
     // split length: no split when tiles are balanced, bounded work otherwise
-    const int64_t L = std::max<int64_t>({ceil_div(3 * n, 2 * ntiles), ceil_div(n, 2 * (int64_t)cus), 16384});
+    int64_t L = std::max<int64_t>({ceil_div(3 * n, 2 * ntiles), ceil_div(n, 2 * (int64_t)cus), 16384});
+    if (hints.split_len) L = hints.split_len;
     a.split_len = (uint32_t)std::min<int64_t>(L, 0x7FFFFFFF);
     a.max_items = (int32_t)(ntiles + ceil_div(n, (int64_t)a.split_len));
     // scatter LDS: 3 T counters, S tile/bin words, S * k values
-    int ppt = 16;
+    // 1024-thread scatter workgroups measured fastest on MI355X for both the
+    // 1- and 4-attribute workloads (one workgroup per CU, LDS-bound).
+    const int nt = hints.scatter_threads ? hints.scatter_threads : 1024;
+    // 32 particles per thread need more than the 128 VGPRs a 1024-thread
+    // workgroup allows.
+    int ppt = std::min(hints.scatter_ppt ? hints.scatter_ppt : 16, nt >= 1024 ? 16 : 32);
     size_t sc = 0;
     for (; ppt >= 4; ppt /= 2) {
-      const size_t S = 512 * (size_t)ppt;
+      const size_t S = (size_t)nt * ppt;
       a.stage_val_off = (int32_t)align16(12 * (size_t)T + 4 * S);
       sc = a.stage_val_off + S * nk * asz;
       if (sc + kScatterStatic <= lds_budget) break;
     }
     if (ppt < 4) return fail(BIN_ERR_UNSUPPORTED, "partition scatter stage does not fit LDS");
     c.ppt = ppt;
+    c.scatter_threads = nt;
     c.scatter_lds = std::max<size_t>(sc, 16);
     c.count_lds = 4 * (size_t)T;
     c.bin_lds = tile_lds;
@@ -227,13 +235,13 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints,
     a.inside = a.bsum ? a.bsum + c.scan_blocks : nullptr;
     a.items = static_cast<uint32_t*>(cv.take(12 * (size_t)a.max_items));
     a.n_items = static_cast<uint32_t*>(cv.take(4));
-    a.tile_items = static_cast<uint32_t*>(cv.take(8 * (size_t)T));
+    a.tile_items = static_cast<uint32_t*>(cv.take(12 * (size_t)T));
     a.rec_bin = static_cast<uint16_t*>(cv.take(2 * (size_t)std::max<int64_t>(n, 1)));
     for (int j = 0; j < nk; ++j) a.rec_val[j] = cv.take(asz * (size_t)std::max<int64_t>(n, 1));
-    // Partial slots are needed only for items of split tiles; at most
-    // max_items - ntiles + (number of split tiles) <= 2 * (max_items - ntiles).
-    const int64_t split_items = std::min<int64_t>(a.max_items, 2 * (a.max_items - ntiles));
-    a.partial = split_items > 0 ? cv.take((size_t)a.lay.slot_bytes * a.max_items) : nullptr;
+    // Partial slots only for items of split tiles (ni >= 2 items each):
+    // sum over split tiles of ni <= 2 * sum of (ni - 1) <= 2 * (max_items - ntiles).
+    a.max_slots = (int32_t)std::min<int64_t>(a.max_items, 2 * (a.max_items - ntiles));
+    a.partial = a.max_slots > 0 ? cv.take((size_t)a.lay.slot_bytes * a.max_slots) : nullptr;
     p->scratch_bytes = cv.used;
     p->cfg.grid = a.max_items;
     p->cfg.block = c.bin_block;
@@ -341,9 +349,10 @@ std::string describe(const Prepared& p) {
       break;
     case bk::STRAT_PART:
       snprintf(buf, sizeof buf,
-               "partition tiles=%d tile_bins=%d wg=%d chunk=%lld ppt=%d split=%u max_items=%d "
+               "partition tiles=%d tile_bins=%d wg=%d chunk=%lld threads=%d ppt=%d split=%u max_items=%d "
                "scatter_lds=%zu bin_lds=%zu prec=%s",
-               p.part.ntiles, 1 << p.part.lay.tile_shift, p.part.nwg, (long long)p.part.chunk, p.pcfg.ppt,
+               p.part.ntiles, 1 << p.part.lay.tile_shift, p.part.nwg, (long long)p.part.chunk, p.pcfg.scatter_threads,
+               p.pcfg.ppt,
                p.part.split_len, p.part.max_items, p.pcfg.scatter_lds, p.pcfg.bin_lds, prec);
       break;
     default:
