@@ -200,6 +200,10 @@ int bin_stream_status(void* stream);
 int bin_release_workspace(void);
 /* Library version as "major.minor.patch". */
 const char* bin_version(void);
+/* Copy 'bytes' from device memory to host memory, synchronously (waits for
+ * all work on the device).  A convenience for callers without a HIP runtime
+ * of their own, e.g. to read a server's resident result grids. */
+int bin_copy_to_host(void* host_dst, const void* device_src, size_t bytes);
 
 /* Kernel timing, for measurement only: while enabled, every kernel launch of
  * the library is bracketed by a HIP event pair on its stream.  Enabling

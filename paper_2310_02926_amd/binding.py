@@ -33,7 +33,7 @@ EXPORTS = (
     "bin_graph_destroy", "bin_autotune", "bin_status_string", "bin_last_error_message",
     "bin_stream_status", "bin_release_workspace", "bin_version", "bin_timing_enable", "bin_timing_read",
     "bin_timing_report",
-    "bin_describe_plan", "bin_set_plan_override", "bin_set_tuning", "binsrv_create", "binsrv_submit", "binsrv_wait", "binsrv_release",
+    "bin_describe_plan", "bin_set_plan_override", "bin_set_tuning", "bin_copy_to_host", "binsrv_create", "binsrv_submit", "binsrv_wait", "binsrv_release",
     "binsrv_get_stats", "binsrv_destroy",
 )
 
@@ -114,6 +114,7 @@ def lib() -> ctypes.CDLL:
         "bin_describe_plan": (c_int, [POINTER(Request), c_char_p, c_size_t]),
         "bin_set_plan_override": (c_int, [c_int32, c_int32, c_int32]),
         "bin_set_tuning": (c_int, [c_int32, c_int64]),
+        "bin_copy_to_host": (c_int, [c_void_p, c_void_p, c_size_t]),
         "binsrv_create": (c_int, [POINTER(ServerConfig), POINTER(c_void_p)]),
         "binsrv_submit": (c_int, [c_void_p, POINTER(ServerRequest), POINTER(c_uint64)]),
         "binsrv_wait": (c_int, [c_void_p, c_uint64, c_int64, POINTER(Result)]),
@@ -268,6 +269,130 @@ def request(coords, attrs, n, axes, bounds, nx, ny, ops, out):
     o, ok = output(out.get("count"), out.get("sum"), out.get("min"), out.get("max"), out.get("avg"))
     r = Request(c, a, n, (c_int32 * 2)(*axes), (c_double * 4)(*bounds), nx, ny, ops, o)
     return r, (ck, ak, ok)
+
+
+def request_array(reqs: Sequence[Dict]):
+    """A ctypes array of Request records from dicts with the keyword
+    arguments of bin_particles (coords, attrs, n, axes, bounds, nx, ny, ops,
+    out), plus the objects they reference (keep both alive)."""
+    arr = (Request * max(len(reqs), 1))()
+    keep = []
+    for i, r in enumerate(reqs):
+        rec, k = request(r["coords"], r.get("attrs") or [], r["n"], r.get("axes", (0, 1)),
+                         r.get("bounds", (0.0, 1.0, 0.0, 1.0)), r["nx"], r["ny"], r["ops"], r["out"])
+        arr[i] = rec
+        keep.append(k)
+    return arr, keep
+
+
+def bin_particles_batched(reqs: Sequence[Dict], stream=None) -> None:
+    """Enqueue a batch of independent requests (see request_array)."""
+    arr, keep = request_array(reqs)
+    check(lib().bin_particles_batched(arr, len(reqs), _stream_handle(stream)))
+
+
+def bin_autotune(reqs: Sequence[Dict]) -> None:
+    """Time candidate configurations for these request shapes (overwrites
+    their outputs; synchronises a private stream) and remember the best."""
+    arr, keep = request_array(reqs)
+    check(lib().bin_autotune(arr, len(reqs)))
+
+
+class BinGraph:
+    """A captured batch: create once, launch many times, destroy."""
+
+    def __init__(self, reqs: Sequence[Dict]):
+        arr, self._keep = request_array(reqs)
+        h = c_void_p()
+        check(lib().bin_graph_create(arr, len(reqs), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None) -> None:
+        check(lib().bin_graph_launch(self._h, _stream_handle(stream)))
+
+    def destroy(self) -> None:
+        if self._h:
+            check(lib().bin_graph_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def copy_to_host(dev_ptr: int, nbytes: int, dtype, shape):
+    """Read nbytes of device memory into a new numpy array."""
+    import numpy as np
+    a = np.empty(shape, dtype=dtype)
+    assert a.nbytes == nbytes
+    check(lib().bin_copy_to_host(a.ctypes.data, dev_ptr, nbytes))
+    return a
+
+
+class Server:
+    """Continuous-batching request server (binsrv_*).  Column tensors handed
+    to submit() are kept referenced until the request is released."""
+
+    def __init__(self, budget_bytes: int = 64 << 30, n_slots: int = 2, max_batch: int = 64, device: int = 0):
+        self._h = c_void_p()
+        cfg = ServerConfig(budget_bytes, n_slots, max_batch, device, 0)
+        check(lib().binsrv_create(ctypes.byref(cfg), ctypes.byref(self._h)))
+        self._keep = {}
+
+    def submit(self, coords, attrs, n, axes, bounds, nx, ny, ops) -> int:
+        c, ck = columns(coords)
+        a, ak = columns(attrs) if attrs else (Columns(None, 0, BIN_F32), None)
+        req = ServerRequest(c, a, n, (c_int32 * 2)(*axes), (c_double * 4)(*bounds), nx, ny, ops)
+        t = c_uint64()
+        check(lib().binsrv_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
+        self._keep[t.value] = (coords, attrs, ck, ak, (nx, ny, ops, len(attrs or [])))
+        return int(t.value)
+
+    def wait(self, ticket: int, timeout_s: Optional[float] = None) -> Result:
+        res = Result()
+        ns = -1 if timeout_s is None else int(timeout_s * 1e9)
+        check(lib().binsrv_wait(self._h, ticket, ns, ctypes.byref(res)))
+        return res
+
+    def fetch(self, ticket: int, res: Result) -> Dict:
+        """Copy a finished request's grids to host numpy arrays."""
+        import numpy as np
+        coords, attrs, _, _, (nx, ny, ops, k) = self._keep[ticket]
+        af64 = k > 0 and str(attrs[0].dtype).endswith("float64")
+        sa = np.float32 if (not af64 and ops & PREC_PLAIN) else np.float64
+        mm = np.float64 if af64 else np.float32
+        nb = nx * ny
+        out = {}
+        if ops & COUNT:
+            out["count"] = copy_to_host(res.count, 4 * nb, np.uint32, (ny, nx)).astype(np.int64)
+        for key, bit, dt, arr in (("sum", SUM, sa, res.sum), ("min", MIN, mm, res.min), ("max", MAX, mm, res.max),
+                                  ("avg", AVG, sa, res.avg)):
+            if ops & bit:
+                out[key] = [copy_to_host(arr[j], np.dtype(dt).itemsize * nb, dt, (ny, nx)) for j in range(k)]
+        return out
+
+    def release(self, ticket: int) -> None:
+        check(lib().binsrv_release(self._h, ticket))
+        self._keep.pop(ticket, None)
+
+    def stats(self) -> Dict:
+        s = ServerStats()
+        check(lib().binsrv_get_stats(self._h, ctypes.byref(s)))
+        return {n: int(getattr(s, n)) for n, _ in ServerStats._fields_}
+
+    def destroy(self) -> None:
+        if self._h:
+            check(lib().binsrv_destroy(self._h))
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 def bin_describe_plan(req: Request) -> str:

@@ -187,6 +187,16 @@ int bin_release_workspace(void) {
 
 const char* bin_version(void) { return "0.1.0"; }
 
+int bin_copy_to_host(void* host_dst, const void* device_src, size_t bytes) {
+  clear_error();
+  if (bytes == 0) return BIN_OK;
+  if (!host_dst || !device_src) return fail(BIN_ERR_INVALID_ARG, "NULL copy pointer");
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(host_dst, device_src, bytes, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(device to host)");
+  return BIN_OK;
+}
+
 int bin_timing_enable(int on) { return timing_enable(on); }
 
 int bin_timing_read(int64_t* launches, double* total_ms) {

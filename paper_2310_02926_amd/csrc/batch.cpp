@@ -1,0 +1,481 @@
+// Batched binning: many independent requests of uneven size run as a few
+// table-driven launches (one per kernel stage and request group) instead of
+// a launch sequence per request.  Also the HIP-graph capture of a batch.
+//
+// Requests are planned one by one, then grouped by (strategy, coordinate
+// type, attribute type, precision).  A partition group shares one
+// concatenated count matrix (one global scan gives every request its record
+// offsets) and one concatenated record array; an LDS group shares nothing
+// but the launches.  Requests that need the global-atomic strategy run one
+// by one.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.h"
+
+namespace binimpl {
+
+namespace {
+
+size_t al256(size_t v) { return (v + 255) & ~size_t(255); }
+size_t al16(size_t v) { return (v + 15) & ~size_t(15); }
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+struct PartGroup {
+  bool cf64 = false, af64 = false;
+  int prec = 0;
+  std::vector<int> idx;              // request indices
+  std::vector<bk::PartArgs> args;    // patched records
+  bk::PartCfg cfg{};
+  bk::PartBatch b{};
+  size_t desc_off = 0, map_wg_off = 0, map_item_off = 0, map_tile_off = 0;
+  std::vector<uint32_t> map_wg, map_item, map_tile;
+};
+
+struct LdsGroup {
+  bool cf64 = false, af64 = false;
+  int prec = 0;
+  std::vector<int> idx;
+  std::vector<bk::LdsArgs> args;
+  size_t lds_bytes = 0;
+  int block = 512;
+  bk::LdsBatch b{};
+  size_t desc_off = 0, map_slot_off = 0, map_merge_off = 0;
+  std::vector<uint32_t> map_slot, map_merge;
+};
+
+}  // namespace
+
+struct BatchPlan {
+  std::vector<Prepared> preps;
+  std::vector<PartGroup> part;
+  std::vector<LdsGroup> lds;
+  std::vector<int> global_reqs;
+  size_t scratch_bytes = 0;  // device scratch, tables included
+  size_t tables_off = 0, tables_bytes = 0;
+  std::vector<unsigned char> tables;  // host image of the device tables
+};
+
+namespace {
+
+// Pass 1 (base == nullptr) sizes everything; pass 2 lays out pointers.
+int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const PlanHints& hints,
+               unsigned char* base, BatchPlan* bp) {
+  bp->preps.assign(nreq, Prepared{});
+  bp->part.clear();
+  bp->lds.clear();
+  bp->global_reqs.clear();
+  std::map<std::tuple<int, int, int, int>, int> gmap;
+  for (int i = 0; i < nreq; ++i) {
+    Prepared& p = bp->preps[i];
+    int st = prepare(reqs[i], dev, hints, nullptr, &p);
+    if (st) return st;
+    const int strat = p.cfg.strategy;
+    if (strat == bk::STRAT_GLOBAL) {
+      bp->global_reqs.push_back(i);
+      continue;
+    }
+    auto key = std::make_tuple(strat, (int)p.coord_f64, (int)p.attr_f64, p.prec);
+    auto it = gmap.find(key);
+    if (it == gmap.end()) {
+      if (strat == bk::STRAT_PART) {
+        PartGroup g;
+        g.cf64 = p.coord_f64;
+        g.af64 = p.attr_f64;
+        g.prec = p.prec;
+        bp->part.push_back(g);
+        it = gmap.emplace(key, (int)bp->part.size() - 1).first;
+      } else {
+        LdsGroup g;
+        g.cf64 = p.coord_f64;
+        g.af64 = p.attr_f64;
+        g.prec = p.prec;
+        bp->lds.push_back(g);
+        it = gmap.emplace(key, (int)bp->lds.size() - 1).first;
+      }
+    }
+    if (strat == bk::STRAT_PART) bp->part[it->second].idx.push_back(i);
+    else bp->lds[it->second].idx.push_back(i);
+  }
+
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    unsigned char* p = base ? base + off : nullptr;
+    off += al256(std::max<size_t>(bytes, 1));
+    return p;
+  };
+  // --- partition groups
+  for (auto& g : bp->part) {
+    const int R = (int)g.idx.size();
+    if (R > 65535) return fail(BIN_ERR_UNSUPPORTED, "a batch group holds at most 65535 requests");
+    g.args.resize(R);
+    // One scatter shape for the whole group: the smallest PPT any request
+    // needs, staged values sized for the largest request.
+    int ppt = 32, nt = 1024;
+    size_t count_lds = 16, bin_lds = 16;
+    int bin_block = 256;
+    int64_t M = 0, total_n = 0, total_items = 0, total_tiles = 0;
+    int kmax = 0;
+    size_t asz = g.af64 ? 8 : 4;
+    for (int r = 0; r < R; ++r) {
+      const Prepared& p = bp->preps[g.idx[r]];
+      ppt = std::min(ppt, p.pcfg.ppt);
+      nt = std::min(nt, p.pcfg.scatter_threads);
+      count_lds = std::max(count_lds, p.pcfg.count_lds);
+      bin_lds = std::max(bin_lds, p.pcfg.bin_lds);
+      bin_block = std::max(bin_block, p.pcfg.bin_block);
+      M += (int64_t)p.part.ntiles * p.part.nwg;
+      total_n += std::max<int64_t>(p.part.n, 1);
+      total_items += p.part.max_items;
+      total_tiles += p.part.ntiles;
+      kmax = std::max(kmax, p.part.k);
+    }
+    const size_t S = (size_t)nt * ppt;
+    size_t scatter_lds = 16;
+    for (int r = 0; r < R; ++r) {
+      const Prepared& p = bp->preps[g.idx[r]];
+      const size_t sv = al16(12 * (size_t)p.part.ntiles + 4 * S);
+      scatter_lds = std::max(scatter_lds, sv + S * p.part.k * asz);
+    }
+    g.cfg.ppt = ppt;
+    g.cfg.scatter_threads = nt;
+    g.cfg.scatter_lds = scatter_lds;
+    g.cfg.count_lds = count_lds;
+    g.cfg.bin_lds = bin_lds;
+    g.cfg.bin_block = bin_block;
+    g.cfg.scan_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, cdiv(M, 4096)));
+    g.cfg.scan_per = cdiv(std::max<int64_t>(M, 1), g.cfg.scan_blocks);
+    if (scatter_lds + 256 > dev.lds_per_block)
+      return fail(BIN_ERR_UNSUPPORTED, "batched scatter stage does not fit LDS");
+    // shared scratch
+    uint32_t* counts = reinterpret_cast<uint32_t*>(take(4 * (size_t)std::max<int64_t>(M, 1)));
+    uint32_t* bsum = reinterpret_cast<uint32_t*>(take(4 * ((size_t)g.cfg.scan_blocks + 1)));
+    uint32_t* items = reinterpret_cast<uint32_t*>(take(12 * (size_t)total_items));
+    uint32_t* n_items = reinterpret_cast<uint32_t*>(take(4 * (size_t)R));
+    uint32_t* tile_items = reinterpret_cast<uint32_t*>(take(12 * (size_t)total_tiles));
+    uint16_t* rec_bin = reinterpret_cast<uint16_t*>(take(2 * (size_t)total_n));
+    void* rec_val[bk::kMaxAttrs] = {};
+    for (int j = 0; j < kmax; ++j) rec_val[j] = take(asz * (size_t)total_n);
+    int64_t cb = 0, ib = 0, tb = 0;
+    for (int r = 0; r < R; ++r) {
+      bk::PartArgs a = bp->preps[g.idx[r]].part;
+      const int64_t m = (int64_t)a.ntiles * a.nwg;
+      a.counts = counts ? counts + cb : nullptr;
+      a.bsum = bsum;
+      a.inside = counts ? (r + 1 < R ? counts + cb + m : bsum + g.cfg.scan_blocks) : nullptr;
+      a.items = items ? items + 3 * ib : nullptr;
+      a.n_items = n_items ? n_items + r : nullptr;
+      a.tile_items = tile_items ? tile_items + 3 * tb : nullptr;
+      a.rec_bin = rec_bin;
+      for (int j = 0; j < a.k; ++j) a.rec_val[j] = rec_val[j];
+      a.stage_val_off = (int32_t)al16(12 * (size_t)a.ntiles + 4 * S);
+      a.partial = a.max_slots > 0 ? take((size_t)a.lay.slot_bytes * a.max_slots) : nullptr;
+      g.args[r] = a;
+      cb += m;
+      ib += a.max_items;
+      tb += a.ntiles;
+    }
+    g.b.counts = counts;
+    g.b.bsum = bsum;
+    g.b.m = M;
+    g.b.nreq = R;
+    g.map_wg.clear();
+    g.map_item.clear();
+    g.map_tile.clear();
+    for (int r = 0; r < R; ++r) {
+      const bk::PartArgs& a = g.args[r];
+      for (int w = 0; w < a.nwg; ++w) g.map_wg.push_back(((uint32_t)r << 16) | (uint32_t)w);
+      for (int i = 0; i < a.max_items; ++i) g.map_item.push_back(((uint32_t)r << 16) | (uint32_t)i);
+      for (int t = 0; t < a.ntiles; ++t) g.map_tile.push_back(((uint32_t)r << 16) | (uint32_t)t);
+      if (a.nwg > 65536 || a.max_items > 65536 || a.ntiles > 65536)
+        return fail(BIN_ERR_UNSUPPORTED, "request too large for a batch block map");
+    }
+    g.b.n_wg_blocks = (int32_t)g.map_wg.size();
+    g.b.n_item_blocks = (int32_t)g.map_item.size();
+    g.b.n_tile_blocks = (int32_t)g.map_tile.size();
+  }
+  // --- LDS groups
+  for (auto& g : bp->lds) {
+    const int R = (int)g.idx.size();
+    if (R > 65535) return fail(BIN_ERR_UNSUPPORTED, "a batch group holds at most 65535 requests");
+    g.args.resize(R);
+    g.lds_bytes = 16;
+    g.block = 512;
+    g.map_slot.clear();
+    g.map_merge.clear();
+    for (int r = 0; r < R; ++r) {
+      const Prepared& p = bp->preps[g.idx[r]];
+      bk::LdsArgs a = p.lds;
+      a.partial = a.nslots > 1 ? take((size_t)a.lay.slot_bytes * a.nslots) : nullptr;
+      g.args[r] = a;
+      g.lds_bytes = std::max(g.lds_bytes, p.cfg.lds_bytes);
+      g.block = std::max(g.block, p.cfg.block);
+      for (int s = 0; s < a.nslots; ++s) g.map_slot.push_back(((uint32_t)r << 16) | (uint32_t)s);
+      if (a.nslots > 1)
+        for (int64_t c = 0; c < cdiv(a.nbins, 256); ++c) g.map_merge.push_back(((uint32_t)r << 16) | (uint32_t)c);
+    }
+    g.b.nreq = R;
+    g.b.n_slot_blocks = (int32_t)g.map_slot.size();
+    g.b.n_merge_blocks = (int32_t)g.map_merge.size();
+  }
+  // --- tables: descriptors and maps, one upload
+  size_t t = 0;
+  auto tab = [&](size_t bytes) {
+    const size_t o = t;
+    t += al256(std::max<size_t>(bytes, 1));
+    return o;
+  };
+  for (auto& g : bp->part) {
+    g.desc_off = tab(sizeof(bk::PartArgs) * g.args.size());
+    g.map_wg_off = tab(4 * g.map_wg.size());
+    g.map_item_off = tab(4 * g.map_item.size());
+    g.map_tile_off = tab(4 * g.map_tile.size());
+  }
+  for (auto& g : bp->lds) {
+    g.desc_off = tab(sizeof(bk::LdsArgs) * g.args.size());
+    g.map_slot_off = tab(4 * g.map_slot.size());
+    g.map_merge_off = tab(4 * g.map_merge.size());
+  }
+  bp->tables_bytes = t;
+  bp->tables_off = off;
+  unsigned char* tdev = take(t);
+  bp->scratch_bytes = off;
+  if (!base) return BIN_OK;
+  bp->tables.assign(t, 0);
+  unsigned char* h = bp->tables.data();
+  for (auto& g : bp->part) {
+    std::memcpy(h + g.desc_off, g.args.data(), sizeof(bk::PartArgs) * g.args.size());
+    std::memcpy(h + g.map_wg_off, g.map_wg.data(), 4 * g.map_wg.size());
+    std::memcpy(h + g.map_item_off, g.map_item.data(), 4 * g.map_item.size());
+    std::memcpy(h + g.map_tile_off, g.map_tile.data(), 4 * g.map_tile.size());
+    g.b.descs = reinterpret_cast<const bk::PartArgs*>(tdev + g.desc_off);
+    g.b.map_wg = reinterpret_cast<const uint32_t*>(tdev + g.map_wg_off);
+    g.b.map_item = reinterpret_cast<const uint32_t*>(tdev + g.map_item_off);
+    g.b.map_tile = reinterpret_cast<const uint32_t*>(tdev + g.map_tile_off);
+  }
+  for (auto& g : bp->lds) {
+    std::memcpy(h + g.desc_off, g.args.data(), sizeof(bk::LdsArgs) * g.args.size());
+    std::memcpy(h + g.map_slot_off, g.map_slot.data(), 4 * g.map_slot.size());
+    std::memcpy(h + g.map_merge_off, g.map_merge.data(), 4 * g.map_merge.size());
+    g.b.descs = reinterpret_cast<const bk::LdsArgs*>(tdev + g.desc_off);
+    g.b.map_slot = reinterpret_cast<const uint32_t*>(tdev + g.map_slot_off);
+    g.b.map_merge = reinterpret_cast<const uint32_t*>(tdev + g.map_merge_off);
+  }
+  return BIN_OK;
+}
+
+// Kernel launches of a laid-out batch (tables already on the device).
+int launch_batch(const BatchPlan& bp, hipStream_t s, bk::KTimer* tm) {
+  for (const auto& g : bp.part) {
+    hipError_t e = bk::launch_partition_batch(g.b, g.cf64, g.af64, g.prec, g.cfg, s, tm);
+    if (e != hipSuccess) return hip_fail(e, "launch batched partition kernels");
+  }
+  for (const auto& g : bp.lds) {
+    hipError_t e = bk::launch_lds_batch(g.b, g.cf64, g.af64, g.prec, g.lds_bytes, g.block, s, tm);
+    if (e != hipSuccess) return hip_fail(e, "launch batched LDS kernels");
+  }
+  return BIN_OK;
+}
+
+int validate_requests(const bin_request* reqs, int nreq) {
+  if (!reqs && nreq > 0) return fail(BIN_ERR_INVALID_ARG, "reqs is NULL");
+  if (nreq < 0) return fail(BIN_ERR_INVALID_ARG, "nreq < 0");
+  for (int i = 0; i < nreq; ++i) {
+    const bin_request& r = reqs[i];
+    int st = validate(&r.coords, &r.attrs, r.n, r.axes, r.bounds, r.nx, r.ny, r.ops, &r.out, false);
+    if (st) {
+      std::string msg = last_error();
+      return fail(st, "request %d: %s", i, msg.c_str());
+    }
+  }
+  return BIN_OK;
+}
+
+// Pinned staging for table uploads, one buffer per stream; an event marks
+// when the previous upload from it has finished.
+struct Stage {
+  void* host = nullptr;
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;
+};
+std::mutex g_stage_mu;
+std::unordered_map<void*, Stage> g_stages;
+
+int upload_tables(const BatchPlan& bp, unsigned char* scratch, hipStream_t s) {
+  if (bp.tables_bytes == 0) return BIN_OK;
+  std::lock_guard<std::mutex> lk(g_stage_mu);
+  Stage& st = g_stages[(void*)s];
+  hipError_t e;
+  if (st.done) {
+    e = hipEventSynchronize(st.done);  // the buffer may still feed the last upload
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize(staging)");
+  } else {
+    e = hipEventCreateWithFlags(&st.done, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate(staging)");
+  }
+  if (st.bytes < bp.tables_bytes) {
+    if (st.host) (void)hipHostFree(st.host);
+    st.host = nullptr;
+    st.bytes = 0;
+    e = hipHostMalloc(&st.host, bp.tables_bytes, hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(e, "hipHostMalloc(staging)");
+    st.bytes = bp.tables_bytes;
+  }
+  std::memcpy(st.host, bp.tables.data(), bp.tables_bytes);
+  e = hipMemcpyAsync(scratch + bp.tables_off, st.host, bp.tables_bytes, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(batch tables)");
+  e = hipEventRecord(st.done, s);
+  if (e != hipSuccess) return hip_fail(e, "hipEventRecord(staging)");
+  return BIN_OK;
+}
+
+}  // namespace
+
+int run_batch(const bin_request* reqs, int nreq, hipStream_t s, const PlanHints& hints) {
+  int st = validate_requests(reqs, nreq);
+  if (st) return st;
+  if (nreq == 0) return BIN_OK;
+  DeviceInfo dev;
+  st = device_info(&dev);
+  if (st) return st;
+  BatchPlan bp;
+  st = plan_batch(reqs, nreq, dev, hints, nullptr, &bp);
+  if (st) return st;
+  void* scratch = nullptr;
+  st = scratch_get(dev.device, s, bp.scratch_bytes, &scratch);
+  if (st) return st;
+  st = plan_batch(reqs, nreq, dev, hints, static_cast<unsigned char*>(scratch), &bp);
+  if (st) return st;
+  st = upload_tables(bp, static_cast<unsigned char*>(scratch), s);
+  if (st) return st;
+  bk::KTimer* tm = timing_timer();
+  st = launch_batch(bp, s, tm);
+  if (st) return st;
+  for (int i : bp.global_reqs) {
+    st = run_request(reqs[i], s, hints);
+    if (st) return st;
+  }
+  return BIN_OK;
+}
+
+size_t batch_scratch_bytes(const bin_request* reqs, int nreq, int* status) {
+  *status = validate_requests(reqs, nreq);
+  if (*status || nreq == 0) return 0;
+  DeviceInfo dev;
+  *status = device_info(&dev);
+  if (*status) return 0;
+  BatchPlan bp;
+  *status = plan_batch(reqs, nreq, dev, thread_hints(), nullptr, &bp);
+  if (*status) return 0;
+  size_t extra = 0;  // requests on the global strategy use their own scratch
+  for (int i : bp.global_reqs) extra += al256(bp.preps[i].scratch_bytes);
+  return bp.scratch_bytes + extra;
+}
+
+}  // namespace binimpl
+
+// ---------------------------------------------------------------------------
+// Graphs.
+// ---------------------------------------------------------------------------
+struct bin_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* scratch = nullptr;
+  int device = 0;
+};
+
+using namespace binimpl;
+
+extern "C" {
+
+int bin_particles_batched(const bin_request* reqs, int32_t nreq, void* stream) {
+  clear_error();
+  return run_batch(reqs, nreq, static_cast<hipStream_t>(stream), thread_hints());
+}
+
+int bin_graph_create(const bin_request* reqs, int32_t nreq, bin_graph** out) {
+  clear_error();
+  if (!out) return fail(BIN_ERR_INVALID_ARG, "graph is NULL");
+  *out = nullptr;
+  int st = validate_requests(reqs, nreq);
+  if (st) return st;
+  if (nreq == 0) return fail(BIN_ERR_INVALID_ARG, "a graph needs at least one request");
+  DeviceInfo dev;
+  st = device_info(&dev);
+  if (st) return st;
+  BatchPlan bp;
+  const PlanHints& hints = thread_hints();
+  st = plan_batch(reqs, nreq, dev, hints, nullptr, &bp);
+  if (st) return st;
+  if (!bp.global_reqs.empty())
+    return fail(BIN_ERR_UNSUPPORTED, "graphs do not take requests that need the global-atomic strategy");
+  bin_graph* g = new bin_graph;
+  g->device = dev.device;
+  hipError_t e = hipMalloc(&g->scratch, std::max<size_t>(bp.scratch_bytes, 256));
+  if (e != hipSuccess) {
+    delete g;
+    return hip_fail(e, "hipMalloc(graph scratch)");
+  }
+  st = plan_batch(reqs, nreq, dev, hints, static_cast<unsigned char*>(g->scratch), &bp);
+  if (st == BIN_OK && bp.tables_bytes) {
+    e = hipMemcpy(static_cast<unsigned char*>(g->scratch) + bp.tables_off, bp.tables.data(), bp.tables_bytes,
+                  hipMemcpyHostToDevice);
+    if (e != hipSuccess) st = hip_fail(e, "hipMemcpy(graph tables)");
+  }
+  hipStream_t cs = nullptr;
+  if (st == BIN_OK) {
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) st = hip_fail(e, "hipStreamCreate(capture)");
+  }
+  if (st == BIN_OK) {
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) st = hip_fail(e, "hipStreamBeginCapture");
+  }
+  if (st == BIN_OK) {
+    const int lst = launch_batch(bp, cs, nullptr);
+    e = hipStreamEndCapture(cs, &g->graph);
+    if (lst) st = lst;
+    else if (e != hipSuccess) st = hip_fail(e, "hipStreamEndCapture");
+  }
+  if (st == BIN_OK) {
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) st = hip_fail(e, "hipGraphInstantiate");
+  }
+  if (cs) (void)hipStreamDestroy(cs);
+  if (st) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    (void)hipFree(g->scratch);
+    delete g;
+    return st;
+  }
+  *out = g;
+  return BIN_OK;
+}
+
+int bin_graph_launch(bin_graph* g, void* stream) {
+  clear_error();
+  if (!g || !g->exec) return fail(BIN_ERR_INVALID_ARG, "graph is NULL");
+  hipError_t e = hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return BIN_OK;
+}
+
+int bin_graph_destroy(bin_graph* g) {
+  clear_error();
+  if (!g) return BIN_OK;
+  hipError_t e = hipDeviceSynchronize();  // no replay may still use the scratch
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->scratch) (void)hipFree(g->scratch);
+  delete g;
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  return BIN_OK;
+}
+
+}  // extern "C"

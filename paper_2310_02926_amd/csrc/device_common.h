@@ -102,6 +102,37 @@ __device__ __forceinline__ T ld(const void* p, int64_t i) {
   return __builtin_nontemporal_load(static_cast<const T*>(p) + i);
 }
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Elements i .. i+3 of a column into out[0..3], zero past hi.  With vec
+// (column 16-byte aligned, i a multiple of 4) a full group is read with
+// 16-byte loads: HBM streams at full rate only with wide loads.
+template <typename T>
+__device__ __forceinline__ void ld4(const void* p, int64_t i, int64_t hi, bool vec, T* out) {
+  if (vec && i + 4 <= hi) {
+    if constexpr (sizeof(T) == 4) {
+      const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(static_cast<const T*>(p) + i));
+      out[0] = v.x;
+      out[1] = v.y;
+      out[2] = v.z;
+      out[3] = v.w;
+    } else {
+      const f64x2* q = reinterpret_cast<const f64x2*>(static_cast<const T*>(p) + i);
+      const f64x2 a = __builtin_nontemporal_load(q);
+      const f64x2 b = __builtin_nontemporal_load(q + 1);
+      out[0] = a.x;
+      out[1] = a.y;
+      out[2] = b.x;
+      out[3] = b.y;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out[e] = i + e < hi ? ld<T>(p, i + e) : T(0);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // LDS tile accumulators (layout in TileLayout).  All functions are called by
 // every thread of the workgroup; tb = bins of the tile held in LDS.

@@ -75,6 +75,10 @@ struct Prepared {
 
 const PlanHints& thread_hints();
 int resolve_precision(uint32_t ops, bool attr_f64);
+// The caller's explicit hints, else the autotuned entry for the request's
+// shape class, else defaults.
+PlanHints effective_hints(const bin_request& r, const PlanHints& explicit_hints);
+int autotune(const bin_request* reqs, int count);
 
 // Plan a validated request and lay out its scratch at 'scratch' (may be null
 // when only sizing: then pointers into scratch are left null and
@@ -88,6 +92,9 @@ std::string describe(const Prepared& p);
 // Whole requests.
 int run_request(const bin_request& r, hipStream_t s, const PlanHints& hints);
 int run_auto_bounds(const bin_request& r, hipStream_t s);
+int run_batch(const bin_request* reqs, int nreq, hipStream_t s, const PlanHints& hints);
+// Device scratch a batch needs (0 and *status set on a bad batch).
+size_t batch_scratch_bytes(const bin_request* reqs, int nreq, int* status);
 
 }  // namespace binimpl
 

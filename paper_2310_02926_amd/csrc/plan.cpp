@@ -95,7 +95,8 @@ int resolve_precision(uint32_t ops, bool attr_f64) {
   return bk::PREC_F64;
 }
 
-int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints, void* scratch, Prepared* p) {
+int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints_in, void* scratch, Prepared* p) {
+  const PlanHints hints = effective_hints(r, hints_in);
   std::memset(&p->bin, 0, sizeof p->bin);
   std::memset(&p->init, 0, sizeof p->init);
   std::memset(&p->fin, 0, sizeof p->fin);
@@ -208,18 +209,28 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints,
     // scatter LDS: 3 T counters, S tile/bin words, S * k values
     // 1024-thread scatter workgroups measured fastest on MI355X for both the
     // 1- and 4-attribute workloads (one workgroup per CU, LDS-bound).
-    const int nt = hints.scatter_threads ? hints.scatter_threads : 1024;
-    // 32 particles per thread need more than the 128 VGPRs a 1024-thread
-    // workgroup allows.
-    int ppt = std::min(hints.scatter_ppt ? hints.scatter_ppt : 16, nt >= 1024 ? 16 : 32);
+    // Largest scatter stage that fits LDS: 1024 threads first (fastest on
+    // MI355X), fewer particles per thread, then fewer threads (many
+    // attributes).  32 particles per thread need more than the 128 VGPRs a
+    // 1024-thread workgroup allows.
+    int nt = 0, ppt = 0;
     size_t sc = 0;
-    for (; ppt >= 4; ppt /= 2) {
-      const size_t S = (size_t)nt * ppt;
-      a.stage_val_off = (int32_t)align16(12 * (size_t)T + 4 * S);
-      sc = a.stage_val_off + S * nk * asz;
-      if (sc + kScatterStatic <= lds_budget) break;
+    for (int tnt = hints.scatter_threads ? hints.scatter_threads : 1024; tnt >= 256 && !ppt; tnt /= 2) {
+      for (int tp = std::min(hints.scatter_ppt ? hints.scatter_ppt : 16, tnt >= 1024 ? 16 : 32); tp >= 4; tp /= 2) {
+        const size_t S = (size_t)tnt * tp;
+        const int32_t svo = (int32_t)align16(12 * (size_t)T + 4 * S);
+        const size_t need = svo + S * nk * asz;
+        if (need + kScatterStatic <= lds_budget) {
+          nt = tnt;
+          ppt = tp;
+          a.stage_val_off = svo;
+          sc = need;
+          break;
+        }
+      }
+      if (hints.scatter_threads) break;
     }
-    if (ppt < 4) return fail(BIN_ERR_UNSUPPORTED, "partition scatter stage does not fit LDS");
+    if (!ppt) return fail(BIN_ERR_UNSUPPORTED, "partition scatter stage does not fit LDS");
     c.ppt = ppt;
     c.scatter_threads = nt;
     c.scatter_lds = std::max<size_t>(sc, 16);

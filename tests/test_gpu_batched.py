@@ -1,0 +1,199 @@
+"""Batched launches and HIP graphs: each request's result equals the oracle
+and its own plain bin_particles result (alone vs in the mix)."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2310_02926_amd import synth
+from tests import gpu_check as G
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _case(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _to_np(out):
+    res = {}
+    if "count" in out:
+        res["count"] = out["count"].cpu().numpy().view(np.uint32).astype(np.int64)
+    for key in ("sum", "min", "max", "avg"):
+        if key in out:
+            res[key] = [t.cpu().numpy() for t in out[key]]
+    return res
+
+
+def _mix(count, seed, n_hi=300_000, sides=(32, 64, 128, 256, 512, 1024)):
+    specs = synth.batch_specs(count, seed=seed, n_lo=1e3, n_hi=n_hi, sides=sides)
+    wss = [synth.instance(s) for s in specs]
+    return specs, wss
+
+
+def _requests(wss, flags=0):
+    from paper_2310_02926_amd import binding as B
+    reqs, dev = [], torch.device("cuda")
+    for ws in wss:
+        coords, attrs = G.to_device(ws)
+        ops = ws.ops | flags
+        out = B.alloc_outputs(attrs, ws.nx, ws.ny, ops, dev)
+        reqs.append(dict(coords=coords, attrs=attrs, n=ws.n, axes=ws.axes, bounds=ws.bounds, nx=ws.nx, ny=ws.ny,
+                         ops=ops, out=out))
+    return reqs
+
+
+def _check_vs_oracle(reqs, wss, what):
+    for i, (r, ws) in enumerate(zip(reqs, wss)):
+        G.assert_parity(_to_np(r["out"]), G.oracle(ws), ws.ops, what=f"{what} request {i} (n={ws.n}, {ws.nx}^2)")
+
+
+def _same_as_alone(reqs, wss, what):
+    """Each batched result equals the plain call's: count/min/max exactly,
+    sums/avgs within rounding of binary64 accumulation order."""
+    from paper_2310_02926_amd import binding as B
+    for i, (r, ws) in enumerate(zip(reqs, wss)):
+        out = B.alloc_outputs(r["attrs"], ws.nx, ws.ny, r["ops"], r["coords"][0].device)
+        B.bin_particles(r["coords"], r["attrs"], r["n"], r["axes"], r["bounds"], ws.nx, ws.ny, r["ops"], out)
+        torch.cuda.synchronize()
+        a, b = _to_np(out), _to_np(r["out"])
+        if "count" in a:
+            assert np.array_equal(a["count"], b["count"]), (what, i)
+        for key in ("min", "max"):
+            for x, y in zip(a.get(key, []), b.get(key, [])):
+                assert np.array_equal(x.view(np.int32), y.view(np.int32)), (what, i, key)
+        for key in ("sum", "avg"):
+            for x, y in zip(a.get(key, []), b.get(key, [])):
+                assert np.allclose(x, y, rtol=1e-12, atol=1e-12, equal_nan=True), (what, i, key)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_batched_mix_matches_oracle_and_plain(seed):
+    from paper_2310_02926_amd import binding as B
+    _case(f"batched mix of 40 requests seed={seed}")
+    specs, wss = _mix(40, seed)
+    reqs = _requests(wss)
+    B.bin_particles_batched(reqs)
+    torch.cuda.synchronize()
+    _check_vs_oracle(reqs, wss, "batched")
+    _same_as_alone(reqs, wss, "batched")
+
+
+@pytest.mark.parametrize("prec", ["comp", "plain", "f64"])
+def test_batched_precisions(prec):
+    from paper_2310_02926_amd import binding as B
+    _case(f"batched precision {prec}")
+    flag = {"comp": B.PREC_COMP, "plain": B.PREC_PLAIN, "f64": B.PREC_F64}[prec]
+    specs, wss = _mix(12, 7)
+    reqs = _requests(wss, flag)
+    B.bin_particles_batched(reqs)
+    torch.cuda.synchronize()
+    for i, (r, ws) in enumerate(zip(reqs, wss)):
+        G.assert_parity(_to_np(r["out"]), G.oracle(ws), ws.ops, plain=(prec == "plain"), what=f"{prec} req {i}")
+
+
+def test_batched_mixed_dtypes_and_strategies():
+    """f64 coordinates, f64 attributes and a forced global-atomic request in
+    one batch: several groups plus the one-by-one fallback."""
+    from paper_2310_02926_amd import binding as B
+    _case("batched mixed dtypes")
+    rng = np.random.default_rng(3)
+    wss = []
+    for (n, side, cdt, adt) in [(50_000, 48, np.float64, np.float32), (80_000, 700, np.float64, np.float64),
+                                (20_000, 16, np.float32, np.float64), (120_000, 900, np.float32, np.float32)]:
+        wss.append(synth.Workload([rng.random(n).astype(cdt), rng.random(n).astype(cdt)],
+                                  [rng.standard_normal(n).astype(adt) for _ in range(2)], nx=side, ny=side))
+    reqs = _requests(wss)
+    B.bin_particles_batched(reqs)
+    torch.cuda.synchronize()
+    _check_vs_oracle(reqs, wss, "mixed")
+    B.bin_set_plan_override(0, 0, 0)  # every request through the global-atomic fallback
+    try:
+        reqs = _requests(wss)
+        B.bin_particles_batched(reqs)
+        torch.cuda.synchronize()
+    finally:
+        B.bin_set_plan_override(-1, 0, 0)
+    _check_vs_oracle(reqs, wss, "global fallback")
+
+
+def test_batched_edge_requests():
+    from paper_2310_02926_amd import binding as B
+    _case("batched edge requests")
+    rng = np.random.default_rng(4)
+    wss = [synth.Workload([np.zeros(0, np.float32), np.zeros(0, np.float32)], [np.zeros(0, np.float32)], nx=300, ny=300),
+           synth.Workload([np.full(100, 5.0, np.float32), np.full(100, 5.0, np.float32)], [np.ones(100, np.float32)],
+                          nx=2000, ny=3),
+           synth.Workload([rng.random(1, dtype=np.float32), rng.random(1, dtype=np.float32)], [np.ones(1, np.float32)],
+                          nx=1, ny=1)]
+    reqs = _requests(wss)
+    B.bin_particles_batched(reqs)
+    torch.cuda.synchronize()
+    _check_vs_oracle(reqs, wss, "edge")
+    B.bin_particles_batched([])  # empty batch is a no-op
+
+
+def test_batched_rejects_bad_request_by_index():
+    from paper_2310_02926_amd import binding as B
+    specs, wss = _mix(3, 9)
+    reqs = _requests(wss)
+    reqs[2]["nx"] = 0
+    with pytest.raises(B.BinError) as ei:
+        B.bin_particles_batched(reqs)
+    assert ei.value.status == B.BIN_ERR_INVALID_ARG and "request 2" in str(ei.value)
+
+
+def test_graph_replays_match_eager():
+    """A captured batch replayed several times, with eager work and syncs in
+    between, gives the eager result every time (inputs refilled between
+    replays are picked up)."""
+    from paper_2310_02926_amd import binding as B
+    _case("graph replays")
+    specs, wss = _mix(16, 5)
+    reqs = _requests(wss)
+    g = B.BinGraph(reqs)
+    s = torch.cuda.Stream()
+    try:
+        for rep in range(3):
+            for r in reqs:  # scribble over the outputs: replays must overwrite them
+                if "count" in r["out"]:
+                    r["out"]["count"].fill_(7)
+                for key in ("sum", "min", "max", "avg"):
+                    for t in r["out"].get(key, []):
+                        t.fill_(-3.0)
+            torch.cuda.synchronize()
+            g.launch(s)
+            s.synchronize()
+            _ = torch.ones(1000, device="cuda").sum().item()  # eager work between replays
+            _check_vs_oracle(reqs, wss, f"graph replay {rep}")
+        # refill the inputs of request 0 in place; the next replay must see them
+        ws0 = wss[0]
+        new_x = np.random.default_rng(99).random(ws0.n).astype(np.float32)
+        reqs[0]["coords"][0].copy_(torch.from_numpy(new_x))
+        ws0.coords[0] = new_x
+        torch.cuda.synchronize()
+        g.launch(s)
+        s.synchronize()
+        _check_vs_oracle(reqs[:1], wss[:1], "graph after refill")
+    finally:
+        g.destroy()
+
+
+def test_autotune_then_bin(tmp_path, monkeypatch):
+    """The autotuner picks a configuration per shape class; results stay
+    exact/within tolerance with the tuned configuration."""
+    from paper_2310_02926_amd import binding as B
+    _case("autotune")
+    specs, wss = _mix(3, 11, n_hi=200_000, sides=(48, 600))
+    reqs = _requests(wss)
+    B.bin_autotune(reqs)
+    B.bin_particles_batched(reqs)
+    torch.cuda.synchronize()
+    _check_vs_oracle(reqs, wss, "after autotune")
+    for r, ws in zip(reqs, wss):
+        out = B.alloc_outputs(r["attrs"], ws.nx, ws.ny, r["ops"], r["coords"][0].device)
+        B.bin_particles(r["coords"], r["attrs"], r["n"], r["axes"], r["bounds"], ws.nx, ws.ny, r["ops"], out)
+        torch.cuda.synchronize()
+        G.assert_parity(_to_np(out), G.oracle(ws), ws.ops, what="plain after autotune")
