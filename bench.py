@@ -1,12 +1,22 @@
 """Benchmark: particle binning throughput on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload hotspot|gmm|uniform]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--workload hotspot|gmm|uniform|batched|served]
 
-One step = one bin_particles call over the whole particle set (init, bin,
-finalize), inputs resident in HBM.  Prints one JSON line with throughput
-(Gparticles/s), the roofline position of the dominant (binning) kernel
-measured with HIP events recorded by the library around that kernel, and the
-CPU oracle timed on a bounded sample of the same workload.
+hotspot / gmm / uniform: one step = one bin_particles call over the whole
+particle set (init, bin, finalize), inputs resident in HBM.  Prints one JSON
+line with throughput (Gparticles/s), the roofline position of the dominant
+kernel measured with HIP events recorded by the library around that kernel,
+and the CPU oracle timed on a bounded sample of the same workload.
+
+batched: 256 independent requests (particle counts log-uniform in [1e3, 1e7],
+square grids of side 32..1024, 1-4 attributes, random op sets); one step =
+the whole batch, as a captured graph, as one batched call, and as 256
+one-at-a-time calls, all timed on the same stream.
+
+served: Poisson arrival streams of requests drawn from the batched set,
+served by the continuous-batching server (64 GB budget) and, for
+comparison, one request at a time; p50/p99 latency and throughput per rate.
 """
 from __future__ import annotations
 
@@ -115,12 +125,241 @@ def load_traffic(kernel_hash: str, workload: str):
     return rec.get("bytes_per_launch")
 
 
+def _gen_instance(spec):
+    from paper_2310_02926_amd import synth
+    return synth.instance(spec)
+
+
+def batch_workloads(count: int, seed: int, scale: int, workers: int = 16):
+    """The batched request set (synth.batch_specs), generated by a pool of
+    processes forked before any GPU use."""
+    import multiprocessing as mp
+    from paper_2310_02926_amd import synth
+    specs = synth.batch_specs(count, seed=seed, n_hi=1e7 / (1 << scale))
+    workers = max(1, min(workers, os.cpu_count() or 1))
+    with mp.get_context("fork").Pool(workers) as pool:
+        wss = pool.map(_gen_instance, specs, chunksize=1)
+    return specs, wss
+
+
+def _upload(wss, dev):
+    import torch
+    from paper_2310_02926_amd import binding as B
+    reqs = []
+    for ws in wss:
+        coords = [torch.from_numpy(c).to(dev) for c in ws.coords]
+        attrs = [torch.from_numpy(a).to(dev) for a in ws.attrs]
+        out = B.alloc_outputs(attrs, ws.nx, ws.ny, ws.ops, dev)
+        reqs.append(dict(coords=coords, attrs=attrs, n=ws.n, axes=ws.axes, bounds=ws.bounds, nx=ws.nx, ny=ws.ny,
+                         ops=ws.ops, out=out))
+    return reqs
+
+
+def _timed(stream, steps, fn):
+    import torch
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(steps):
+        fn()
+    ev1.record(stream)
+    stream.synchronize()
+    return ev0.elapsed_time(ev1) / steps
+
+
+def _same_results(reqs, snap):
+    """Counts equal and sums within 1e-9 relative of a snapshot."""
+    import torch
+    for r, s in zip(reqs, snap):
+        for key, val in s.items():
+            cur = r["out"][key]
+            if key == "count":
+                if not torch.equal(cur, val):
+                    return False
+            else:
+                for x, y in zip(cur, val):
+                    if not torch.allclose(x, y, rtol=1e-9, atol=1e-9, equal_nan=True):
+                        return False
+    return True
+
+
+def _snapshot(reqs):
+    snap = []
+    for r in reqs:
+        d = {}
+        for key, val in r["out"].items():
+            d[key] = val.clone() if key == "count" else [t.clone() for t in val]
+        snap.append(d)
+    return snap
+
+
+def run_batched(args):
+    t0 = time.time()
+    specs, wss = batch_workloads(256, 0, args.scale)
+    total_n = sum(ws.n for ws in wss)
+    in_bytes = sum(sum(c.nbytes for c in ws.coords) + sum(a.nbytes for a in ws.attrs) for ws in wss)
+    log(f"generated 256 batched instances, {total_n} particles, {in_bytes / 1e9:.2f} GB in {time.time() - t0:.1f}s")
+    import torch
+    from paper_2310_02926_amd import binding as B
+    dev = torch.device("cuda:0")
+    reqs = _upload(wss, dev)
+    del wss
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    t0 = time.time()
+    B.bin_autotune(reqs)
+    log(f"autotune {time.time() - t0:.1f}s")
+    batch = B.Batch(reqs)
+
+    def one_at_a_time():
+        for i in range(batch.n):
+            batch.launch_one(i, stream)
+
+    # reference results: one request at a time
+    one_at_a_time()
+    stream.synchronize()
+    ref = _snapshot(reqs)
+    for _ in range(args.warmup):
+        batch.launch(stream)
+    stream.synchronize()
+    ok_batched = _same_results(reqs, ref)
+    graph = B.BinGraph(reqs)
+    for _ in range(args.warmup):
+        graph.launch(stream)
+    stream.synchronize()
+    ok_graph = _same_results(reqs, ref)
+    for _ in range(args.warmup):
+        one_at_a_time()
+    ms_one = _timed(stream, args.steps, one_at_a_time)
+    ms_batch = _timed(stream, args.steps, lambda: batch.launch(stream))
+    ms_graph = _timed(stream, args.steps, lambda: graph.launch(stream))
+    graph.destroy()
+    log(f"one-at-a-time {ms_one:.3f} ms, batched {ms_batch:.3f} ms, graph {ms_graph:.3f} ms per batch")
+    gp = lambda ms: round(total_n / (ms / 1e3) / 1e9, 3)
+    best = min(ms_graph, ms_batch)
+    rec = {
+        "metric": METRIC, "value": gp(best), "unit": "Gparticles/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(best, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched_256_requests", "n_total": total_n, "input_bytes": in_bytes,
+                   "requests": "n log-uniform [1e3,1e7], square side in {32..1024}, 1-4 f32 attrs, random ops",
+                   "tuning": "bin_autotune over the request shapes"},
+        "batched": {"graph_ms": round(ms_graph, 4), "batched_call_ms": round(ms_batch, 4),
+                    "one_at_a_time_ms": round(ms_one, 4), "graph_Gps": gp(ms_graph),
+                    "batched_call_Gps": gp(ms_batch), "one_at_a_time_Gps": gp(ms_one),
+                    "speedup_vs_one_at_a_time": round(ms_one / best, 3),
+                    "results_equal_one_at_a_time": bool(ok_batched and ok_graph),
+                    "input_GBs": round(in_bytes / (best / 1e3) / 1e9, 1)},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+def _percentiles(lat_ms):
+    a = np.sort(np.asarray(lat_ms))
+    return round(float(np.percentile(a, 50)), 3), round(float(np.percentile(a, 99)), 3)
+
+
+def run_served(args):
+    import threading
+    t0 = time.time()
+    specs, wss = batch_workloads(256, 0, args.scale)
+    log(f"generated request pool in {time.time() - t0:.1f}s")
+    import torch
+    from paper_2310_02926_amd import binding as B
+    from paper_2310_02926_amd import synth
+    dev = torch.device("cuda:0")
+    pool = _upload(wss, dev)
+    del wss
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    B.bin_autotune(pool)
+    batch = B.Batch(pool)
+    rates = [100, 500, 1000, 2000, 5000]
+    rows = []
+    for rate in rates:
+        count = int(min(2000, max(200, rate)))
+        arr = synth.poisson_arrivals(rate, count, seed=rate)
+        pick = np.random.default_rng(rate).integers(0, len(pool), count)
+        n_total = int(sum(pool[i]["n"] for i in pick))
+        # served: one submitter thread at the arrival times, the main thread waits
+        srv = B.Server(budget_bytes=64 << 30, n_slots=4, max_batch=64)
+        tickets = [None] * count
+        sub_t = [0.0] * count
+
+        def submitter():
+            start = time.perf_counter()
+            for j in range(count):
+                while time.perf_counter() - start < arr[j]:
+                    d = arr[j] - (time.perf_counter() - start)
+                    if d > 2e-4:
+                        time.sleep(d - 1e-4)
+                r = pool[pick[j]]
+                sub_t[j] = time.perf_counter()
+                tickets[j] = srv.submit(r["coords"], r["attrs"], r["n"], r["axes"], r["bounds"], r["nx"], r["ny"],
+                                        r["ops"])
+
+        th = threading.Thread(target=submitter)
+        t_start = time.perf_counter()
+        th.start()
+        lat = []
+        t_end = t_start
+        for j in range(count):
+            while tickets[j] is None:
+                time.sleep(5e-5)
+            res = srv.wait(tickets[j], timeout_s=120)
+            if res.status != B.BIN_OK:
+                raise SystemExit(f"served request failed: {B.status_string(res.status)}")
+            lat.append(res.submit_to_done_ms)
+            t_end = max(t_end, sub_t[j] + res.submit_to_done_ms / 1e3)
+            srv.release(tickets[j])
+        th.join()
+        stats = srv.stats()
+        srv.destroy()
+        p50, p99 = _percentiles(lat)
+        span = t_end - t_start
+        # one at a time: same arrivals, each request enqueued alone and waited for
+        lat1 = []
+        start = time.perf_counter()
+        t_end1 = start
+        for j in range(count):
+            now = time.perf_counter() - start
+            if now < arr[j]:
+                time.sleep(arr[j] - now)
+            batch.launch_one(int(pick[j]), stream)
+            stream.synchronize()
+            done = time.perf_counter()
+            lat1.append((done - start - arr[j]) * 1e3)
+            t_end1 = done
+        q50, q99 = _percentiles(lat1)
+        span1 = t_end1 - start
+        row = {"rate_req_s": rate, "requests": count, "particles": n_total,
+               "served": {"Gps": round(n_total / span / 1e9, 3), "p50_ms": p50, "p99_ms": p99,
+                          "batches": int(stats["batches"]), "peak_bytes": int(stats["peak_bytes"])},
+               "one_at_a_time": {"Gps": round(n_total / span1 / 1e9, 3), "p50_ms": q50, "p99_ms": q99}}
+        log(f"rate {rate}: {row}")
+        rows.append(row)
+    top = rows[-1]
+    rec = {
+        "metric": METRIC, "value": top["served"]["Gps"], "unit": "Gparticles/s", "n_gpus": 1,
+        "steps": len(rates), "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "served_poisson_batched_pool", "budget_bytes": 64 << 30, "slots": 4,
+                   "max_batch": 64, "rates_req_s": rates,
+                   "requests": "drawn uniformly from the 256-request batched set"},
+        "served": rows, "p50_ms": top["served"]["p50_ms"], "p99_ms": top["served"]["p99_ms"],
+        "cpu_baseline": None,
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="hotspot", choices=["hotspot", "gmm", "uniform"])
+    ap.add_argument("--workload", default="hotspot", choices=["hotspot", "gmm", "uniform", "batched", "served"])
     ap.add_argument("--prec", default="default", choices=["default", "comp", "plain", "f64"])
     ap.add_argument("--scale", type=int, default=0, help="shrink n by 2^scale (quick runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -130,6 +369,10 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "batched":
+        return run_batched(args)
+    if args.workload == "served":
+        return run_served(args)
 
     import torch
     from paper_2310_02926_amd import binding as B

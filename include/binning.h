@@ -170,6 +170,28 @@ int bin_validate(const bin_columns* coords, const bin_columns* attrs, int64_t n,
  * request array is read during the call only.  Enqueues and returns. */
 int bin_particles_batched(const bin_request* reqs, int32_t nreq, void* stream);
 
+/* ---- several grids over one particle table --------------------------------- */
+/* One binning of the table per grid spec.  The in situ load of the paper's
+ * experiments (Section 4.3) bins the same variables over several coordinate
+ * systems at every step, each system as its own operator instance run in
+ * sequence; here all of them are one enqueue.  Each spec picks its own axes
+ * (two columns of coords), bounds ({xlo, xhi, ylo, yhi}, explicit), mesh,
+ * ops and outputs, with the rules of bin_particles; all specs share coords,
+ * attrs and n.  Attributes binned on the same axes belong in one spec (k
+ * attributes of one spec share every per-particle step).  Results equal
+ * those of one bin_particles call per spec.  Invalid specs are reported as
+ * "request g: ..." before anything is enqueued.  Outputs of different specs
+ * must not overlap.  Enqueues and returns. */
+typedef struct bin_grid_spec {
+  int32_t axes[2];
+  double bounds[4];
+  int32_t nx, ny;
+  uint32_t ops;
+  bin_output out;
+} bin_grid_spec;
+int bin_particles_multi(const bin_columns* coords, const bin_columns* attrs, int64_t n,
+                        const bin_grid_spec* grids, int32_t ngrids, void* stream);
+
 /* ---- graphs ---------------------------------------------------------------- */
 /* Capture the batched launch of nreq requests as a HIP graph.  The graph
  * owns its descriptor and scratch memory; the caller's buffers are borrowed

@@ -29,7 +29,7 @@ MAX_ATTRS = 16
 
 #: Every function declared in include/binning.h.
 EXPORTS = (
-    "bin_particles", "bin_validate", "bin_particles_batched", "bin_graph_create", "bin_graph_launch",
+    "bin_particles", "bin_validate", "bin_particles_batched", "bin_particles_multi", "bin_graph_create", "bin_graph_launch",
     "bin_graph_destroy", "bin_autotune", "bin_status_string", "bin_last_error_message",
     "bin_stream_status", "bin_release_workspace", "bin_version", "bin_timing_enable", "bin_timing_read",
     "bin_timing_report",
@@ -61,6 +61,11 @@ class ServerConfig(ctypes.Structure):
 class ServerRequest(ctypes.Structure):
     _fields_ = [("coords", Columns), ("attrs", Columns), ("n", c_int64), ("axes", c_int32 * 2),
                 ("bounds", c_double * 4), ("nx", c_int32), ("ny", c_int32), ("ops", c_uint32)]
+
+
+class GridSpec(ctypes.Structure):
+    _fields_ = [("axes", c_int32 * 2), ("bounds", c_double * 4), ("nx", c_int32), ("ny", c_int32),
+                ("ops", c_uint32), ("out", Output)]
 
 
 class Result(ctypes.Structure):
@@ -99,6 +104,8 @@ def lib() -> ctypes.CDLL:
         "bin_validate": (c_int, [POINTER(Columns), POINTER(Columns), c_int64, POINTER(c_int32),
                                  POINTER(c_double), c_int32, c_int32, c_uint32, POINTER(Output)]),
         "bin_particles_batched": (c_int, [POINTER(Request), c_int32, c_void_p]),
+        "bin_particles_multi": (c_int, [POINTER(Columns), POINTER(Columns), c_int64, POINTER(GridSpec), c_int32,
+                                        c_void_p]),
         "bin_graph_create": (c_int, [POINTER(Request), c_int32, POINTER(c_void_p)]),
         "bin_graph_launch": (c_int, [c_void_p, c_void_p]),
         "bin_graph_destroy": (c_int, [c_void_p]),
@@ -296,6 +303,46 @@ def bin_autotune(reqs: Sequence[Dict]) -> None:
     their outputs; synchronises a private stream) and remember the best."""
     arr, keep = request_array(reqs)
     check(lib().bin_autotune(arr, len(reqs)))
+
+
+def grid_specs(grids: Sequence[Dict]):
+    """A ctypes array of GridSpec records from dicts with keys axes, bounds,
+    nx, ny, ops, out (as bin_particles), plus the objects they reference."""
+    arr = (GridSpec * max(len(grids), 1))()
+    keep = []
+    for i, g in enumerate(grids):
+        out = g["out"]
+        o, ok = output(out.get("count"), out.get("sum"), out.get("min"), out.get("max"), out.get("avg"))
+        arr[i] = GridSpec((c_int32 * 2)(*g["axes"]), (c_double * 4)(*g["bounds"]), g["nx"], g["ny"], g["ops"], o)
+        keep.append(ok)
+    return arr, keep
+
+
+def bin_particles_multi(coords, attrs, n: int, grids: Sequence[Dict], stream=None, coord_dtype=None,
+                        attr_dtype=None) -> None:
+    """Enqueue one binning of the table per grid spec (see grid_specs)."""
+    c, ck = columns(coords, coord_dtype)
+    a, ak = columns(attrs, attr_dtype) if attrs else (None, None)
+    arr, keep = grid_specs(grids)
+    check(lib().bin_particles_multi(ctypes.byref(c), ctypes.byref(a) if a is not None else None, n, arr,
+                                    len(grids), _stream_handle(stream)))
+
+
+class Batch:
+    """Requests marshalled once and enqueued many times, as one batch
+    (bin_particles_batched) or one request at a time (bin_particles)."""
+
+    def __init__(self, reqs: Sequence[Dict]):
+        self.arr, self._keep = request_array(reqs)
+        self.n = len(reqs)
+
+    def launch(self, stream=None) -> None:
+        check(lib().bin_particles_batched(self.arr, self.n, _stream_handle(stream)))
+
+    def launch_one(self, i: int, stream=None) -> None:
+        r = self.arr[i]
+        check(lib().bin_particles(ctypes.byref(r.coords), ctypes.byref(r.attrs), r.n, r.axes, r.bounds, r.nx,
+                                  r.ny, r.ops, ctypes.byref(r.out), _stream_handle(stream)))
 
 
 class BinGraph:

@@ -398,6 +398,30 @@ int bin_particles_batched(const bin_request* reqs, int32_t nreq, void* stream) {
   return run_batch(reqs, nreq, static_cast<hipStream_t>(stream), thread_hints());
 }
 
+int bin_particles_multi(const bin_columns* coords, const bin_columns* attrs, int64_t n,
+                        const bin_grid_spec* grids, int32_t ngrids, void* stream) {
+  clear_error();
+  if (!coords) return fail(BIN_ERR_INVALID_ARG, "coords is NULL");
+  if (ngrids < 0 || ngrids > 65535) return fail(BIN_ERR_INVALID_ARG, "ngrids must be in [0, 65535]");
+  if (ngrids > 0 && !grids) return fail(BIN_ERR_INVALID_ARG, "grids is NULL");
+  std::vector<bin_request> reqs((size_t)ngrids);
+  for (int g = 0; g < ngrids; ++g) {
+    bin_request& r = reqs[(size_t)g];
+    std::memset(&r, 0, sizeof r);
+    r.coords = *coords;
+    if (attrs) r.attrs = *attrs;
+    r.n = n;
+    r.axes[0] = grids[g].axes[0];
+    r.axes[1] = grids[g].axes[1];
+    std::memcpy(r.bounds, grids[g].bounds, sizeof r.bounds);
+    r.nx = grids[g].nx;
+    r.ny = grids[g].ny;
+    r.ops = grids[g].ops;
+    r.out = grids[g].out;
+  }
+  return run_batch(reqs.data(), ngrids, static_cast<hipStream_t>(stream), thread_hints());
+}
+
 int bin_graph_create(const bin_request* reqs, int32_t nreq, bin_graph** out) {
   clear_error();
   if (!out) return fail(BIN_ERR_INVALID_ARG, "graph is NULL");

@@ -42,6 +42,27 @@ __device__ __forceinline__ void resolve_axes(const long long* keys, Axis& ax, Ax
 // patterns equals IEEE totalOrder; for a value with the sign bit set,
 // unsigned order of the bits is the reverse of totalOrder.  One integer
 // atomic per lane, no key decoding pass.
+// totalOrder keys of raw float bits (signed order of the key = totalOrder).
+__device__ __forceinline__ int total_key(int b) { return b >= 0 ? b : (b ^ 0x7FFFFFFF); }
+__device__ __forceinline__ long long total_key(long long b) { return b >= 0 ? b : (b ^ 0x7FFFFFFFFFFFFFFFLL); }
+
+// Skip the atomic when the value cannot beat the value read from the result
+// array: min/max only move one way, so even a stale read is a safe filter.
+template <typename T, typename I>
+__device__ __forceinline__ bool beats_min(const T* p, T v) {
+  const I cur = __hip_atomic_load(reinterpret_cast<const I*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  I vb;
+  __builtin_memcpy(&vb, &v, sizeof vb);
+  return total_key(vb) < total_key(cur);
+}
+template <typename T, typename I>
+__device__ __forceinline__ bool beats_max(const T* p, T v) {
+  const I cur = __hip_atomic_load(reinterpret_cast<const I*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  I vb;
+  __builtin_memcpy(&vb, &v, sizeof vb);
+  return total_key(vb) > total_key(cur);
+}
+
 __device__ __forceinline__ void atomic_min_fp(float* p, float v) {
   const int b = __float_as_int(v);
   if (b >= 0)
@@ -106,27 +127,33 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-// Elements i .. i+3 of a column into out[0..3], zero past hi.  With vec
-// (column 16-byte aligned, i a multiple of 4) a full group is read with
-// 16-byte loads: HBM streams at full rate only with wide loads.
+// Elements i .. i+3 of a 16-byte aligned column (i a multiple of 4), read
+// with 16-byte loads: HBM streams at full rate only with wide loads.
+template <typename T>
+__device__ __forceinline__ void ld4v(const void* p, int64_t i, T* out) {
+  if constexpr (sizeof(T) == 4) {
+    const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(static_cast<const T*>(p) + i));
+    out[0] = v.x;
+    out[1] = v.y;
+    out[2] = v.z;
+    out[3] = v.w;
+  } else {
+    const f64x2* q = reinterpret_cast<const f64x2*>(static_cast<const T*>(p) + i);
+    const f64x2 a = __builtin_nontemporal_load(q);
+    const f64x2 b = __builtin_nontemporal_load(q + 1);
+    out[0] = a.x;
+    out[1] = a.y;
+    out[2] = b.x;
+    out[3] = b.y;
+  }
+}
+
+// Elements i .. i+3 of a column into out[0..3], zero past hi; wide loads
+// when vec (column 16-byte aligned, i a multiple of 4) and the group is full.
 template <typename T>
 __device__ __forceinline__ void ld4(const void* p, int64_t i, int64_t hi, bool vec, T* out) {
   if (vec && i + 4 <= hi) {
-    if constexpr (sizeof(T) == 4) {
-      const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(static_cast<const T*>(p) + i));
-      out[0] = v.x;
-      out[1] = v.y;
-      out[2] = v.z;
-      out[3] = v.w;
-    } else {
-      const f64x2* q = reinterpret_cast<const f64x2*>(static_cast<const T*>(p) + i);
-      const f64x2 a = __builtin_nontemporal_load(q);
-      const f64x2 b = __builtin_nontemporal_load(q + 1);
-      out[0] = a.x;
-      out[1] = a.y;
-      out[2] = b.x;
-      out[3] = b.y;
-    }
+    ld4v<T>(p, i, out);
   } else {
 #pragma unroll
     for (int e = 0; e < 4; ++e) out[e] = i + e < hi ? ld<T>(p, i + e) : T(0);
@@ -180,8 +207,20 @@ struct Tile {
         if (e != 0.0f) atomicAdd(S + L.tb + b, e);
       }
     }
-    if (L.want_min) atomicMin(reinterpret_cast<K*>(smem + L.lds_min_off[j]) + b, fkey(v));
-    if (L.want_max) atomicMax(reinterpret_cast<K*>(smem + L.lds_max_off[j]) + b, fkey(v));
+    // min/max keys only move one way, so a value that does not beat the key
+    // read (however stale) cannot change it: skip its atomic.  Once a bin has
+    // seen m values, a new one changes its min with probability ~1/m.
+    if (L.want_min || L.want_max) {
+      const K kv = fkey(v);
+      if (L.want_min) {
+        K* m = reinterpret_cast<K*>(smem + L.lds_min_off[j]) + b;
+        if (kv < __hip_atomic_load(m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) atomicMin(m, kv);
+      }
+      if (L.want_max) {
+        K* m = reinterpret_cast<K*>(smem + L.lds_max_off[j]) + b;
+        if (kv > __hip_atomic_load(m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) atomicMax(m, kv);
+      }
+    }
   }
 
   __device__ static uint32_t cnt_get(const unsigned char* smem, int b) {

@@ -111,6 +111,8 @@ struct LdsArgs {
   int64_t n;
   int64_t chunk;   // particles per workgroup
   int32_t nx, nbins, k, nslots;
+  int32_t vec;     // every column 16-byte aligned and chunk % 4 == 0: wide loads
+  int32_t pad;
   Outs out;
   TileLayout lay;
   void* partial;   // nslots partial slots (nslots > 1)
@@ -145,7 +147,8 @@ struct PartArgs {
   uint32_t* n_items;   // [1]
   uint32_t* tile_items;  // [ntiles][3]: first item, item count, first partial slot
   void* partial;       // max_slots partial slots (items of split tiles)
-  int32_t max_slots, pad2;
+  int32_t max_slots;
+  int32_t vec;         // every column 16-byte aligned and chunk % 4 == 0: wide loads
   Outs out;
   TileLayout lay;
 };

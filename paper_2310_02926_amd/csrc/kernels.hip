@@ -68,8 +68,9 @@ __device__ __forceinline__ void global_update(const AccPtrs& p, int b, AT v) {
       if (e != 0.0f) atomicAdd(p.comp + b, e);
     }
   }
-  if (p.mn) atomic_min_fp(static_cast<AT*>(p.mn) + b, v);
-  if (p.mx) atomic_max_fp(static_cast<AT*>(p.mx) + b, v);
+  using I = typename KeyOf<AT>::T;
+  if (p.mn && beats_min<AT, I>(static_cast<AT*>(p.mn) + b, v)) atomic_min_fp(static_cast<AT*>(p.mn) + b, v);
+  if (p.mx && beats_max<AT, I>(static_cast<AT*>(p.mx) + b, v)) atomic_max_fp(static_cast<AT*>(p.mx) + b, v);
 }
 
 template <typename CT, typename AT, int PREC, int PPT>
@@ -146,32 +147,35 @@ __device__ __forceinline__ void bin_lds_body(const LdsArgs& a, int wg) {
 
   const int64_t lo = (int64_t)wg * a.chunk;
   const int64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
-  constexpr int U = 4;
-  for (int64_t base = lo; base < hi; base += (int64_t)U * blockDim.x) {
-    int bin[U];
+  // Groups of 4 consecutive particles per lane (16-byte loads).
+  const bool vec = a.vec != 0;
+  constexpr int G = 2;
+  for (int64_t base = lo; base < hi; base += (int64_t)4 * G * blockDim.x) {
+    int bin[4 * G];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t i = base + (int64_t)u * blockDim.x + threadIdx.x;
-      bin[u] = -1;
-      if (i < hi) {
+    for (int g = 0; g < G; ++g) {
+      const int64_t i = base + 4 * ((int64_t)g * blockDim.x + threadIdx.x);
+      CT xs[4], ys[4];
+      ld4<CT>(a.x, i, hi, vec, xs);
+      ld4<CT>(a.y, i, hi, vec, ys);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
         int ix, iy;
-        const double x = (double)ld<CT>(a.x, i);
-        const double y = (double)ld<CT>(a.y, i);
-        if (locate(x, ax, ix) && locate(y, ay, iy)) bin[u] = iy * a.nx + ix;
+        bin[4 * g + e] = -1;
+        if (i + e < hi && locate((double)xs[e], ax, ix) && locate((double)ys[e], ay, iy))
+          bin[4 * g + e] = iy * a.nx + ix;
       }
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+    for (int u = 0; u < 4 * G; ++u)
       if (bin[u] >= 0) TL::count(smem, bin[u]);
     for (int j = 0; j < a.k; ++j) {
-      AT v[U];
+      AT v[4 * G];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t i = base + (int64_t)u * blockDim.x + threadIdx.x;
-        v[u] = bin[u] >= 0 ? ld<AT>(a.attr[j], i) : AT(0);
-      }
+      for (int g = 0; g < G; ++g)
+        ld4<AT>(a.attr[j], base + 4 * ((int64_t)g * blockDim.x + threadIdx.x), hi, vec, v + 4 * g);
 #pragma unroll
-      for (int u = 0; u < U; ++u)
+      for (int u = 0; u < 4 * G; ++u)
         if (bin[u] >= 0) TL::add(smem, a.lay, j, bin[u], v[u]);
     }
   }

@@ -96,19 +96,27 @@ __device__ __forceinline__ void part_count_body(const PartArgs& a, int wg) {
   const int64_t lo = (int64_t)wg * a.chunk;
   const int64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
   const int shift = a.lay.tile_shift;
-  constexpr int U = 8;
-  for (int64_t base = lo; base < hi; base += (int64_t)U * blockDim.x) {
-    double xs[U], ys[U];
+  const bool vec = a.vec != 0;
+  // Each lane takes groups of 4 consecutive particles (16-byte loads).
+  constexpr int G = 4;
+  const int64_t step = (int64_t)4 * G * blockDim.x;
+  for (int64_t base = lo; base < hi; base += step) {
+    CT xs[4 * G], ys[4 * G];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t i = base + (int64_t)u * blockDim.x + threadIdx.x;
-      xs[u] = i < hi ? (double)ld<CT>(a.x, i) : __builtin_nan("");
-      ys[u] = i < hi ? (double)ld<CT>(a.y, i) : __builtin_nan("");
+    for (int g = 0; g < G; ++g) {
+      const int64_t i = base + 4 * ((int64_t)g * blockDim.x + threadIdx.x);
+      ld4<CT>(a.x, i, hi, vec, xs + 4 * g);
+      ld4<CT>(a.y, i, hi, vec, ys + 4 * g);
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      int ix, iy;
-      if (locate(xs[u], ax, ix) && locate(ys[u], ay, iy)) atomicAdd(h + ((iy * a.nx + ix) >> shift), 1u);
+    for (int g = 0; g < G; ++g) {
+      const int64_t i = base + 4 * ((int64_t)g * blockDim.x + threadIdx.x);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int ix, iy;
+        if (i + e < hi && locate((double)xs[4 * g + e], ax, ix) && locate((double)ys[4 * g + e], ay, iy))
+          atomicAdd(h + ((iy * a.nx + ix) >> shift), 1u);
+      }
     }
   }
   __syncthreads();
@@ -224,104 +232,145 @@ __global__ __launch_bounds__(1024) void part_items_batched(const PartArgs* __res
 // Scatter: per sub-chunk of S = NT * PPT particles, rank each inside
 // particle within its tile (LDS atomic), scan the tile counts, place records
 // in LDS in tile order, then copy each tile's run to its global segment.
-// The coordinates of the next sub-chunk are loaded while the current one is
-// sorted and written.
+// Lane t takes the groups of 4 consecutive particles starting at
+// base + 4 * (q * NT + t), q < PPT / 4.  Whole sub-chunks of an aligned
+// request are read with 16-byte loads and no bounds tests, and the next
+// one's coordinates are loaded while the current one is sorted and written;
+// the remainder (and unaligned requests) take a bounds-tested path.
 // LDS: cnt[T] | off[T] | run[T] | (tile << 16 | local bin)[S] | values[k][S]
 // ---------------------------------------------------------------------------
-template <typename CT, typename AT, int PPT, int NT>
-__device__ __forceinline__ void part_scatter_body(const PartArgs& a, int wg) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ uint32_t wave_tot[NT / 64];
+template <typename CT, typename AT, int PPT, int NT, bool FULL>
+__device__ __forceinline__ void scatter_sub(const PartArgs& a, unsigned char* smem, uint32_t* wave_tot,
+                                            const Axis& ax, const Axis& ay, int64_t base, int64_t hi,
+                                            int64_t full_end, CT* px, CT* py) {
   constexpr int S = NT * PPT;
+  constexpr int Q = PPT / 4;
   const int T = a.ntiles;
   uint32_t* cnt = reinterpret_cast<uint32_t*>(smem);
   uint32_t* off = cnt + T;
   uint32_t* run = off + T;
   uint32_t* stg_tb = run + T;
   AT* stg_v = reinterpret_cast<AT*>(smem + a.stage_val_off);
+  const int shift = a.lay.tile_shift;
+  const uint32_t lmask = (1u << shift) - 1u;
+  const int k = a.k;
+
+  uint32_t tb[PPT], pos[PPT];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t i = base + 4 * ((int64_t)q * NT + threadIdx.x);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int u = 4 * q + e;
+      tb[u] = 0xFFFFFFFFu;
+      int ix, iy;
+      if ((FULL || i + e < hi) && locate((double)px[u], ax, ix) && locate((double)py[u], ay, iy)) {
+        const uint32_t b = (uint32_t)(iy * a.nx + ix);
+        tb[u] = ((b >> shift) << 16) | (b & lmask);
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) pos[u] = tb[u] != 0xFFFFFFFFu ? atomicAdd(cnt + (tb[u] >> 16), 1u) : 0u;
+  if constexpr (FULL) {  // prefetch the next whole sub-chunk's coordinates
+    if (base + S < full_end) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int64_t i = base + S + 4 * ((int64_t)q * NT + threadIdx.x);
+        ld4v<CT>(a.x, i, px + 4 * q);
+        ld4v<CT>(a.y, i, py + 4 * q);
+      }
+    }
+  }
+  __syncthreads();
+  uint32_t carry = 0;
+  for (int t0 = 0; t0 < T; t0 += NT) {
+    const int t = t0 + threadIdx.x;
+    uint32_t tot;
+    const uint32_t ex = block_scan_excl<NT>(t < T ? cnt[t] : 0u, wave_tot, tot);
+    if (t < T) off[t] = carry + ex;
+    carry += tot;
+  }
+  const uint32_t nsub = carry;
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    if (tb[u] == 0xFFFFFFFFu) continue;
+    pos[u] += off[tb[u] >> 16];
+    stg_tb[pos[u]] = tb[u];
+  }
+  for (int j = 0; j < k; ++j) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t i = base + 4 * ((int64_t)q * NT + threadIdx.x);
+      AT v[4];
+      if constexpr (FULL)
+        ld4v<AT>(a.attr[j], i, v);
+      else
+        ld4<AT>(a.attr[j], i, hi, false, v);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (tb[4 * q + e] != 0xFFFFFFFFu) stg_v[(int64_t)j * S + pos[4 * q + e]] = v[e];
+    }
+  }
+  __syncthreads();
+  // Consecutive p of one tile go to consecutive record addresses.
+  for (uint32_t p = threadIdx.x; p < nsub; p += NT) {
+    const uint32_t v = stg_tb[p];
+    const uint32_t t = v >> 16;
+    const uint32_t dst = run[t] + (p - off[t]);
+    a.rec_bin[dst] = (uint16_t)(v & 0xFFFFu);
+    for (int j = 0; j < k; ++j) static_cast<AT*>(a.rec_val[j])[dst] = stg_v[(int64_t)j * S + p];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < T; t += NT) {
+    run[t] += cnt[t];
+    cnt[t] = 0u;
+  }
+  __syncthreads();
+}
+
+template <typename CT, typename AT, int PPT, int NT>
+__device__ __forceinline__ void part_scatter_body(const PartArgs& a, int wg) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ uint32_t wave_tot[NT / 64];
+  constexpr int S = NT * PPT;
+  constexpr int Q = PPT / 4;
+  const int T = a.ntiles;
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(smem);
+  uint32_t* run = cnt + 2 * T;
   Axis ax = a.ax, ay = a.ay;
   resolve_axes(a.dyn, ax, ay);
-
   for (int t = threadIdx.x; t < T; t += NT) {
     cnt[t] = 0u;
     run[t] = a.counts[(int64_t)t * a.nwg + wg];
   }
   const int64_t lo = (int64_t)wg * a.chunk;
   const int64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
-  const int shift = a.lay.tile_shift;
-  const uint32_t lmask = (1u << shift) - 1u;
-  const int k = a.k;
+  const int64_t full_end = a.vec ? lo + (hi - lo) / S * S : lo;
   CT px[PPT], py[PPT];
+  if (lo < full_end) {
 #pragma unroll
-  for (int u = 0; u < PPT; ++u) {
-    const int64_t i = lo + (int64_t)u * NT + threadIdx.x;
-    px[u] = i < hi ? ld<CT>(a.x, i) : CT(0);
-    py[u] = i < hi ? ld<CT>(a.y, i) : CT(0);
+    for (int q = 0; q < Q; ++q) {
+      const int64_t i = lo + 4 * ((int64_t)q * NT + threadIdx.x);
+      ld4v<CT>(a.x, i, px + 4 * q);
+      ld4v<CT>(a.y, i, py + 4 * q);
+    }
   }
   __syncthreads();
-  for (int64_t base = lo; base < hi; base += S) {
-    uint32_t tb[PPT], pos[PPT];
+  for (int64_t base = lo; base < full_end; base += S)
+    scatter_sub<CT, AT, PPT, NT, true>(a, smem, wave_tot, ax, ay, base, hi, full_end, px, py);
+  for (int64_t base = full_end; base < hi; base += S) {
 #pragma unroll
-    for (int u = 0; u < PPT; ++u) {
-      const int64_t i = base + (int64_t)u * NT + threadIdx.x;
-      tb[u] = 0xFFFFFFFFu;
-      pos[u] = 0u;
-      int ix, iy;
-      if (i < hi && locate((double)px[u], ax, ix) && locate((double)py[u], ay, iy)) {
-        const uint32_t b = (uint32_t)(iy * a.nx + ix);
-        tb[u] = ((b >> shift) << 16) | (b & lmask);
+    for (int q = 0; q < Q; ++q) {
+      const int64_t i = base + 4 * ((int64_t)q * NT + threadIdx.x);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        px[4 * q + e] = i + e < hi ? ld<CT>(a.x, i + e) : CT(0);
+        py[4 * q + e] = i + e < hi ? ld<CT>(a.y, i + e) : CT(0);
       }
     }
-#pragma unroll
-    for (int u = 0; u < PPT; ++u)
-      if (tb[u] != 0xFFFFFFFFu) pos[u] = atomicAdd(cnt + (tb[u] >> 16), 1u);
-    // Prefetch the next sub-chunk's coordinates.
-#pragma unroll
-    for (int u = 0; u < PPT; ++u) {
-      const int64_t i = base + S + (int64_t)u * NT + threadIdx.x;
-      px[u] = i < hi ? ld<CT>(a.x, i) : CT(0);
-      py[u] = i < hi ? ld<CT>(a.y, i) : CT(0);
-    }
-    __syncthreads();
-    uint32_t carry = 0;
-    for (int t0 = 0; t0 < T; t0 += NT) {
-      const int t = t0 + threadIdx.x;
-      uint32_t tot;
-      const uint32_t ex = block_scan_excl<NT>(t < T ? cnt[t] : 0u, wave_tot, tot);
-      if (t < T) off[t] = carry + ex;
-      carry += tot;
-    }
-    const uint32_t nsub = carry;
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < PPT; ++u) {
-      if (tb[u] == 0xFFFFFFFFu) continue;
-      pos[u] += off[tb[u] >> 16];
-      stg_tb[pos[u]] = tb[u];
-    }
-    for (int j = 0; j < k; ++j) {
-#pragma unroll
-      for (int u = 0; u < PPT; ++u) {
-        if (tb[u] == 0xFFFFFFFFu) continue;
-        const int64_t i = base + (int64_t)u * NT + threadIdx.x;
-        stg_v[(int64_t)j * S + pos[u]] = ld<AT>(a.attr[j], i);
-      }
-    }
-    __syncthreads();
-    // Consecutive p of one tile go to consecutive record addresses.
-    for (uint32_t p = threadIdx.x; p < nsub; p += NT) {
-      const uint32_t v = stg_tb[p];
-      const uint32_t t = v >> 16;
-      const uint32_t dst = run[t] + (p - off[t]);
-      a.rec_bin[dst] = (uint16_t)(v & 0xFFFFu);
-      for (int j = 0; j < k; ++j) static_cast<AT*>(a.rec_val[j])[dst] = stg_v[(int64_t)j * S + p];
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < T; t += NT) {
-      run[t] += cnt[t];
-      cnt[t] = 0u;
-    }
-    __syncthreads();
+    scatter_sub<CT, AT, PPT, NT, false>(a, smem, wave_tot, ax, ay, base, hi, full_end, px, py);
   }
 }
 
@@ -355,26 +404,49 @@ __device__ __forceinline__ void part_bin_body(const PartArgs& a, int item) {
   TL::init(smem, a.lay, k);
   __syncthreads();
 
-  constexpr int U = 4;
-  for (uint32_t base = rb; base < re; base += U * blockDim.x) {
-    uint32_t lb[U];
+  // Groups of 4 consecutive records from rb rounded down to a multiple of 4
+  // (record arrays are 256-byte aligned): 8-byte bin and 16-byte value loads.
+  constexpr int G = 2;
+  const uint32_t r0 = rb & ~3u;
+  for (uint32_t base = r0; base < re; base += 4 * G * blockDim.x) {
+    uint32_t lb[4 * G];
+    bool full[G];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint32_t r = base + u * blockDim.x + threadIdx.x;
-      lb[u] = r < re ? (uint32_t)__builtin_nontemporal_load(a.rec_bin + r) : 0xFFFFFFFFu;
+    for (int g = 0; g < G; ++g) {
+      const uint32_t r = base + 4 * (g * blockDim.x + threadIdx.x);
+      full[g] = r >= rb && r + 4 <= re;
+      if (full[g]) {
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        const u32x2 w = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(a.rec_bin + r));
+        lb[4 * g] = w.x & 0xFFFFu;
+        lb[4 * g + 1] = w.x >> 16;
+        lb[4 * g + 2] = w.y & 0xFFFFu;
+        lb[4 * g + 3] = w.y >> 16;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          lb[4 * g + e] = (r + e >= rb && r + e < re) ? (uint32_t)__builtin_nontemporal_load(a.rec_bin + r + e)
+                                                      : 0xFFFFFFFFu;
+      }
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+    for (int u = 0; u < 4 * G; ++u)
       if (lb[u] != 0xFFFFFFFFu) TL::count(smem, (int)lb[u]);
     for (int j = 0; j < k; ++j) {
-      AT v[U];
+      AT v[4 * G];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const uint32_t r = base + u * blockDim.x + threadIdx.x;
-        v[u] = lb[u] != 0xFFFFFFFFu ? __builtin_nontemporal_load(static_cast<const AT*>(a.rec_val[j]) + r) : AT(0);
+      for (int g = 0; g < G; ++g) {
+        const uint32_t r = base + 4 * (g * blockDim.x + threadIdx.x);
+        if (full[g]) {
+          ld4<AT>(a.rec_val[j], r, re, true, v + 4 * g);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            v[4 * g + e] = lb[4 * g + e] != 0xFFFFFFFFu ? ld<AT>(a.rec_val[j], r + e) : AT(0);
+        }
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u)
+      for (int u = 0; u < 4 * G; ++u)
         if (lb[u] != 0xFFFFFFFFu) TL::add(smem, a.lay, j, (int)lb[u], v[u]);
     }
   }

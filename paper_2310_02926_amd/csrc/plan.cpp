@@ -171,8 +171,11 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints_
     int64_t grid = std::min<int64_t>(ceil_div(std::max<int64_t>(n, 1), min_chunk), (int64_t)cus * per_cu);
     if (hints.grid) grid = hints.grid;
     grid = std::max<int64_t>(grid, 1);
-    a.chunk = ceil_div(std::max<int64_t>(n, 1), grid);
+    a.chunk = ceil_div(ceil_div(std::max<int64_t>(n, 1), grid), 64) * 64;
     c.grid = (int)ceil_div(std::max<int64_t>(n, 1), a.chunk);
+    bool aligned = ((uintptr_t)a.x % 16 == 0) && ((uintptr_t)a.y % 16 == 0);
+    for (int j = 0; j < nk; ++j) aligned = aligned && ((uintptr_t)a.attr[j] % 16 == 0);
+    a.vec = aligned ? 1 : 0;
     a.nslots = c.grid;
     if (a.nslots > 1) a.partial = cv.take((size_t)a.lay.slot_bytes * a.nslots);
     p->scratch_bytes = cv.used;
@@ -199,8 +202,13 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints_
     if (hints.grid) nwg = std::min<int64_t>(hints.grid, 65535);
     if (hints.part_wg) nwg = hints.part_wg;
     nwg = std::max<int64_t>(nwg, 1);
-    a.chunk = ceil_div(std::max<int64_t>(n, 1), nwg);
+    // Slices start at multiples of 64 particles so that aligned columns are
+    // read with 16-byte loads.
+    a.chunk = ceil_div(ceil_div(std::max<int64_t>(n, 1), nwg), 64) * 64;
     a.nwg = (int32_t)ceil_div(std::max<int64_t>(n, 1), a.chunk);
+    bool aligned = ((uintptr_t)a.x % 16 == 0) && ((uintptr_t)a.y % 16 == 0);
+    for (int j = 0; j < nk; ++j) aligned = aligned && ((uintptr_t)a.attr[j] % 16 == 0);
+    a.vec = aligned ? 1 : 0;
     // split length: no split when tiles are balanced, bounded work otherwise
     int64_t L = std::max<int64_t>({ceil_div(3 * n, 2 * ntiles), ceil_div(n, 2 * (int64_t)cus), 16384});
     if (hints.split_len) L = hints.split_len;
@@ -211,12 +219,13 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints_
     // 1- and 4-attribute workloads (one workgroup per CU, LDS-bound).
     // Largest scatter stage that fits LDS: 1024 threads first (fastest on
     // MI355X), fewer particles per thread, then fewer threads (many
-    // attributes).  32 particles per thread need more than the 128 VGPRs a
-    // 1024-thread workgroup allows.
+    // attributes).  A 1024-thread workgroup allows 128 VGPRs per lane: 16
+    // f32 or 8 f64 coordinate pairs per thread (more would spill).
     int nt = 0, ppt = 0;
     size_t sc = 0;
     for (int tnt = hints.scatter_threads ? hints.scatter_threads : 1024; tnt >= 256 && !ppt; tnt /= 2) {
-      for (int tp = std::min(hints.scatter_ppt ? hints.scatter_ppt : 16, tnt >= 1024 ? 16 : 32); tp >= 4; tp /= 2) {
+      const int cap = tnt >= 1024 ? (p->coord_f64 ? 8 : 16) : 32;
+      for (int tp = std::min(hints.scatter_ppt ? hints.scatter_ppt : 16, cap); tp >= 4; tp /= 2) {
         const size_t S = (size_t)tnt * tp;
         const int32_t svo = (int32_t)align16(12 * (size_t)T + 4 * S);
         const size_t need = svo + S * nk * asz;
@@ -355,16 +364,16 @@ std::string describe(const Prepared& p) {
   const char* prec = p.prec == bk::PREC_PLAIN ? "fp32" : p.prec == bk::PREC_F64 ? "fp64" : "fp32-comp";
   switch (p.cfg.strategy) {
     case bk::STRAT_LDS:
-      snprintf(buf, sizeof buf, "lds grid=%d block=%d lds=%zu chunk=%lld prec=%s", p.cfg.grid, p.cfg.block,
-               p.cfg.lds_bytes, (long long)p.lds.chunk, prec);
+      snprintf(buf, sizeof buf, "lds grid=%d block=%d lds=%zu chunk=%lld vec=%d prec=%s", p.cfg.grid,
+               p.cfg.block, p.cfg.lds_bytes, (long long)p.lds.chunk, p.lds.vec, prec);
       break;
     case bk::STRAT_PART:
       snprintf(buf, sizeof buf,
                "partition tiles=%d tile_bins=%d wg=%d chunk=%lld threads=%d ppt=%d split=%u max_items=%d "
-               "scatter_lds=%zu bin_lds=%zu prec=%s",
+               "scatter_lds=%zu bin_lds=%zu vec=%d prec=%s",
                p.part.ntiles, 1 << p.part.lay.tile_shift, p.part.nwg, (long long)p.part.chunk, p.pcfg.scatter_threads,
                p.pcfg.ppt,
-               p.part.split_len, p.part.max_items, p.pcfg.scatter_lds, p.pcfg.bin_lds, prec);
+               p.part.split_len, p.part.max_items, p.pcfg.scatter_lds, p.pcfg.bin_lds, p.part.vec, prec);
       break;
     default:
       snprintf(buf, sizeof buf, "global grid=%d block=%d prec=%s", p.cfg.grid, p.cfg.block, prec);

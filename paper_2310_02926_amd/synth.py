@@ -14,6 +14,8 @@ is not available, so the generators below stand in for it:
 * ``hotspot_f32``   - 90% of the particles inside a random 1% of the bins of a
   square grid, the rest uniform, lognormal(0,2) mass, f32.
 * ``batch_instances`` - many independent requests of uneven size.
+* ``insitu_table``  - ten N-body-like variables binned over nine coordinate
+  systems (the multi-grid in situ load of Section 4.3).
 
 Every generator uses NumPy's PCG64 (``numpy.random.default_rng``) and returns
 particles in shuffled order (no spatial locality), columns as separate
@@ -231,3 +233,34 @@ def edge_points(lo: float, hi: float, nbins: int, dtype=np.float64) -> np.ndarra
     pts = [e, np.nextafter(e, dt.type(-np.inf)), np.nextafter(e, dt.type(np.inf)),
            np.array([lo, hi, np.nan, np.inf, -np.inf, lo - (hi - lo), hi + (hi - lo)], dtype=dt)]
     return np.concatenate(pts).astype(dt)
+
+
+# Columns of the in situ table and the coordinate systems binned over it.
+INSITU_COLUMNS = ("x", "y", "z", "vx", "vy", "vz", "ax", "ay", "az", "m")
+INSITU_PLANES = ((0, 1), (0, 2), (1, 2), (3, 4), (3, 5), (4, 5), (6, 7), (6, 8), (7, 8))
+
+
+@dataclass
+class InsituTable:
+    columns: List[np.ndarray]
+    planes: Sequence[tuple]
+    bounds: List[tuple]
+    n: int
+
+
+def insitu_table(n: int = 1 << 20, seed: int = 0, dtype=np.float32) -> InsituTable:
+    """An N-body-like particle table for the multi-grid in situ load: ten
+    variables (position uniform in [-1,1)^3, velocity and acceleration
+    N(0,1) per component, mass lognormal(0,1)) binned over nine coordinate
+    systems: the three planes of position, of velocity and of acceleration.
+    Bounds: [-1,1] for positions, [-4,4] for the other planes (particles
+    beyond 4 sigma fall outside)."""
+    rng = np.random.default_rng(seed)
+    cols = [rng.uniform(-1.0, 1.0, n).astype(dtype) for _ in range(3)]
+    cols += [rng.standard_normal(n).astype(dtype) for _ in range(6)]
+    cols.append(rng.lognormal(0.0, 1.0, n).astype(dtype))
+    bounds = []
+    for a, b in INSITU_PLANES:
+        lo, hi = (-1.0, 1.0) if a < 3 else (-4.0, 4.0)
+        bounds.append((lo, hi, lo, hi))
+    return InsituTable(cols, INSITU_PLANES, bounds, n)

@@ -121,3 +121,23 @@ def test_single_hip_runtime_mapped():
     maps = open("/proc/self/maps").read()
     libs = {l.split()[-1] for l in maps.splitlines() if "libamdhip64" in l}
     assert len(libs) == 1, libs
+
+
+def test_multi_grid_rejects_bad_specs_before_any_hip_call():
+    a = good()
+    grid = dict(axes=(0, 2), bounds=(0.0, 1.0, 0.0, 1.0), nx=16, ny=8, ops=B.OPS_ALL, out=a["out"])
+    bad = dict(grid, nx=0)
+    with pytest.raises(B.BinError) as ei:
+        B.bin_particles_multi(a["coords"], a["attrs"], 1000, [grid, bad], stream=0, coord_dtype=B.BIN_F32,
+                              attr_dtype=B.BIN_F32)
+    assert ei.value.status == B.BIN_ERR_INVALID_ARG
+    assert "request 1" in B.last_error(), B.last_error()
+    with pytest.raises(B.BinError) as ei:
+        B.bin_particles_multi(a["coords"], a["attrs"], 1000, [dict(grid, axes=(0, 3))], stream=0,
+                              coord_dtype=B.BIN_F32, attr_dtype=B.BIN_F32)
+    assert ei.value.status == B.BIN_ERR_INVALID_ARG
+    L = B.lib()
+    assert L.bin_particles_multi(None, None, 0, None, 0, None) == B.BIN_ERR_INVALID_ARG
+    c, keep = B.columns([F, F + 0x100], B.BIN_F32)
+    assert L.bin_particles_multi(ctypes.byref(c), None, 10, None, 2, None) == B.BIN_ERR_INVALID_ARG
+    assert L.bin_particles_multi(ctypes.byref(c), None, 10, None, -1, None) == B.BIN_ERR_INVALID_ARG

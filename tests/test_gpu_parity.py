@@ -305,3 +305,36 @@ def test_auto_bounds_degenerate(strategy):
     ws = _ws([np.full(n, np.nan), rng.random(n)], [rng.standard_normal(n)], 8, 8)
     got = _run_auto(ws, strategy)
     assert got["count"].sum() == 0 and np.all(np.isnan(got["avg"][0]))
+
+
+@pytest.mark.parametrize("strategy", [pytest.param(1, id="lds"), pytest.param(2, id="part")])
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("shift", [0, 1, 3])
+def test_unaligned_columns_take_the_narrow_load_path(strategy, dtype, shift):
+    """Columns that start off a 16-byte boundary (views into larger buffers)
+    are read element by element; results equal the aligned case's oracle."""
+    from paper_2310_02926_amd import binding as B
+    _case(f"unaligned columns shift={shift} dtype={np.dtype(dtype).name} strategy={strategy}")
+    rng = np.random.default_rng(100 + shift)
+    n = 1_000_037
+    side = 64 if strategy == 1 else 1024
+    ws = _ws([rng.uniform(-0.05, 1.05, n).astype(dtype), rng.uniform(-0.05, 1.05, n).astype(dtype)],
+             [rng.standard_normal(n).astype(np.float32), rng.lognormal(0, 1, n).astype(np.float32)], side, side)
+    dev_c, dev_a = G.to_device(ws)
+    # the first coordinate column and the second attribute start `shift` elements into their buffers
+    xbuf = torch.empty(n + shift, dtype=dev_c[0].dtype, device="cuda")
+    xbuf[shift:] = dev_c[0]
+    abuf = torch.empty(n + shift, dtype=dev_a[1].dtype, device="cuda")
+    abuf[shift:] = dev_a[1]
+    coords = [xbuf[shift:], dev_c[1]]
+    attrs = [dev_a[0], abuf[shift:]]
+    B.bin_set_plan_override(strategy, 0, 0)
+    try:
+        out = B.alloc_outputs(attrs, ws.nx, ws.ny, 31, "cuda")
+        req, keep = B.request(coords, attrs, n, ws.axes, ws.bounds, ws.nx, ws.ny, 31, out)
+        desc = B.bin_describe_plan(req)
+        assert f"vec={0 if shift else 1}" in desc, desc
+        got = G.run_gpu(ws, coords=coords, attrs=attrs)
+    finally:
+        B.bin_set_plan_override(-1, 0, 0)
+    G.assert_parity(got, G.oracle(ws), 31, what=f"unaligned shift={shift}")
