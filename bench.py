@@ -1,7 +1,7 @@
 """Benchmark: particle binning throughput on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--workload hotspot|gmm|uniform|batched|served]
+                    [--workload hotspot|gmm|uniform|batched|served|insitu]
 
 hotspot / gmm / uniform: one step = one bin_particles call over the whole
 particle set (init, bin, finalize), inputs resident in HBM.  Prints one JSON
@@ -17,6 +17,10 @@ one-at-a-time calls, all timed on the same stream.
 served: Poisson arrival streams of requests drawn from the batched set,
 served by the continuous-batching server (64 GB budget) and, for
 comparison, one request at a time; p50/p99 latency and throughput per rate.
+
+insitu: a synthetic solver and the binning of its particles on one GPU:
+solver alone, lockstep zero-copy binning, and the asynchronous deep-copy
+mode on a second stream (solver slowdown, apparent in situ time).
 """
 from __future__ import annotations
 
@@ -354,12 +358,96 @@ def run_served(args):
     print(json.dumps(rec), flush=True)
 
 
+def run_insitu(args):
+    """Same-device in situ coupling: a synthetic solver (particle push plus a
+    chain of bf16 matrix products standing in for the force computation) and
+    the binning of its particles every step, three ways: solver alone,
+    lockstep zero-copy binning on the solver's stream, and the asynchronous
+    mode (deep copy on the solver's stream, binning on a second stream)."""
+    import torch
+    from paper_2310_02926_amd import binding as B
+    from paper_2310_02926_amd import synth
+    n = (1 << 24) >> args.scale
+    side = 1024
+    ws = synth.gmm_f32(n=n, seed=3, nx=side, ny=side, k=1)
+    dev = torch.device("cuda:0")
+    x, y = (torch.from_numpy(c).to(dev) for c in ws.coords)
+    m = torch.from_numpy(ws.attrs[0]).to(dev)
+    g = torch.Generator(device="cpu").manual_seed(3)
+    vx = (torch.randn(n, generator=g) * 1e-3).to(dev)
+    vy = (torch.randn(n, generator=g) * 1e-3).to(dev)
+    h = torch.randn(4096, 4096, generator=g).to(dev, torch.bfloat16)
+    w = (torch.randn(4096, 4096, generator=g) / 64).to(dev, torch.bfloat16)
+    outs = B.alloc_outputs([m], side, side, 31, dev)
+    src, bs = torch.cuda.Stream(), torch.cuda.Stream()
+    bounds = (0.0, 1.0, 0.0, 1.0)
+
+    def solver():
+        nonlocal h
+        x.add_(vx).remainder_(1.0)
+        y.add_(vy).remainder_(1.0)
+        for _ in range(4):
+            h = torch.mm(h, w)
+
+    def step_solver():
+        with torch.cuda.stream(src):
+            solver()
+
+    def step_lockstep():
+        with torch.cuda.stream(src):
+            solver()
+            B.bin_particles([x, y], [m], n, (0, 1), bounds, side, side, 31, outs, stream=src)
+
+    def step_async():
+        with torch.cuda.stream(src):
+            solver()
+            B.bin_particles_async([x, y], [m], n, (0, 1), bounds, side, side, 31, outs, src_stream=src,
+                                  bin_stream=bs)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e_src, e_bs = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(src)
+        bs.wait_event(e0)
+        for _ in range(args.steps):
+            fn()
+        e_src.record(src)
+        e_bs.record(bs)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e_src) / args.steps, max(e0.elapsed_time(e_src), e0.elapsed_time(e_bs)) / args.steps
+
+    def bin_alone():
+        B.bin_particles([x, y], [m], n, (0, 1), bounds, side, side, 31, outs, stream=src)
+
+    t_bin, _ = timed(bin_alone)
+    t_solver, _ = timed(step_solver)
+    t_lock, _ = timed(step_lockstep)
+    t_async_solver, t_async = timed(step_async)
+    rec = {
+        "metric": METRIC, "value": round(n / (t_bin / 1e3) / 1e9, 3), "unit": "Gparticles/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_async, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "insitu_same_device_16M_1024sq", "n": n, "grid": f"{side}x{side}",
+                   "solver": "particle push + 4 bf16 4096^3 matrix products per step"},
+        "insitu": {"bin_alone_ms": round(t_bin, 4), "solver_alone_ms": round(t_solver, 4),
+                   "lockstep_step_ms": round(t_lock, 4), "async_step_ms": round(t_async, 4),
+                   "async_solver_stream_ms": round(t_async_solver, 4),
+                   "lockstep_insitu_ms": round(t_lock - t_solver, 4),
+                   "async_apparent_insitu_ms": round(t_async - t_solver, 4),
+                   "async_solver_slowdown": round(t_async_solver / t_solver, 4)},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="hotspot", choices=["hotspot", "gmm", "uniform", "batched", "served"])
+    ap.add_argument("--workload", default="hotspot", choices=["hotspot", "gmm", "uniform", "batched", "served", "insitu"])
     ap.add_argument("--prec", default="default", choices=["default", "comp", "plain", "f64"])
     ap.add_argument("--scale", type=int, default=0, help="shrink n by 2^scale (quick runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -373,6 +461,8 @@ def main():
         return run_batched(args)
     if args.workload == "served":
         return run_served(args)
+    if args.workload == "insitu":
+        return run_insitu(args)
 
     import torch
     from paper_2310_02926_amd import binding as B

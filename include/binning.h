@@ -170,6 +170,26 @@ int bin_validate(const bin_columns* coords, const bin_columns* attrs, int64_t n,
  * request array is read during the call only.  Enqueues and returns. */
 int bin_particles_batched(const bin_request* reqs, int32_t nreq, void* stream);
 
+/* ---- asynchronous in situ binning ------------------------------------------ */
+/* The asynchronous mode of the paper (Section 2, used in the runs of Section
+ * 4.3): the simulation hands its data over and carries on at once while the
+ * analysis works on a deep copy.  Arguments as bin_particles, plus:
+ *  src_stream  the simulation's stream.  The columns the request reads (the
+ *              two axis columns and the attributes) are copied device to
+ *              device on it, into staging memory that the library allocates
+ *              in that stream's order.  Work the caller enqueues on
+ *              src_stream after this call runs after the copy, so it may
+ *              overwrite the columns at once.
+ *  bin_stream  the analysis stream.  It waits for the copy (an event), bins
+ *              from the staged copy and frees it in its own order.  The
+ *              outputs are valid once bin_stream has completed the call.
+ * The two streams may be the same.  Returns BIN_OK once everything is
+ * enqueued; errors as bin_particles, plus BIN_ERR_OOM when staging memory
+ * cannot be allocated.  Never synchronises. */
+int bin_particles_async(const bin_columns* coords, const bin_columns* attrs, int64_t n,
+                        const int32_t axes[2], const double bounds[4], int32_t nx, int32_t ny,
+                        uint32_t ops, const bin_output* out, void* src_stream, void* bin_stream);
+
 /* ---- several grids over one particle table --------------------------------- */
 /* One binning of the table per grid spec.  The in situ load of the paper's
  * experiments (Section 4.3) bins the same variables over several coordinate

@@ -29,7 +29,7 @@ MAX_ATTRS = 16
 
 #: Every function declared in include/binning.h.
 EXPORTS = (
-    "bin_particles", "bin_validate", "bin_particles_batched", "bin_particles_multi", "bin_graph_create", "bin_graph_launch",
+    "bin_particles", "bin_validate", "bin_particles_async", "bin_particles_batched", "bin_particles_multi", "bin_graph_create", "bin_graph_launch",
     "bin_graph_destroy", "bin_autotune", "bin_status_string", "bin_last_error_message",
     "bin_stream_status", "bin_release_workspace", "bin_version", "bin_timing_enable", "bin_timing_read",
     "bin_timing_report",
@@ -103,6 +103,9 @@ def lib() -> ctypes.CDLL:
                                   POINTER(c_double), c_int32, c_int32, c_uint32, POINTER(Output), c_void_p]),
         "bin_validate": (c_int, [POINTER(Columns), POINTER(Columns), c_int64, POINTER(c_int32),
                                  POINTER(c_double), c_int32, c_int32, c_uint32, POINTER(Output)]),
+        "bin_particles_async": (c_int, [POINTER(Columns), POINTER(Columns), c_int64, POINTER(c_int32),
+                                        POINTER(c_double), c_int32, c_int32, c_uint32, POINTER(Output), c_void_p,
+                                        c_void_p]),
         "bin_particles_batched": (c_int, [POINTER(Request), c_int32, c_void_p]),
         "bin_particles_multi": (c_int, [POINTER(Columns), POINTER(Columns), c_int64, POINTER(GridSpec), c_int32,
                                         c_void_p]),
@@ -224,6 +227,19 @@ def bin_particles(coords, attrs, n: int, axes, bounds, nx: int, ny: int, ops: in
     st = lib().bin_particles(ctypes.byref(c), ctypes.byref(a) if a is not None else None, n, ax, bd,
                              nx, ny, ops, ctypes.byref(o), _stream_handle(stream))
     check(st)
+
+
+def bin_particles_async(coords, attrs, n: int, axes, bounds, nx: int, ny: int, ops: int, out: Dict,
+                        src_stream=None, bin_stream=None, coord_dtype=None, attr_dtype=None) -> None:
+    """Deep-copy the request's columns on src_stream and bin the copy on
+    bin_stream (the asynchronous in situ mode); see the C header."""
+    c, ck = columns(coords, coord_dtype)
+    a, ak = columns(attrs, attr_dtype) if attrs is not None else (None, None)
+    o, ok = output(out.get("count"), out.get("sum"), out.get("min"), out.get("max"), out.get("avg"))
+    ax = (c_int32 * 2)(*axes)
+    bd = (c_double * 4)(*bounds) if bounds is not None else None
+    check(lib().bin_particles_async(ctypes.byref(c), ctypes.byref(a) if a is not None else None, n, ax, bd, nx, ny,
+                                    ops, ctypes.byref(o), _stream_handle(src_stream), _stream_handle(bin_stream)))
 
 
 def bin_validate(coords, attrs, n, axes, bounds, nx, ny, ops, out, coord_dtype=None, attr_dtype=None) -> int:

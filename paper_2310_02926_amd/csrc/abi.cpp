@@ -115,6 +115,64 @@ int bin_particles(const bin_columns* coords, const bin_columns* attrs, int64_t n
   return run_request(r, s, thread_hints());
 }
 
+int bin_particles_async(const bin_columns* coords, const bin_columns* attrs, int64_t n, const int32_t axes[2],
+                        const double bounds[4], int32_t nx, int32_t ny, uint32_t ops, const bin_output* out,
+                        void* src_stream, void* bin_stream) {
+  clear_error();
+  int st = validate(coords, attrs, n, axes, bounds, nx, ny, ops, out, true);
+  if (st) return st;
+  hipStream_t ss = static_cast<hipStream_t>(src_stream);
+  hipStream_t bs = static_cast<hipStream_t>(bin_stream);
+  st = precheck_stream(ss);
+  if (st) return st;
+  st = precheck_stream(bs);
+  if (st) return st;
+  const int k = attrs ? attrs->ncols : 0;
+  const size_t csz = coords->dtype == BIN_F64 ? 8 : 4;
+  const size_t asz = (k && attrs->dtype == BIN_F64) ? 8 : 4;
+  const size_t ccol = (size_t)n * csz, acol = (size_t)n * asz;
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t bytes = 2 * al(ccol) + (size_t)k * al(acol);
+  if (bytes == 0) {  // nothing to copy: order the binning after src's work
+    bin_request r = make_request(coords, attrs, n, axes, bounds, nx, ny, ops, out);
+    hipEvent_t ev = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, ss);
+    if (e == hipSuccess) e = hipStreamWaitEvent(bs, ev, 0);
+    if (ev) (void)hipEventDestroy(ev);
+    if (e != hipSuccess) return hip_fail(e, "order binning after source stream");
+    return bounds ? run_request(r, bs, thread_hints()) : run_auto_bounds(r, bs);
+  }
+  DeviceInfo dev;
+  st = device_info(&dev);
+  if (st) return st;
+  const void* ccols[2];
+  const void* acols[BIN_MAX_ATTRS];
+  auto copy = [&](void* stage) -> int {
+    unsigned char* p = static_cast<unsigned char*>(stage);
+    size_t o = 0;
+    for (int c = 0; c < 2; ++c, o += al(ccol)) {
+      ccols[c] = p + o;
+      const hipError_t e = hipMemcpyAsync(p + o, coords->cols[axes[c]], ccol, hipMemcpyDeviceToDevice, ss);
+      if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(staging)");
+    }
+    for (int j = 0; j < k; ++j, o += al(acol)) {
+      acols[j] = p + o;
+      const hipError_t e = hipMemcpyAsync(p + o, attrs->cols[j], acol, hipMemcpyDeviceToDevice, ss);
+      if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(staging)");
+    }
+    return BIN_OK;
+  };
+  auto bin = [&](void*) -> int {
+    bin_columns sc{reinterpret_cast<const void* const*>(ccols), 2, coords->dtype};
+    bin_columns sa{reinterpret_cast<const void* const*>(acols), k, k ? attrs->dtype : BIN_F32};
+    const int32_t sax[2] = {0, 1};
+    bin_request r = make_request(&sc, k ? &sa : nullptr, n, sax, bounds, nx, ny, ops, out);
+    return bounds ? run_request(r, bs, thread_hints()) : run_auto_bounds(r, bs);
+  };
+  return stage_run(dev.device, ss, bs, bytes, copy, bin);
+}
+
 int bin_set_plan_override(int32_t strategy, int32_t block, int32_t grid) {
   clear_error();
   if (strategy < -1 || strategy > 2) return fail(BIN_ERR_INVALID_ARG, "strategy must be -1, 0, 1 or 2");
@@ -182,7 +240,9 @@ int bin_stream_status(void* stream) {
 
 int bin_release_workspace(void) {
   clear_error();
-  return release_all_scratch();
+  int st = release_all_scratch();  // synchronises the device first
+  const int st2 = release_all_staging();
+  return st ? st : st2;
 }
 
 const char* bin_version(void) { return "0.1.0"; }

@@ -139,7 +139,7 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
     size_t scatter_lds = 16;
     for (int r = 0; r < R; ++r) {
       const Prepared& p = bp->preps[g.idx[r]];
-      const size_t sv = al16(12 * (size_t)p.part.ntiles + 4 * S);
+      const size_t sv = al16(20 * (size_t)p.part.ntiles + 4 * S);
       scatter_lds = std::max(scatter_lds, sv + S * p.part.k * asz);
     }
     g.cfg.ppt = ppt;
@@ -173,7 +173,7 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
       a.tile_items = tile_items ? tile_items + 3 * tb : nullptr;
       a.rec_bin = rec_bin;
       for (int j = 0; j < a.k; ++j) a.rec_val[j] = rec_val[j];
-      a.stage_val_off = (int32_t)al16(12 * (size_t)a.ntiles + 4 * S);
+      a.stage_val_off = (int32_t)al16(20 * (size_t)a.ntiles + 4 * S);
       a.partial = a.max_slots > 0 ? take((size_t)a.lay.slot_bytes * a.max_slots) : nullptr;
       g.args[r] = a;
       cb += m;

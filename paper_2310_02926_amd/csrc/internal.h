@@ -6,6 +6,7 @@
 #include <stdarg.h>
 
 #include <atomic>
+#include <functional>
 #include <string>
 
 #include "../../include/binning.h"
@@ -49,6 +50,13 @@ int device_info(DeviceInfo* info);
 // scratch pools
 int scratch_get(int dev, hipStream_t s, size_t bytes, void** out);
 int release_all_scratch();
+// Asynchronous mode: copy(stage) enqueues the deep copy on src into a
+// staging buffer of at least 'bytes'; bin(stage) enqueues the binning on bs,
+// which is ordered after the copy.  Buffers are reused once their binning
+// has completed.
+int stage_run(int device, hipStream_t src, hipStream_t bs, size_t bytes,
+              const std::function<int(void* stage)>& copy, const std::function<int(void* stage)>& bin);
+int release_all_staging();
 bool fault_injection_hit();
 
 // kernel timing (bin_timing_*): a timer for one call, or null when off

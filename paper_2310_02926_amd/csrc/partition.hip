@@ -237,18 +237,28 @@ __global__ __launch_bounds__(1024) void part_items_batched(const PartArgs* __res
 // request are read with 16-byte loads and no bounds tests, and the next
 // one's coordinates are loaded while the current one is sorted and written;
 // the remainder (and unaligned requests) take a bounds-tested path.
-// LDS: cnt[T] | off[T] | run[T] | (tile << 16 | local bin)[S] | values[k][S]
+// Three barriers per sub-chunk: the tile counters are double-buffered, and
+// one wave scans them, advances the run heads by the previous sub-chunk's
+// counts and clears that buffer.
+// LDS: cnt[2][T] | off[T] | delta[T] | run[T] | (tile << 16 | local bin)[S] |
+//      values[k][S]
 // ---------------------------------------------------------------------------
+struct ScatterShared {
+  uint32_t nsub;
+};
+
 template <typename CT, typename AT, int PPT, int NT, bool FULL>
-__device__ __forceinline__ void scatter_sub(const PartArgs& a, unsigned char* smem, uint32_t* wave_tot,
+__device__ __forceinline__ void scatter_sub(const PartArgs& a, unsigned char* smem, ScatterShared& sh,
                                             const Axis& ax, const Axis& ay, int64_t base, int64_t hi,
-                                            int64_t full_end, CT* px, CT* py) {
+                                            int64_t full_end, int parity, CT* px, CT* py) {
   constexpr int S = NT * PPT;
   constexpr int Q = PPT / 4;
   const int T = a.ntiles;
-  uint32_t* cnt = reinterpret_cast<uint32_t*>(smem);
-  uint32_t* off = cnt + T;
-  uint32_t* run = off + T;
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(smem) + parity * T;
+  uint32_t* cprev = reinterpret_cast<uint32_t*>(smem) + (parity ^ 1) * T;
+  uint32_t* off = reinterpret_cast<uint32_t*>(smem) + 2 * T;
+  uint32_t* delta = off + T;
+  uint32_t* run = delta + T;
   uint32_t* stg_tb = run + T;
   AT* stg_v = reinterpret_cast<AT*>(smem + a.stage_val_off);
   const int shift = a.lay.tile_shift;
@@ -283,15 +293,34 @@ __device__ __forceinline__ void scatter_sub(const PartArgs& a, unsigned char* sm
     }
   }
   __syncthreads();
-  uint32_t carry = 0;
-  for (int t0 = 0; t0 < T; t0 += NT) {
-    const int t = t0 + threadIdx.x;
-    uint32_t tot;
-    const uint32_t ex = block_scan_excl<NT>(t < T ? cnt[t] : 0u, wave_tot, tot);
-    if (t < T) off[t] = carry + ex;
-    carry += tot;
+  if (threadIdx.x < 64) {  // one wave: lane l owns tiles [l * m, l * m + m)
+    const int lane = threadIdx.x;
+    const int m = (T + 63) >> 6;
+    const int t0 = lane * m;
+    uint32_t own = 0;
+    for (int q = 0; q < m; ++q)
+      if (t0 + q < T) own += cnt[t0 + q];
+    uint32_t x = own;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    uint32_t o0 = x - own;
+    for (int q = 0; q < m; ++q) {
+      const int t = t0 + q;
+      if (t < T) {
+        const uint32_t c = cnt[t];
+        const uint32_t r = run[t] + cprev[t];
+        run[t] = r;
+        cprev[t] = 0u;
+        off[t] = o0;
+        delta[t] = r - o0;
+        o0 += c;
+      }
+    }
+    if (lane == 63) sh.nsub = x;
   }
-  const uint32_t nsub = carry;
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < PPT; ++u) {
@@ -315,34 +344,29 @@ __device__ __forceinline__ void scatter_sub(const PartArgs& a, unsigned char* sm
   }
   __syncthreads();
   // Consecutive p of one tile go to consecutive record addresses.
+  const uint32_t nsub = sh.nsub;
   for (uint32_t p = threadIdx.x; p < nsub; p += NT) {
     const uint32_t v = stg_tb[p];
-    const uint32_t t = v >> 16;
-    const uint32_t dst = run[t] + (p - off[t]);
+    const uint32_t dst = delta[v >> 16] + p;
     a.rec_bin[dst] = (uint16_t)(v & 0xFFFFu);
     for (int j = 0; j < k; ++j) static_cast<AT*>(a.rec_val[j])[dst] = stg_v[(int64_t)j * S + p];
   }
-  __syncthreads();
-  for (int t = threadIdx.x; t < T; t += NT) {
-    run[t] += cnt[t];
-    cnt[t] = 0u;
-  }
-  __syncthreads();
 }
 
 template <typename CT, typename AT, int PPT, int NT>
 __device__ __forceinline__ void part_scatter_body(const PartArgs& a, int wg) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ uint32_t wave_tot[NT / 64];
+  __shared__ ScatterShared sh;
   constexpr int S = NT * PPT;
   constexpr int Q = PPT / 4;
   const int T = a.ntiles;
   uint32_t* cnt = reinterpret_cast<uint32_t*>(smem);
-  uint32_t* run = cnt + 2 * T;
+  uint32_t* run = cnt + 4 * T;
   Axis ax = a.ax, ay = a.ay;
   resolve_axes(a.dyn, ax, ay);
   for (int t = threadIdx.x; t < T; t += NT) {
     cnt[t] = 0u;
+    cnt[T + t] = 0u;
     run[t] = a.counts[(int64_t)t * a.nwg + wg];
   }
   const int64_t lo = (int64_t)wg * a.chunk;
@@ -358,9 +382,10 @@ __device__ __forceinline__ void part_scatter_body(const PartArgs& a, int wg) {
     }
   }
   __syncthreads();
-  for (int64_t base = lo; base < full_end; base += S)
-    scatter_sub<CT, AT, PPT, NT, true>(a, smem, wave_tot, ax, ay, base, hi, full_end, px, py);
-  for (int64_t base = full_end; base < hi; base += S) {
+  int parity = 0;
+  for (int64_t base = lo; base < full_end; base += S, parity ^= 1)
+    scatter_sub<CT, AT, PPT, NT, true>(a, smem, sh, ax, ay, base, hi, full_end, parity, px, py);
+  for (int64_t base = full_end; base < hi; base += S, parity ^= 1) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int64_t i = base + 4 * ((int64_t)q * NT + threadIdx.x);
@@ -370,7 +395,7 @@ __device__ __forceinline__ void part_scatter_body(const PartArgs& a, int wg) {
         py[4 * q + e] = i + e < hi ? ld<CT>(a.y, i + e) : CT(0);
       }
     }
-    scatter_sub<CT, AT, PPT, NT, false>(a, smem, wave_tot, ax, ay, base, hi, full_end, px, py);
+    scatter_sub<CT, AT, PPT, NT, false>(a, smem, sh, ax, ay, base, hi, full_end, parity, px, py);
   }
 }
 

@@ -214,7 +214,7 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints_
     if (hints.split_len) L = hints.split_len;
     a.split_len = (uint32_t)std::min<int64_t>(L, 0x7FFFFFFF);
     a.max_items = (int32_t)(ntiles + ceil_div(n, (int64_t)a.split_len));
-    // scatter LDS: 3 T counters, S tile/bin words, S * k values
+    // scatter LDS: 5 T counters, S tile/bin words, S * k values
     // 1024-thread scatter workgroups measured fastest on MI355X for both the
     // 1- and 4-attribute workloads (one workgroup per CU, LDS-bound).
     // Largest scatter stage that fits LDS: 1024 threads first (fastest on
@@ -227,7 +227,7 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints_
       const int cap = tnt >= 1024 ? (p->coord_f64 ? 8 : 16) : 32;
       for (int tp = std::min(hints.scatter_ppt ? hints.scatter_ppt : 16, cap); tp >= 4; tp /= 2) {
         const size_t S = (size_t)tnt * tp;
-        const int32_t svo = (int32_t)align16(12 * (size_t)T + 4 * S);
+        const int32_t svo = (int32_t)align16(20 * (size_t)T + 4 * S);
         const size_t need = svo + S * nk * asz;
         if (need + kScatterStatic <= lds_budget) {
           nt = tnt;

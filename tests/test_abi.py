@@ -141,3 +141,13 @@ def test_multi_grid_rejects_bad_specs_before_any_hip_call():
     c, keep = B.columns([F, F + 0x100], B.BIN_F32)
     assert L.bin_particles_multi(ctypes.byref(c), None, 10, None, 2, None) == B.BIN_ERR_INVALID_ARG
     assert L.bin_particles_multi(ctypes.byref(c), None, 10, None, -1, None) == B.BIN_ERR_INVALID_ARG
+
+
+def test_async_rejects_before_any_hip_call():
+    args = good(nx=0)
+    with pytest.raises(B.BinError) as ei:
+        B.bin_particles_async(**args, src_stream=0, bin_stream=0)
+    assert ei.value.status == B.BIN_ERR_INVALID_ARG
+    with pytest.raises(B.BinError) as ei:
+        B.bin_particles_async(**good(axes=(0, 5)), src_stream=0, bin_stream=0)
+    assert ei.value.status == B.BIN_ERR_INVALID_ARG
