@@ -106,9 +106,6 @@ def kernel_algorithmic_bytes(name: str, ws) -> int:
     kernel: the particle columns it must read, or the result grid it must
     write.  Intermediate records, counts and partials are not counted."""
     ins, outs = algorithmic_bytes(ws)
-    coords = sum(c.itemsize * c.size for c in ws.coords[:2])
-    if name == "part_count_kernel":
-        return coords
     if name in ("part_scatter_kernel", "bin_global_kernel", "bin_lds_kernel"):
         return ins
     if name in ("part_bin_kernel", "part_merge_kernel", "lds_merge_kernel", "bin_finalize_kernel"):

@@ -33,8 +33,8 @@ struct PartGroup {
   std::vector<bk::PartArgs> args;    // patched records
   bk::PartCfg cfg{};
   bk::PartBatch b{};
-  size_t desc_off = 0, map_wg_off = 0, map_item_off = 0, map_tile_off = 0;
-  std::vector<uint32_t> map_wg, map_item, map_tile;
+  size_t desc_off = 0, map_wg_off = 0, map_walk_off = 0, map_item_off = 0, map_tile_off = 0;
+  std::vector<uint32_t> map_wg, map_walk, map_item, map_tile;
 };
 
 struct LdsGroup {
@@ -117,85 +117,68 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
     // One scatter shape for the whole group: the smallest PPT any request
     // needs, staged values sized for the largest request.
     int ppt = 32, nt = 1024;
-    size_t count_lds = 16, bin_lds = 16;
+    size_t bin_lds = 16;
     int bin_block = 256;
-    int64_t M = 0, total_n = 0, total_items = 0, total_tiles = 0;
-    int kmax = 0;
     size_t asz = g.af64 ? 8 : 4;
     for (int r = 0; r < R; ++r) {
       const Prepared& p = bp->preps[g.idx[r]];
       ppt = std::min(ppt, p.pcfg.ppt);
       nt = std::min(nt, p.pcfg.scatter_threads);
-      count_lds = std::max(count_lds, p.pcfg.count_lds);
       bin_lds = std::max(bin_lds, p.pcfg.bin_lds);
       bin_block = std::max(bin_block, p.pcfg.bin_block);
-      M += (int64_t)p.part.ntiles * p.part.nwg;
-      total_n += std::max<int64_t>(p.part.n, 1);
-      total_items += p.part.max_items;
-      total_tiles += p.part.ntiles;
-      kmax = std::max(kmax, p.part.k);
     }
+    // The table-driven scatter needs a few more registers than the single
+    // one: 8 particles per thread at 1024 threads.
+    if (nt >= 1024) ppt = std::min(ppt, 8);
     const size_t S = (size_t)nt * ppt;
     size_t scatter_lds = 16;
     for (int r = 0; r < R; ++r) {
       const Prepared& p = bp->preps[g.idx[r]];
-      const size_t sv = al16(20 * (size_t)p.part.ntiles + 4 * S);
+      const size_t sv = al16(16 * (size_t)p.part.ntiles + 4 * S);
       scatter_lds = std::max(scatter_lds, sv + S * p.part.k * asz);
     }
     g.cfg.ppt = ppt;
     g.cfg.scatter_threads = nt;
     g.cfg.scatter_lds = scatter_lds;
-    g.cfg.count_lds = count_lds;
     g.cfg.bin_lds = bin_lds;
     g.cfg.bin_block = bin_block;
-    g.cfg.scan_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, cdiv(M, 4096)));
-    g.cfg.scan_per = cdiv(std::max<int64_t>(M, 1), g.cfg.scan_blocks);
     if (scatter_lds + 256 > dev.lds_per_block)
       return fail(BIN_ERR_UNSUPPORTED, "batched scatter stage does not fit LDS");
-    // shared scratch
-    uint32_t* counts = reinterpret_cast<uint32_t*>(take(4 * (size_t)std::max<int64_t>(M, 1)));
-    uint32_t* bsum = reinterpret_cast<uint32_t*>(take(4 * ((size_t)g.cfg.scan_blocks + 1)));
-    uint32_t* items = reinterpret_cast<uint32_t*>(take(12 * (size_t)total_items));
+    // Per-request scratch: tile totals, sub-chunk run tables, records,
+    // items and partial slots.
     uint32_t* n_items = reinterpret_cast<uint32_t*>(take(4 * (size_t)R));
-    uint32_t* tile_items = reinterpret_cast<uint32_t*>(take(12 * (size_t)total_tiles));
-    uint16_t* rec_bin = reinterpret_cast<uint16_t*>(take(2 * (size_t)total_n));
-    void* rec_val[bk::kMaxAttrs] = {};
-    for (int j = 0; j < kmax; ++j) rec_val[j] = take(asz * (size_t)total_n);
-    int64_t cb = 0, ib = 0, tb = 0;
     for (int r = 0; r < R; ++r) {
       bk::PartArgs a = bp->preps[g.idx[r]].part;
-      const int64_t m = (int64_t)a.ntiles * a.nwg;
-      a.counts = counts ? counts + cb : nullptr;
-      a.bsum = bsum;
-      a.inside = counts ? (r + 1 < R ? counts + cb + m : bsum + g.cfg.scan_blocks) : nullptr;
-      a.items = items ? items + 3 * ib : nullptr;
+      set_part_blocks(a, nt, ppt);
+      const size_t nrec = (size_t)std::max<int64_t>(a.n, 1);
+      a.counts = reinterpret_cast<uint32_t*>(take(4 * (size_t)a.ntiles * a.nwg));
+      a.blk_off = reinterpret_cast<uint32_t*>(take(4 * (size_t)a.nwg * a.nbpw * (size_t)(a.ntiles + 1)));
+      a.ilist = reinterpret_cast<uint32_t*>(take(4 * (size_t)a.ntiles * a.nwg));
+      a.items = reinterpret_cast<uint32_t*>(take(12 * (size_t)a.max_items));
       a.n_items = n_items ? n_items + r : nullptr;
-      a.tile_items = tile_items ? tile_items + 3 * tb : nullptr;
-      a.rec_bin = rec_bin;
-      for (int j = 0; j < a.k; ++j) a.rec_val[j] = rec_val[j];
-      a.stage_val_off = (int32_t)al16(20 * (size_t)a.ntiles + 4 * S);
+      a.tile_items = reinterpret_cast<uint32_t*>(take(12 * (size_t)a.ntiles));
+      a.rec_bin = reinterpret_cast<uint16_t*>(take(2 * nrec));
+      for (int j = 0; j < a.k; ++j) a.rec_val[j] = take(asz * nrec);
+      a.stage_val_off = (int32_t)al16(16 * (size_t)a.ntiles + 4 * S);
       a.partial = a.max_slots > 0 ? take((size_t)a.lay.slot_bytes * a.max_slots) : nullptr;
       g.args[r] = a;
-      cb += m;
-      ib += a.max_items;
-      tb += a.ntiles;
     }
-    g.b.counts = counts;
-    g.b.bsum = bsum;
-    g.b.m = M;
     g.b.nreq = R;
     g.map_wg.clear();
+    g.map_walk.clear();
     g.map_item.clear();
     g.map_tile.clear();
     for (int r = 0; r < R; ++r) {
       const bk::PartArgs& a = g.args[r];
       for (int w = 0; w < a.nwg; ++w) g.map_wg.push_back(((uint32_t)r << 16) | (uint32_t)w);
+      for (int b = 0; b < (a.ntiles + 15) / 16; ++b) g.map_walk.push_back(((uint32_t)r << 16) | (uint32_t)b);
       for (int i = 0; i < a.max_items; ++i) g.map_item.push_back(((uint32_t)r << 16) | (uint32_t)i);
       for (int t = 0; t < a.ntiles; ++t) g.map_tile.push_back(((uint32_t)r << 16) | (uint32_t)t);
       if (a.nwg > 65536 || a.max_items > 65536 || a.ntiles > 65536)
         return fail(BIN_ERR_UNSUPPORTED, "request too large for a batch block map");
     }
     g.b.n_wg_blocks = (int32_t)g.map_wg.size();
+    g.b.n_walk_blocks = (int32_t)g.map_walk.size();
     g.b.n_item_blocks = (int32_t)g.map_item.size();
     g.b.n_tile_blocks = (int32_t)g.map_tile.size();
   }
@@ -233,6 +216,7 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
   for (auto& g : bp->part) {
     g.desc_off = tab(sizeof(bk::PartArgs) * g.args.size());
     g.map_wg_off = tab(4 * g.map_wg.size());
+    g.map_walk_off = tab(4 * g.map_walk.size());
     g.map_item_off = tab(4 * g.map_item.size());
     g.map_tile_off = tab(4 * g.map_tile.size());
   }
@@ -251,10 +235,12 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
   for (auto& g : bp->part) {
     std::memcpy(h + g.desc_off, g.args.data(), sizeof(bk::PartArgs) * g.args.size());
     std::memcpy(h + g.map_wg_off, g.map_wg.data(), 4 * g.map_wg.size());
+    std::memcpy(h + g.map_walk_off, g.map_walk.data(), 4 * g.map_walk.size());
     std::memcpy(h + g.map_item_off, g.map_item.data(), 4 * g.map_item.size());
     std::memcpy(h + g.map_tile_off, g.map_tile.data(), 4 * g.map_tile.size());
     g.b.descs = reinterpret_cast<const bk::PartArgs*>(tdev + g.desc_off);
     g.b.map_wg = reinterpret_cast<const uint32_t*>(tdev + g.map_wg_off);
+    g.b.map_walk = reinterpret_cast<const uint32_t*>(tdev + g.map_walk_off);
     g.b.map_item = reinterpret_cast<const uint32_t*>(tdev + g.map_item_off);
     g.b.map_tile = reinterpret_cast<const uint32_t*>(tdev + g.map_tile_off);
   }

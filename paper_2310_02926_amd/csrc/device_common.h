@@ -129,8 +129,8 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // Elements i .. i+3 of a 16-byte aligned column (i a multiple of 4), read
 // with 16-byte loads: HBM streams at full rate only with wide loads.
-template <typename T>
-__device__ __forceinline__ void ld4v(const void* p, int64_t i, T* out) {
+template <typename T, typename I>
+__device__ __forceinline__ void ld4v(const void* p, I i, T* out) {
   if constexpr (sizeof(T) == 4) {
     const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(static_cast<const T*>(p) + i));
     out[0] = v.x;
@@ -153,7 +153,7 @@ __device__ __forceinline__ void ld4v(const void* p, int64_t i, T* out) {
 template <typename T>
 __device__ __forceinline__ void ld4(const void* p, int64_t i, int64_t hi, bool vec, T* out) {
   if (vec && i + 4 <= hi) {
-    ld4v<T>(p, i, out);
+    ld4v<T, int64_t>(p, i, out);
   } else {
 #pragma unroll
     for (int e = 0; e < 4; ++e) out[e] = i + e < hi ? ld<T>(p, i + e) : T(0);

@@ -92,6 +92,9 @@ int autotune(const bin_request* reqs, int count);
 // when only sizing: then pointers into scratch are left null and
 // scratch_bytes is filled in).
 int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints, void* scratch, Prepared* p);
+// Sub-chunk sizes and the blk_off rows per slice of a partition request
+// whose scatter runs with these threads and particles per thread.
+void set_part_blocks(bk::PartArgs& a, int scatter_threads, int ppt);
 // Enqueue the kernels of a prepared request.
 int enqueue(const Prepared& p, hipStream_t s, bk::KTimer* tm);
 // Human-readable plan.

@@ -134,21 +134,24 @@ struct PartArgs {
   Axis ax, ay;
   const long long* dyn;  // bounds computed on the device (4 keys), or null
   int64_t n;
-  int64_t chunk;       // particles per count/scatter workgroup
+  int64_t chunk;       // particles per scatter workgroup slice (a multiple of 64)
   int32_t nx, nbins, k, ntiles, nwg, max_items;
-  uint32_t split_len;  // max records per work item
+  uint32_t split_len;  // max records per work item (whole slices are never split)
   int32_t stage_val_off;  // byte offset of staged values in the scatter LDS
-  uint32_t* counts;    // [ntiles][nwg] counts, scanned in place to offsets
-  uint32_t* bsum;      // scan block sums (+ total at [scan_blocks])
-  uint32_t* inside;    // -> total records (inside particles)
-  uint16_t* rec_bin;   // [n] local bin of each record
-  void* rec_val[kMaxAttrs];  // [n] attribute values of each record
-  uint32_t* items;     // [max_items][3]: tile, begin, end
+  int32_t sub;         // particles per whole sub-chunk (scatter threads x particles per thread)
+  int32_t sub_tail;    // particles per remainder sub-chunk (scatter threads x 4)
+  int32_t nbpw;        // rows of blk_off reserved per slice (upper bound on its sub-chunks)
+  int32_t vec;         // every column 16-byte aligned: whole sub-chunks use wide loads
+  uint32_t* counts;    // [ntiles][nwg] records of each tile in each slice
+  uint32_t* blk_off;   // [nwg * nbpw][ntiles + 1] start of each tile's run within its sub-chunk
+  uint16_t* rec_bin;   // [n] records: a sub-chunk starting at particle i writes its
+  void* rec_val[kMaxAttrs];  //   records, grouped by tile, to [i, i + inside)
+  uint32_t* ilist;     // [ntiles][nwg] first slice of each of a tile's items
+  uint32_t* items;     // [max_items][3]: tile, first slice, end slice
   uint32_t* n_items;   // [1]
   uint32_t* tile_items;  // [ntiles][3]: first item, item count, first partial slot
   void* partial;       // max_slots partial slots (items of split tiles)
-  int32_t max_slots;
-  int32_t vec;         // every column 16-byte aligned and chunk % 4 == 0: wide loads
+  int32_t max_slots, pad;
   Outs out;
   TileLayout lay;
 };
@@ -157,19 +160,15 @@ struct PartArgs {
 // lists its blocks in a map (request << 16 | index within the request).
 struct PartBatch {
   const PartArgs* descs;
-  const uint32_t* map_wg;    // count and scatter blocks (index = workgroup slice)
+  const uint32_t* map_wg;    // scatter blocks (index = workgroup slice)
+  const uint32_t* map_walk;  // item walk blocks (index = group of 16 tiles)
   const uint32_t* map_item;  // binning blocks (index = work item)
   const uint32_t* map_tile;  // merge blocks (index = tile)
-  uint32_t* counts;          // all requests' count matrices, concatenated
-  uint32_t* bsum;
-  int64_t m;                 // total count entries
-  int32_t nreq, n_wg_blocks, n_item_blocks, n_tile_blocks;
+  int32_t nreq, n_wg_blocks, n_walk_blocks, n_item_blocks, n_tile_blocks;
 };
 
 struct PartCfg {
-  size_t count_lds, scatter_lds, bin_lds;
-  int scan_blocks;
-  int64_t scan_per;
+  size_t scatter_lds, bin_lds;
   int ppt;              // particles per thread per scatter sub-chunk
   int scatter_threads;  // threads per scatter workgroup
   int bin_block;

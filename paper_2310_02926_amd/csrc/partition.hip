@@ -2,22 +2,32 @@
 //
 // Global atomics on gfx950 sustain only a few tens of G lane-ops/s across
 // the whole device, while LDS atomics run two orders of magnitude faster, so
-// large grids are binned without any per-particle global atomic:
+// large grids are binned without any per-particle global atomic.  A tile is
+// TB = 2^s consecutive flat bins, TB chosen so that a tile's accumulators
+// fill one workgroup's LDS.
 //
-//   part_count    per workgroup slice of particles: LDS histogram of tiles
-//                 (a tile = TB consecutive flat bins, TB a power of two
-//                 chosen so a tile's accumulators fill one LDS allocation);
-//                 writes counts[tile][wg].
-//   scan_*        exclusive scan of counts (tile-major) -> record offsets.
-//   part_items    one work item per tile, heavy tiles split into items of at
-//                 most L records; split tiles get partial slots.
-//   part_scatter  re-reads the same slice, sorts each sub-chunk by tile in
-//                 LDS and writes compact records (u16 local bin + attribute
-//                 values) tile by tile, so stores are contiguous runs.
-//   part_bin      one workgroup per item: LDS accumulators for the tile,
-//                 then (single-item tile) the finished outputs - count, sum,
-//                 min, max, avg - written once, or (split tile) a partial.
+//   part_scatter  per workgroup slice of particles, per sub-chunk: LDS sort
+//                 of the sub-chunk's inside particles by tile, then the
+//                 records (u16 local bin + attribute values) are written
+//                 back in tile order over the sub-chunk's own index range,
+//                 so every store is part of one contiguous stream.  The
+//                 start of each tile's run in the sub-chunk goes to a small
+//                 table, and each slice's per-tile record totals to
+//                 counts[tile][slice].
+//   part_items    one work item per tile; a heavy tile is split into items
+//                 that each take a range of whole slices.
+//   part_bin      one workgroup per item: gathers the tile's runs from every
+//                 sub-chunk of its slices (a wave-wide load-balanced search
+//                 maps lanes to records), accumulates them in LDS, then
+//                 writes the finished outputs - count, sum, min, max, avg -
+//                 or, for a split tile, a partial slot.
 //   part_merge    combines the partials of split tiles into outputs.
+//
+// Scattered runs of a few records per tile were measured on MI355X to write
+// at under 2 TB/s, while the same bytes written as one stream per sub-chunk
+// go at full rate; the gather in part_bin reads the same runs with many
+// workgroups moving through the sub-chunks together, so neighbouring runs
+// are read at about the same time.
 //
 // Every kernel body takes its request record by reference, so one body
 // serves a single request (record passed by value as the kernel argument)
@@ -32,23 +42,28 @@
 namespace bk {
 
 // ---------------------------------------------------------------------------
-// Block-wide exclusive scans.
+// Shape of workgroup slice w: whole sub-chunks of 'sub' particles (aligned
+// requests only), then remainder sub-chunks of 'sub_tail' particles.
 // ---------------------------------------------------------------------------
-// Generic block size; tmp: blockDim.x words of LDS.
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* tmp, uint32_t* total) {
-  const int t = threadIdx.x;
-  tmp[t] = v;
-  __syncthreads();
-  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-    const uint32_t add = t >= off ? tmp[t - off] : 0u;
-    __syncthreads();
-    tmp[t] += add;
-    __syncthreads();
-  }
-  const uint32_t incl = tmp[t];
-  *total = tmp[blockDim.x - 1];
-  __syncthreads();
-  return incl - v;
+struct SliceShape {
+  int64_t lo, hi;
+  int32_t nfull, nblocks;
+};
+
+__device__ __forceinline__ SliceShape slice_shape(const PartArgs& a, int w) {
+  SliceShape s;
+  s.lo = (int64_t)w * a.chunk;
+  s.hi = s.lo + a.chunk < a.n ? s.lo + a.chunk : a.n;
+  const int64_t len = s.hi > s.lo ? s.hi - s.lo : 0;
+  s.nfull = a.vec ? (int32_t)(len / a.sub) : 0;
+  const int64_t rem = len - (int64_t)s.nfull * a.sub;
+  s.nblocks = s.nfull + (int32_t)((rem + a.sub_tail - 1) / a.sub_tail);
+  return s;
+}
+
+__device__ __forceinline__ int64_t block_base(const SliceShape& s, const PartArgs& a, int j) {
+  return j < s.nfull ? s.lo + (int64_t)j * a.sub
+                     : s.lo + (int64_t)s.nfull * a.sub + (int64_t)(j - s.nfull) * a.sub_tail;
 }
 
 // Fixed block size NT, wave shuffles (three barriers); wave_tot: NT/64 words.
@@ -82,166 +97,18 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t* wave_t
 }
 
 // ---------------------------------------------------------------------------
-// Tile histogram of workgroup slice wg.
-// ---------------------------------------------------------------------------
-template <typename CT>
-__device__ __forceinline__ void part_count_body(const PartArgs& a, int wg) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  uint32_t* h = reinterpret_cast<uint32_t*>(smem);
-  Axis ax = a.ax, ay = a.ay;
-  resolve_axes(a.dyn, ax, ay);
-  const int T = a.ntiles;
-  for (int t = threadIdx.x; t < T; t += blockDim.x) h[t] = 0u;
-  __syncthreads();
-  const int64_t lo = (int64_t)wg * a.chunk;
-  const int64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
-  const int shift = a.lay.tile_shift;
-  const bool vec = a.vec != 0;
-  // Each lane takes groups of 4 consecutive particles (16-byte loads).
-  constexpr int G = 4;
-  const int64_t step = (int64_t)4 * G * blockDim.x;
-  for (int64_t base = lo; base < hi; base += step) {
-    CT xs[4 * G], ys[4 * G];
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const int64_t i = base + 4 * ((int64_t)g * blockDim.x + threadIdx.x);
-      ld4<CT>(a.x, i, hi, vec, xs + 4 * g);
-      ld4<CT>(a.y, i, hi, vec, ys + 4 * g);
-    }
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const int64_t i = base + 4 * ((int64_t)g * blockDim.x + threadIdx.x);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int ix, iy;
-        if (i + e < hi && locate((double)xs[4 * g + e], ax, ix) && locate((double)ys[4 * g + e], ay, iy))
-          atomicAdd(h + ((iy * a.nx + ix) >> shift), 1u);
-      }
-    }
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < T; t += blockDim.x) a.counts[(int64_t)t * a.nwg + wg] = h[t];
-}
-
-template <typename CT>
-__global__ __launch_bounds__(1024) void part_count_kernel(PartArgs a) {
-  part_count_body<CT>(a, blockIdx.x);
-}
-template <typename CT>
-__global__ __launch_bounds__(1024) void part_count_batched(const PartArgs* __restrict__ d,
-                                                           const uint32_t* __restrict__ map) {
-  const uint32_t m = map[blockIdx.x];
-  part_count_body<CT>(d[m >> 16], (int)(m & 0xFFFFu));
-}
-
-// ---------------------------------------------------------------------------
-// Exclusive scan of m u32 values in place (three launches).
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void scan_block_sums_kernel(const uint32_t* v, int64_t m, int64_t per,
-                                                               uint32_t* bsum) {
-  __shared__ uint32_t red[1024];
-  const int64_t lo = (int64_t)blockIdx.x * per;
-  const int64_t hi = lo + per < m ? lo + per : m;
-  uint32_t s = 0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) s += v[i];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
-}
-
-// One block: exclusive scan of nb block sums in place; total at bsum[nb].
-__global__ __launch_bounds__(1024) void scan_top_kernel(uint32_t* bsum, int nb) {
-  __shared__ uint32_t wave_tot[16];
-  uint32_t carry = 0;
-  for (int base = 0; base < nb; base += 1024) {
-    const int i = base + threadIdx.x;
-    uint32_t tot;
-    const uint32_t ex = block_scan_excl<1024>(i < nb ? bsum[i] : 0u, wave_tot, tot);
-    if (i < nb) bsum[i] = carry + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0) bsum[nb] = carry;
-}
-
-__global__ __launch_bounds__(1024) void scan_apply_kernel(uint32_t* v, int64_t m, int64_t per,
-                                                          const uint32_t* bsum) {
-  __shared__ uint32_t wave_tot[16];
-  const int64_t lo = (int64_t)blockIdx.x * per;
-  const int64_t hi = lo + per < m ? lo + per : m;
-  uint32_t carry = bsum[blockIdx.x];
-  for (int64_t base = lo; base < hi; base += 1024) {
-    const int64_t i = base + threadIdx.x;
-    uint32_t tot;
-    const uint32_t ex = block_scan_excl<1024>(i < hi ? v[i] : 0u, wave_tot, tot);
-    if (i < hi) v[i] = carry + ex;
-    carry += tot;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Work items: one per tile, heavy tiles split into ranges of <= split_len.
-// tile_items[3t] = first item, [3t+1] = items, [3t+2] = first partial slot
-// (split tiles only).  counts[] holds the exclusive scan; *inside is the
-// end of this request's records.  One block (1024 threads) per request.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void part_items_body(const PartArgs& a) {
-  __shared__ uint32_t wave_tot[16];
-  const uint32_t total = *a.inside;
-  uint32_t carry = 0, scarry = 0;
-  for (int base = 0; base < a.ntiles; base += 1024) {
-    const int t = base + threadIdx.x;
-    uint32_t start = 0, end = 0, ni = 0;
-    if (t < a.ntiles) {
-      start = a.counts[(int64_t)t * a.nwg];
-      end = t + 1 < a.ntiles ? a.counts[(int64_t)(t + 1) * a.nwg] : total;
-      const uint32_t c = end - start;
-      ni = c == 0 ? 1u : (c + a.split_len - 1) / a.split_len;
-    }
-    uint32_t tot, stot;
-    const uint32_t first = carry + block_scan_excl<1024>(ni, wave_tot, tot);
-    const uint32_t slot0 = scarry + block_scan_excl<1024>(ni > 1 ? ni : 0u, wave_tot, stot);
-    if (t < a.ntiles) {
-      a.tile_items[3 * t] = first;
-      a.tile_items[3 * t + 1] = ni;
-      a.tile_items[3 * t + 2] = slot0;
-      for (uint32_t q = 0; q < ni; ++q) {
-        const uint32_t it = first + q;
-        if (it >= (uint32_t)a.max_items) break;  // max_items is a proven upper bound
-        const uint32_t b = start + q * a.split_len;
-        a.items[3 * it] = (uint32_t)t;
-        a.items[3 * it + 1] = b;
-        a.items[3 * it + 2] = (end - b) < a.split_len ? end : b + a.split_len;
-      }
-    }
-    carry += tot;
-    scarry += stot;
-  }
-  if (threadIdx.x == 0) *a.n_items = carry < (uint32_t)a.max_items ? carry : (uint32_t)a.max_items;
-}
-
-__global__ __launch_bounds__(1024) void part_items_kernel(PartArgs a) { part_items_body(a); }
-__global__ __launch_bounds__(1024) void part_items_batched(const PartArgs* __restrict__ d) {
-  part_items_body(d[blockIdx.x]);
-}
-
-// ---------------------------------------------------------------------------
 // Scatter: per sub-chunk of S = NT * PPT particles, rank each inside
 // particle within its tile (LDS atomic), scan the tile counts, place records
-// in LDS in tile order, then copy each tile's run to its global segment.
-// Lane t takes the groups of 4 consecutive particles starting at
+// in LDS in tile order, then copy them out over the sub-chunk's own index
+// range.  Lane t takes the groups of 4 consecutive particles starting at
 // base + 4 * (q * NT + t), q < PPT / 4.  Whole sub-chunks of an aligned
 // request are read with 16-byte loads and no bounds tests, and the next
 // one's coordinates are loaded while the current one is sorted and written;
-// the remainder (and unaligned requests) take a bounds-tested path.
-// Three barriers per sub-chunk: the tile counters are double-buffered, and
-// one wave scans them, advances the run heads by the previous sub-chunk's
-// counts and clears that buffer.
-// LDS: cnt[2][T] | off[T] | delta[T] | run[T] | (tile << 16 | local bin)[S] |
-//      values[k][S]
+// the remainder (and unaligned requests) take a bounds-tested path with 4
+// particles per thread.  Three barriers per sub-chunk: the tile counters are
+// double-buffered, and one wave scans them, adds them to the slice totals
+// and clears the other buffer.
+// LDS: cnt[2][T] | off[T] | tot[T] | (tile << 16 | local bin)[S] | values[k][S]
 // ---------------------------------------------------------------------------
 struct ScatterShared {
   uint32_t nsub;
@@ -250,21 +117,37 @@ struct ScatterShared {
 template <typename CT, typename AT, int PPT, int NT, bool FULL>
 __device__ __forceinline__ void scatter_sub(const PartArgs& a, unsigned char* smem, ScatterShared& sh,
                                             const Axis& ax, const Axis& ay, int64_t base, int64_t hi,
-                                            int64_t full_end, int parity, CT* px, CT* py) {
+                                            int64_t full_end, int64_t row, int parity, CT* px, CT* py) {
   constexpr int S = NT * PPT;
   constexpr int Q = PPT / 4;
   const int T = a.ntiles;
   uint32_t* cnt = reinterpret_cast<uint32_t*>(smem) + parity * T;
   uint32_t* cprev = reinterpret_cast<uint32_t*>(smem) + (parity ^ 1) * T;
   uint32_t* off = reinterpret_cast<uint32_t*>(smem) + 2 * T;
-  uint32_t* delta = off + T;
-  uint32_t* run = delta + T;
-  uint32_t* stg_tb = run + T;
+  uint32_t* tot = off + T;
+  uint32_t* stg_tb = tot + T;
   AT* stg_v = reinterpret_cast<AT*>(smem + a.stage_val_off);
   const int shift = a.lay.tile_shift;
   const uint32_t lmask = (1u << shift) - 1u;
   const int k = a.k;
 
+  // Whole sub-chunks index from a workgroup-uniform base pointer with 32-bit
+  // lane offsets (one address register per load instead of two).  The first
+  // attribute's values are loaded before the bins are located, so their
+  // latency hides behind locating, ranking and the scan.
+  const uint32_t lane4 = 4u * threadIdx.x;
+  AT v0[PPT];
+  if (k > 0) {
+    if constexpr (FULL) {
+      const AT* ab = static_cast<const AT*>(a.attr[0]) + base;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) ld4v<AT>(ab, lane4 + 4u * q * NT, v0 + 4 * q);
+    } else {
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+        ld4<AT>(a.attr[0], base + 4 * ((int64_t)q * NT + threadIdx.x), hi, false, v0 + 4 * q);
+    }
+  }
   uint32_t tb[PPT], pos[PPT];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -284,11 +167,12 @@ __device__ __forceinline__ void scatter_sub(const PartArgs& a, unsigned char* sm
   for (int u = 0; u < PPT; ++u) pos[u] = tb[u] != 0xFFFFFFFFu ? atomicAdd(cnt + (tb[u] >> 16), 1u) : 0u;
   if constexpr (FULL) {  // prefetch the next whole sub-chunk's coordinates
     if (base + S < full_end) {
+      const CT* xb = static_cast<const CT*>(a.x) + (base + S);
+      const CT* yb = static_cast<const CT*>(a.y) + (base + S);
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        const int64_t i = base + S + 4 * ((int64_t)q * NT + threadIdx.x);
-        ld4v<CT>(a.x, i, px + 4 * q);
-        ld4v<CT>(a.y, i, py + 4 * q);
+        ld4v<CT>(xb, lane4 + 4u * q * NT, px + 4 * q);
+        ld4v<CT>(yb, lane4 + 4u * q * NT, py + 4 * q);
       }
     }
   }
@@ -311,45 +195,49 @@ __device__ __forceinline__ void scatter_sub(const PartArgs& a, unsigned char* sm
       const int t = t0 + q;
       if (t < T) {
         const uint32_t c = cnt[t];
-        const uint32_t r = run[t] + cprev[t];
-        run[t] = r;
+        tot[t] += c;
         cprev[t] = 0u;
         off[t] = o0;
-        delta[t] = r - o0;
         o0 += c;
       }
     }
     if (lane == 63) sh.nsub = x;
   }
   __syncthreads();
+  const uint32_t nsub = sh.nsub;
+  uint32_t* orow = a.blk_off + row * (T + 1);
+  for (int t = threadIdx.x; t <= T; t += NT) orow[t] = t < T ? off[t] : nsub;
 #pragma unroll
   for (int u = 0; u < PPT; ++u) {
     if (tb[u] == 0xFFFFFFFFu) continue;
     pos[u] += off[tb[u] >> 16];
     stg_tb[pos[u]] = tb[u];
   }
-  for (int j = 0; j < k; ++j) {
+  if (k > 0) {
+#pragma unroll
+    for (int u = 0; u < PPT; ++u)
+      if (tb[u] != 0xFFFFFFFFu) stg_v[pos[u]] = v0[u];
+  }
+  for (int j = 1; j < k; ++j) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const int64_t i = base + 4 * ((int64_t)q * NT + threadIdx.x);
       AT v[4];
       if constexpr (FULL)
-        ld4v<AT>(a.attr[j], i, v);
+        ld4v<AT>(static_cast<const AT*>(a.attr[j]) + base, lane4 + 4u * q * NT, v);
       else
-        ld4<AT>(a.attr[j], i, hi, false, v);
+        ld4<AT>(a.attr[j], base + 4 * ((int64_t)q * NT + threadIdx.x), hi, false, v);
 #pragma unroll
       for (int e = 0; e < 4; ++e)
         if (tb[4 * q + e] != 0xFFFFFFFFu) stg_v[(int64_t)j * S + pos[4 * q + e]] = v[e];
     }
   }
   __syncthreads();
-  // Consecutive p of one tile go to consecutive record addresses.
-  const uint32_t nsub = sh.nsub;
-  for (uint32_t p = threadIdx.x; p < nsub; p += NT) {
-    const uint32_t v = stg_tb[p];
-    const uint32_t dst = delta[v >> 16] + p;
-    a.rec_bin[dst] = (uint16_t)(v & 0xFFFFu);
-    for (int j = 0; j < k; ++j) static_cast<AT*>(a.rec_val[j])[dst] = stg_v[(int64_t)j * S + p];
+  // One contiguous stream of records over [base, base + nsub).
+  uint16_t* rb = a.rec_bin + base;
+  for (uint32_t p = threadIdx.x; p < nsub; p += NT) rb[p] = (uint16_t)(stg_tb[p] & 0xFFFFu);
+  for (int j = 0; j < k; ++j) {
+    AT* rv = static_cast<AT*>(a.rec_val[j]) + base;
+    for (uint32_t p = threadIdx.x; p < nsub; p += NT) rv[p] = stg_v[(int64_t)j * S + p];
   }
 }
 
@@ -361,42 +249,48 @@ __device__ __forceinline__ void part_scatter_body(const PartArgs& a, int wg) {
   constexpr int Q = PPT / 4;
   const int T = a.ntiles;
   uint32_t* cnt = reinterpret_cast<uint32_t*>(smem);
-  uint32_t* run = cnt + 4 * T;
+  uint32_t* tot = cnt + 3 * T;
   Axis ax = a.ax, ay = a.ay;
   resolve_axes(a.dyn, ax, ay);
   for (int t = threadIdx.x; t < T; t += NT) {
     cnt[t] = 0u;
     cnt[T + t] = 0u;
-    run[t] = a.counts[(int64_t)t * a.nwg + wg];
+    tot[t] = 0u;
   }
-  const int64_t lo = (int64_t)wg * a.chunk;
-  const int64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
-  const int64_t full_end = a.vec ? lo + (hi - lo) / S * S : lo;
+  const SliceShape shp = slice_shape(a, wg);
+  const int64_t lo = shp.lo, hi = shp.hi;
+  const int64_t full_end = lo + (int64_t)shp.nfull * S;
+  const int64_t row0 = (int64_t)wg * a.nbpw;
   CT px[PPT], py[PPT];
   if (lo < full_end) {
+    const CT* xb = static_cast<const CT*>(a.x) + lo;
+    const CT* yb = static_cast<const CT*>(a.y) + lo;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const int64_t i = lo + 4 * ((int64_t)q * NT + threadIdx.x);
-      ld4v<CT>(a.x, i, px + 4 * q);
-      ld4v<CT>(a.y, i, py + 4 * q);
+      ld4v<CT>(xb, 4u * (q * NT + threadIdx.x), px + 4 * q);
+      ld4v<CT>(yb, 4u * (q * NT + threadIdx.x), py + 4 * q);
     }
   }
   __syncthreads();
   int parity = 0;
-  for (int64_t base = lo; base < full_end; base += S, parity ^= 1)
-    scatter_sub<CT, AT, PPT, NT, true>(a, smem, sh, ax, ay, base, hi, full_end, parity, px, py);
-  for (int64_t base = full_end; base < hi; base += S, parity ^= 1) {
+  int j = 0;
+  for (int64_t base = lo; base < full_end; base += S, parity ^= 1, ++j)
+    scatter_sub<CT, AT, PPT, NT, true>(a, smem, sh, ax, ay, base, hi, full_end, row0 + j, parity, px, py);
+  // The remainder in sub-chunks of 4 particles per thread (fewer registers;
+  // the staging area holds S >= 4 * NT entries).
+  constexpr int S4 = 4 * NT;
+  for (int64_t base = full_end; base < hi; base += S4, parity ^= 1, ++j) {
+    CT tx[4], ty[4];
+    const int64_t i = base + 4 * (int64_t)threadIdx.x;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int64_t i = base + 4 * ((int64_t)q * NT + threadIdx.x);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        px[4 * q + e] = i + e < hi ? ld<CT>(a.x, i + e) : CT(0);
-        py[4 * q + e] = i + e < hi ? ld<CT>(a.y, i + e) : CT(0);
-      }
+    for (int e = 0; e < 4; ++e) {
+      tx[e] = i + e < hi ? ld<CT>(a.x, i + e) : CT(0);
+      ty[e] = i + e < hi ? ld<CT>(a.y, i + e) : CT(0);
     }
-    scatter_sub<CT, AT, PPT, NT, false>(a, smem, sh, ax, ay, base, hi, full_end, parity, px, py);
+    scatter_sub<CT, AT, 4, NT, false>(a, smem, sh, ax, ay, base, hi, full_end, row0 + j, parity, tx, ty);
   }
+  __syncthreads();
+  for (int t = threadIdx.x; t < T; t += NT) a.counts[(int64_t)t * a.nwg + wg] = tot[t];
 }
 
 template <typename CT, typename AT, int PPT, int NT>
@@ -411,7 +305,128 @@ __global__ __launch_bounds__(NT) void part_scatter_batched(const PartArgs* __res
 }
 
 // ---------------------------------------------------------------------------
+// Work items.  For tile t, slice w starts at record excl(w) of the tile (an
+// exclusive prefix over the tile's per-slice counts); its item is
+// floor(excl(w) / split_len), so an item holds whole slices and at most
+// split_len records plus one slice's.  A tile has at most
+// ceil(records / split_len) items; an empty tile has one item with no
+// slices, which writes its empty bins.
+// items[3i] = tile, [3i+1] = first slice, [3i+2] = end slice.
+// tile_items[3t] = first item, [3t+1] = items, [3t+2] = first partial slot
+// (split tiles only).  One block (1024 threads, one wave per tile at a
+// time per tile in the walk, one block in the placement) per request.
+// ---------------------------------------------------------------------------
+struct ItemScan {
+  uint32_t n;       // items of the tile
+  uint32_t total;   // records of the tile
+};
+
+// One wave walks tile t's counts; emit(w, index within the tile) is called
+// (on the lane of slice w) for each slice that starts an item.
+template <typename F>
+__device__ __forceinline__ ItemScan tile_item_walk(const PartArgs& a, int t, F emit) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t* row = a.counts + (int64_t)t * a.nwg;
+  uint32_t carry = 0, nflag = 0, mprev = 0;
+  for (int w0 = 0; w0 < a.nwg; w0 += 64) {
+    const int w = w0 + lane;
+    const uint32_t c = w < a.nwg ? row[w] : 0u;
+    uint32_t incl = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o);
+      if (lane >= o) incl += y;
+    }
+    const uint32_t m = (carry + incl - c) / a.split_len;
+    uint32_t up = __shfl_up(m, 1);
+    if (lane == 0) up = mprev;
+    const bool flag = w < a.nwg && (w == 0 || m != up);
+    const uint64_t bal = __ballot(flag);
+    if (flag) emit(w, nflag + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull)));
+    nflag += (uint32_t)__popcll(bal);
+    const int last = (a.nwg - w0 < 64 ? a.nwg - w0 : 64) - 1;
+    mprev = __shfl(m, last);
+    carry += __shfl(incl, 63);
+  }
+  return ItemScan{nflag, carry};
+}
+
+// Walk: one wave per tile records where the tile's items start (ilist) and
+// how many there are and how many records the tile has (tile_items[3t+1],
+// [3t+2], completed by the placement below).
+__device__ __forceinline__ void part_items_walk_body(const PartArgs& a, int blk) {
+  const int t = blk * 16 + (int)(threadIdx.x >> 6);
+  if (t >= a.ntiles) return;
+  uint32_t* list = a.ilist + (int64_t)t * a.nwg;
+  const ItemScan is = tile_item_walk(a, t, [&](int w, uint32_t idx) { list[idx] = (uint32_t)w; });
+  if ((threadIdx.x & 63) == 0) {
+    a.tile_items[3 * t + 1] = is.n;
+    a.tile_items[3 * t + 2] = is.total;
+  }
+}
+
+// Placement: one block numbers the items of all tiles (exclusive scans over
+// tiles, 4 tiles per thread) and writes them out.
+__device__ __forceinline__ void part_items_place_body(const PartArgs& a) {
+  __shared__ uint32_t wave_tot[16];
+  const int T = a.ntiles;
+  const int t0 = 4 * threadIdx.x;
+  uint32_t ni[4], nrec[4];
+  uint32_t own = 0, sown = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    ni[q] = 0;
+    nrec[q] = 0;
+    if (t0 + q < T) {
+      nrec[q] = a.tile_items[3 * (t0 + q) + 2];
+      ni[q] = nrec[q] ? a.tile_items[3 * (t0 + q) + 1] : 1u;
+      own += ni[q];
+      sown += ni[q] > 1 ? ni[q] : 0u;
+    }
+  }
+  uint32_t tot, stot;
+  uint32_t first = block_scan_excl<1024>(own, wave_tot, tot);
+  uint32_t sfirst = block_scan_excl<1024>(sown, wave_tot, stot);
+  const uint32_t cap = (uint32_t)a.max_items;  // a proven upper bound; the guards keep stores in range
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int t = t0 + q;
+    if (t >= T) continue;
+    a.tile_items[3 * t] = first;
+    a.tile_items[3 * t + 1] = ni[q];
+    a.tile_items[3 * t + 2] = sfirst;
+    const uint32_t* list = a.ilist + (int64_t)t * a.nwg;
+    for (uint32_t i = 0; i < ni[q]; ++i) {
+      const uint32_t it = first + i;
+      if (it >= cap) break;
+      a.items[3 * it] = (uint32_t)t;
+      a.items[3 * it + 1] = nrec[q] ? list[i] : 0u;
+      a.items[3 * it + 2] = nrec[q] ? (i + 1 < ni[q] ? list[i + 1] : (uint32_t)a.nwg) : 0u;
+    }
+    first += ni[q];
+    sfirst += ni[q] > 1 ? ni[q] : 0u;
+  }
+  if (threadIdx.x == 0) *a.n_items = tot < cap ? tot : cap;
+}
+
+__global__ __launch_bounds__(1024) void part_items_walk_kernel(PartArgs a) { part_items_walk_body(a, blockIdx.x); }
+__global__ __launch_bounds__(1024) void part_items_walk_batched(const PartArgs* __restrict__ d,
+                                                                const uint32_t* __restrict__ map) {
+  const uint32_t m = map[blockIdx.x];
+  part_items_walk_body(d[m >> 16], (int)(m & 0xFFFFu));
+}
+__global__ __launch_bounds__(1024) void part_items_kernel(PartArgs a) { part_items_place_body(a); }
+__global__ __launch_bounds__(1024) void part_items_batched(const PartArgs* __restrict__ d) {
+  part_items_place_body(d[blockIdx.x]);
+}
+
+// ---------------------------------------------------------------------------
 // Per-item tile binning; fused finalize for tiles binned by one item.
+// Each wave takes 64 sub-chunks of the item's slices at a time, one per
+// lane: the lane reads where the tile's run starts and ends in its
+// sub-chunk; an inclusive scan of the run lengths across the wave then maps
+// the concatenated runs onto the lanes 64 records at a time (a binary
+// search over the scan for the lane's run).
 // ---------------------------------------------------------------------------
 template <typename AT, int PREC>
 __device__ __forceinline__ void part_bin_body(const PartArgs& a, int item) {
@@ -419,8 +434,8 @@ __device__ __forceinline__ void part_bin_body(const PartArgs& a, int item) {
   extern __shared__ __align__(16) unsigned char smem[];
   if (item >= (int)*a.n_items) return;
   const uint32_t t = a.items[3 * item];
-  const uint32_t rb = a.items[3 * item + 1];
-  const uint32_t re = a.items[3 * item + 2];
+  const uint32_t w0 = a.items[3 * item + 1];
+  const uint32_t w1 = a.items[3 * item + 2];
   const int shift = a.lay.tile_shift;
   const int64_t b0 = (int64_t)t << shift;
   const int TB = 1 << shift;
@@ -429,50 +444,92 @@ __device__ __forceinline__ void part_bin_body(const PartArgs& a, int item) {
   TL::init(smem, a.lay, k);
   __syncthreads();
 
-  // Groups of 4 consecutive records from rb rounded down to a multiple of 4
-  // (record arrays are 256-byte aligned): 8-byte bin and 16-byte value loads.
-  constexpr int G = 2;
-  const uint32_t r0 = rb & ~3u;
-  for (uint32_t base = r0; base < re; base += 4 * G * blockDim.x) {
-    uint32_t lb[4 * G];
-    bool full[G];
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const uint32_t r = base + 4 * (g * blockDim.x + threadIdx.x);
-      full[g] = r >= rb && r + 4 <= re;
-      if (full[g]) {
-        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-        const u32x2 w = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(a.rec_bin + r));
-        lb[4 * g] = w.x & 0xFFFFu;
-        lb[4 * g + 1] = w.x >> 16;
-        lb[4 * g + 2] = w.y & 0xFFFFu;
-        lb[4 * g + 3] = w.y >> 16;
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          lb[4 * g + e] = (r + e >= rb && r + e < re) ? (uint32_t)__builtin_nontemporal_load(a.rec_bin + r + e)
-                                                      : 0xFFFFFFFFu;
+  const int lane = threadIdx.x & 63;
+  const uint32_t wid = threadIdx.x >> 6;
+  const uint32_t nwaves = blockDim.x >> 6;
+  const int64_t T1 = a.ntiles + 1;
+  const uint32_t nblk = (w1 - w0) * (uint32_t)a.nbpw;
+  // The lane's run in sub-chunk c of the item (len 0 past the end or for a
+  // sub-chunk a short slice does not have).
+  auto run_of = [&](uint32_t c, uint32_t& len, uint32_t& rs) {
+    len = 0;
+    rs = 0;
+    if (c < nblk) {
+      const int w = (int)(w0 + c / (uint32_t)a.nbpw);
+      const int j = (int)(c % (uint32_t)a.nbpw);
+      const SliceShape shp = slice_shape(a, w);
+      if (j < shp.nblocks) {
+        const uint32_t* row = a.blk_off + ((int64_t)w * a.nbpw + j) * T1;
+        const uint32_t s0 = row[t];
+        len = row[t + 1] - s0;
+        rs = (uint32_t)(block_base(shp, a, j) + s0);
       }
     }
+  };
+  uint32_t nlen, nrs;  // the next group's run, read while this group is binned
+  run_of(wid * 64 + lane, nlen, nrs);
+  for (uint32_t c0 = wid * 64; c0 < nblk; c0 += nwaves * 64) {
+    const uint32_t len = nlen, rs = nrs;  // first record of the lane's run
+    run_of(c0 + nwaves * 64 + lane, nlen, nrs);
+    uint32_t incl = len;
 #pragma unroll
-    for (int u = 0; u < 4 * G; ++u)
-      if (lb[u] != 0xFFFFFFFFu) TL::count(smem, (int)lb[u]);
-    for (int j = 0; j < k; ++j) {
-      AT v[4 * G];
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o);
+      if (lane >= o) incl += y;
+    }
+    const uint32_t total = __shfl(incl, 63);
+    const uint32_t start = rs - (incl - len);  // record = start + q for q in the lane's run
+    // R windows of 64 records at a time: all their loads are issued before
+    // the first LDS update, so R gathers per wave are in flight.
+    constexpr int R = 8;
+    for (uint32_t r = 0; r < total; r += 64 * R) {
+      uint32_t rec[R];
+      int lb[R];
+      AT v0[R];
 #pragma unroll
-      for (int g = 0; g < G; ++g) {
-        const uint32_t r = base + 4 * (g * blockDim.x + threadIdx.x);
-        if (full[g]) {
-          ld4<AT>(a.rec_val[j], r, re, true, v + 4 * g);
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-            v[4 * g + e] = lb[4 * g + e] != 0xFFFFFFFFu ? ld<AT>(a.rec_val[j], r + e) : AT(0);
+      for (int u = 0; u < R; ++u) {
+        // Window of records [w0q, w0q + 64): the runs holding its first and
+        // last records are found with two ballots (wave-uniform), and each
+        // lane picks the last run in that range starting at or before its
+        // record, reading run starts with readlane (no LDS traffic).
+        const uint32_t w0q = r + 64 * u;
+        uint32_t recu = 0xFFFFFFFFu;
+        if (w0q < total) {
+          const uint32_t wl = w0q + 63 < total ? w0q + 63 : total - 1;
+          const int la = __builtin_ctzll(__ballot(incl > w0q));
+          const int lb = __builtin_ctzll(__ballot(incl > wl));
+          const uint32_t q = w0q + lane;
+          uint32_t st = (uint32_t)__builtin_amdgcn_readlane((int)start, la);
+          for (int x = la + 1; x <= lb; ++x) {
+            const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)incl, x - 1);  // first record of run x
+            const uint32_t sx = (uint32_t)__builtin_amdgcn_readlane((int)start, x);
+            if (q >= e) st = sx;
+          }
+          if (q < total) recu = st + q;
         }
+        rec[u] = recu;
       }
 #pragma unroll
-      for (int u = 0; u < 4 * G; ++u)
-        if (lb[u] != 0xFFFFFFFFu) TL::add(smem, a.lay, j, (int)lb[u], v[u]);
+      for (int u = 0; u < R; ++u) {
+        lb[u] = rec[u] != 0xFFFFFFFFu ? (int)__builtin_nontemporal_load(a.rec_bin + rec[u]) : -1;
+        v0[u] = (rec[u] != 0xFFFFFFFFu && k > 0) ? ld<AT>(a.rec_val[0], rec[u]) : AT(0);
+      }
+#pragma unroll
+      for (int u = 0; u < R; ++u)
+        if (lb[u] >= 0) TL::count(smem, lb[u]);
+      if (k > 0) {
+#pragma unroll
+        for (int u = 0; u < R; ++u)
+          if (lb[u] >= 0) TL::add(smem, a.lay, 0, lb[u], v0[u]);
+      }
+      for (int jj = 1; jj < k; ++jj) {
+        AT v[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) v[u] = lb[u] >= 0 ? ld<AT>(a.rec_val[jj], rec[u]) : AT(0);
+#pragma unroll
+        for (int u = 0; u < R; ++u)
+          if (lb[u] >= 0) TL::add(smem, a.lay, jj, lb[u], v[u]);
+      }
     }
   }
   __syncthreads();
@@ -485,9 +542,17 @@ __device__ __forceinline__ void part_bin_body(const PartArgs& a, int item) {
   }
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin; block b runs item
+// (b % 8) * P + b / 8 with P = ceil(items / 8), so each XCD takes a
+// contiguous range of tiles and neighbouring tiles' runs, which share cache
+// lines, are read through the same L2.
 template <typename AT, int PREC>
 __global__ __launch_bounds__(1024) void part_bin_kernel(PartArgs a) {
-  part_bin_body<AT, PREC>(a, blockIdx.x);
+  const uint32_t n = *a.n_items;
+  const uint32_t per = (n + 7) / 8;
+  const uint32_t s = blockIdx.x / 8;
+  if (s >= per) return;
+  part_bin_body<AT, PREC>(a, (int)((blockIdx.x % 8) * per + s));
 }
 template <typename AT, int PREC>
 __global__ __launch_bounds__(1024) void part_bin_batched(const PartArgs* __restrict__ d,
@@ -555,15 +620,10 @@ __global__ __launch_bounds__(256) void part_merge_batched(const PartArgs* __rest
 template <typename CT, typename AT, int PREC>
 static hipError_t launch_part_t(const PartArgs& a, const PartCfg& c, hipStream_t s, KTimer* tm) {
   hipError_t e;
-  BK_LAUNCH("part_count_kernel", (part_count_kernel<CT>), a.nwg, 1024, c.count_lds, a);
-  const int64_t m = (int64_t)a.ntiles * a.nwg;
-  BK_LAUNCH("scan_block_sums_kernel", scan_block_sums_kernel, c.scan_blocks, 1024, 0, a.counts, m, c.scan_per,
-            a.bsum);
-  BK_LAUNCH("scan_top_kernel", scan_top_kernel, 1, 1024, 0, a.bsum, c.scan_blocks);
-  BK_LAUNCH("scan_apply_kernel", scan_apply_kernel, c.scan_blocks, 1024, 0, a.counts, m, c.scan_per, a.bsum);
-  BK_LAUNCH("part_items_kernel", part_items_kernel, 1, 1024, 0, a);
   BK_SCATTER_SWITCH(part_scatter_kernel, a.nwg, a)
-  BK_LAUNCH("part_bin_kernel", (part_bin_kernel<AT, PREC>), a.max_items, c.bin_block, c.bin_lds, a);
+  BK_LAUNCH("part_items_walk_kernel", part_items_walk_kernel, (a.ntiles + 15) / 16, 1024, 0, a);
+  BK_LAUNCH("part_items_kernel", part_items_kernel, 1, 1024, 0, a);
+  BK_LAUNCH("part_bin_kernel", (part_bin_kernel<AT, PREC>), (a.max_items + 7) / 8 * 8, c.bin_block, c.bin_lds, a);
   BK_LAUNCH("part_merge_kernel", (part_merge_kernel<AT, PREC>), a.ntiles, 256, 0, a);
   return hipSuccess;
 }
@@ -571,14 +631,9 @@ static hipError_t launch_part_t(const PartArgs& a, const PartCfg& c, hipStream_t
 template <typename CT, typename AT, int PREC>
 static hipError_t launch_part_batch_t(const PartBatch& b, const PartCfg& c, hipStream_t s, KTimer* tm) {
   hipError_t e;
-  BK_LAUNCH("part_count_kernel", (part_count_batched<CT>), b.n_wg_blocks, 1024, c.count_lds, b.descs,
-            b.map_wg);
-  BK_LAUNCH("scan_block_sums_kernel", scan_block_sums_kernel, c.scan_blocks, 1024, 0, b.counts, b.m, c.scan_per,
-            b.bsum);
-  BK_LAUNCH("scan_top_kernel", scan_top_kernel, 1, 1024, 0, b.bsum, c.scan_blocks);
-  BK_LAUNCH("scan_apply_kernel", scan_apply_kernel, c.scan_blocks, 1024, 0, b.counts, b.m, c.scan_per, b.bsum);
-  BK_LAUNCH("part_items_kernel", part_items_batched, b.nreq, 1024, 0, b.descs);
   BK_SCATTER_SWITCH(part_scatter_batched, b.n_wg_blocks, b.descs, b.map_wg)
+  BK_LAUNCH("part_items_walk_kernel", part_items_walk_batched, b.n_walk_blocks, 1024, 0, b.descs, b.map_walk);
+  BK_LAUNCH("part_items_kernel", part_items_batched, b.nreq, 1024, 0, b.descs);
   BK_LAUNCH("part_bin_kernel", (part_bin_batched<AT, PREC>), b.n_item_blocks, c.bin_block, c.bin_lds, b.descs,
             b.map_item);
   BK_LAUNCH("part_merge_kernel", (part_merge_batched<AT, PREC>), b.n_tile_blocks, 256, 0, b.descs, b.map_tile);
@@ -626,10 +681,6 @@ hipError_t set_partition_lds_limit(size_t bytes) {
   BK_SET_NT(K, CT, AT, 1024)
 #define BK_SET_TYPES(K) \
   BK_SET_CA(K, float, float) BK_SET_CA(K, float, double) BK_SET_CA(K, double, float) BK_SET_CA(K, double, double)
-  BK_SETF(part_count_kernel<float>)
-  BK_SETF(part_count_kernel<double>)
-  BK_SETF(part_count_batched<float>)
-  BK_SETF(part_count_batched<double>)
   BK_SET_TYPES(part_scatter_kernel)
   BK_SET_TYPES(part_scatter_batched)
   BK_SETF(part_bin_kernel<float, PREC_F64>)

@@ -37,6 +37,28 @@ struct Carve {
   }
 };
 
+// Sub-chunks of partition slice w (mirrors the device-side slice shape):
+// whole ones of 'sub' particles for aligned requests, then remainder ones of
+// 'sub_tail'.
+int64_t slice_blocks(const bk::PartArgs& a, int64_t w) {
+  const int64_t lo = w * a.chunk;
+  const int64_t hi = std::min<int64_t>(lo + a.chunk, a.n);
+  const int64_t len = std::max<int64_t>(hi - lo, 0);
+  const int64_t nfull = a.vec ? len / a.sub : 0;
+  return nfull + ceil_div(len - nfull * a.sub, (int64_t)a.sub_tail);
+}
+
+}  // namespace
+
+void set_part_blocks(bk::PartArgs& a, int scatter_threads, int ppt) {
+  a.sub = scatter_threads * ppt;
+  a.sub_tail = 4 * scatter_threads;
+  // every slice but the last has the first one's length
+  a.nbpw = (int32_t)std::max<int64_t>({slice_blocks(a, 0), slice_blocks(a, a.nwg - 1), 1});
+}
+
+namespace {
+
 // LDS and slot layout of a tile of tb bins.  Returns the LDS bytes.
 size_t tile_layout(int tb, int k, bool sum, bool mn, bool mx, int prec, size_t asz, bk::TileLayout* L) {
   std::memset(L, 0, sizeof *L);
@@ -213,21 +235,27 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints_
     int64_t L = std::max<int64_t>({ceil_div(3 * n, 2 * ntiles), ceil_div(n, 2 * (int64_t)cus), 16384});
     if (hints.split_len) L = hints.split_len;
     a.split_len = (uint32_t)std::min<int64_t>(L, 0x7FFFFFFF);
-    a.max_items = (int32_t)(ntiles + ceil_div(n, (int64_t)a.split_len));
-    // scatter LDS: 5 T counters, S tile/bin words, S * k values
+    // Items group whole slices greedily; two consecutive items of a tile
+    // hold more than split_len records together, so a tile with R records
+    // has at most 2 + 2 R / split_len items.
+    a.max_items = (int32_t)(2 * ntiles + 2 * ceil_div(n, (int64_t)a.split_len));
+    // scatter LDS: 4 T counters, S tile/bin words, S * k values
     // 1024-thread scatter workgroups measured fastest on MI355X for both the
     // 1- and 4-attribute workloads (one workgroup per CU, LDS-bound).
     // Largest scatter stage that fits LDS: 1024 threads first (fastest on
     // MI355X), fewer particles per thread, then fewer threads (many
-    // attributes).  A 1024-thread workgroup allows 128 VGPRs per lane: 16
-    // f32 or 8 f64 coordinate pairs per thread (more would spill).
+    // attributes).  Register budget (no spills): a 1024-thread workgroup
+    // allows 128 VGPRs per lane, enough for 16 particles per thread with f32
+    // columns, 8 with f64 ones; smaller workgroups take 32 (f32
+    // coordinates) or 16 (f64).
     int nt = 0, ppt = 0;
     size_t sc = 0;
+    const bool wide = p->coord_f64 || p->attr_f64;
     for (int tnt = hints.scatter_threads ? hints.scatter_threads : 1024; tnt >= 256 && !ppt; tnt /= 2) {
-      const int cap = tnt >= 1024 ? (p->coord_f64 ? 8 : 16) : 32;
+      const int cap = tnt >= 1024 ? (wide ? 8 : 16) : (p->coord_f64 ? 16 : 32);
       for (int tp = std::min(hints.scatter_ppt ? hints.scatter_ppt : 16, cap); tp >= 4; tp /= 2) {
         const size_t S = (size_t)tnt * tp;
-        const int32_t svo = (int32_t)align16(20 * (size_t)T + 4 * S);
+        const int32_t svo = (int32_t)align16(16 * (size_t)T + 4 * S);
         const size_t need = svo + S * nk * asz;
         if (need + kScatterStatic <= lds_budget) {
           nt = tnt;
@@ -243,16 +271,13 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints_
     c.ppt = ppt;
     c.scatter_threads = nt;
     c.scatter_lds = std::max<size_t>(sc, 16);
-    c.count_lds = 4 * (size_t)T;
     c.bin_lds = tile_lds;
     c.bin_block = 1024;
-    const int64_t m = ntiles * a.nwg;
-    c.scan_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(m, 4096)));
-    c.scan_per = ceil_div(m, c.scan_blocks);
+    set_part_blocks(a, nt, ppt);
     // scratch
-    a.counts = static_cast<uint32_t*>(cv.take(4 * (size_t)m));
-    a.bsum = static_cast<uint32_t*>(cv.take(4 * ((size_t)c.scan_blocks + 1)));
-    a.inside = a.bsum ? a.bsum + c.scan_blocks : nullptr;
+    a.counts = static_cast<uint32_t*>(cv.take(4 * (size_t)ntiles * a.nwg));
+    a.blk_off = static_cast<uint32_t*>(cv.take(4 * (size_t)a.nwg * a.nbpw * (size_t)(ntiles + 1)));
+    a.ilist = static_cast<uint32_t*>(cv.take(4 * (size_t)ntiles * a.nwg));
     a.items = static_cast<uint32_t*>(cv.take(12 * (size_t)a.max_items));
     a.n_items = static_cast<uint32_t*>(cv.take(4));
     a.tile_items = static_cast<uint32_t*>(cv.take(12 * (size_t)T));
@@ -369,10 +394,11 @@ std::string describe(const Prepared& p) {
       break;
     case bk::STRAT_PART:
       snprintf(buf, sizeof buf,
-               "partition tiles=%d tile_bins=%d wg=%d chunk=%lld threads=%d ppt=%d split=%u max_items=%d "
+               "partition tiles=%d tile_bins=%d wg=%d chunk=%lld threads=%d ppt=%d sub=%d blocks=%d split=%u "
+               "max_items=%d "
                "scatter_lds=%zu bin_lds=%zu vec=%d prec=%s",
                p.part.ntiles, 1 << p.part.lay.tile_shift, p.part.nwg, (long long)p.part.chunk, p.pcfg.scatter_threads,
-               p.pcfg.ppt,
+               p.pcfg.ppt, p.part.sub, p.part.nbpw,
                p.part.split_len, p.part.max_items, p.pcfg.scatter_lds, p.pcfg.bin_lds, p.part.vec, prec);
       break;
     default:
