@@ -157,10 +157,12 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
       a.items = reinterpret_cast<uint32_t*>(take(12 * (size_t)a.max_items));
       a.n_items = n_items ? n_items + r : nullptr;
       a.tile_items = reinterpret_cast<uint32_t*>(take(12 * (size_t)a.ntiles));
+      a.split_list = reinterpret_cast<uint32_t*>(take(4 * ((size_t)a.ntiles + 1)));
       a.rec_bin = reinterpret_cast<uint16_t*>(take(2 * nrec));
       for (int j = 0; j < a.k; ++j) a.rec_val[j] = take(asz * nrec);
       a.stage_val_off = (int32_t)al16(16 * (size_t)a.ntiles + 4 * S);
       a.partial = a.max_slots > 0 ? take((size_t)a.lay.slot_bytes * a.max_slots) : nullptr;
+      a.merge_blocks = std::min(a.merge_blocks, 16);  // many requests share the launch
       g.args[r] = a;
     }
     g.b.nreq = R;
@@ -173,7 +175,7 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
       for (int w = 0; w < a.nwg; ++w) g.map_wg.push_back(((uint32_t)r << 16) | (uint32_t)w);
       for (int b = 0; b < (a.ntiles + 15) / 16; ++b) g.map_walk.push_back(((uint32_t)r << 16) | (uint32_t)b);
       for (int i = 0; i < a.max_items; ++i) g.map_item.push_back(((uint32_t)r << 16) | (uint32_t)i);
-      for (int t = 0; t < a.ntiles; ++t) g.map_tile.push_back(((uint32_t)r << 16) | (uint32_t)t);
+      for (int b = 0; b < a.merge_blocks; ++b) g.map_tile.push_back(((uint32_t)r << 16) | (uint32_t)b);
       if (a.nwg > 65536 || a.max_items > 65536 || a.ntiles > 65536)
         return fail(BIN_ERR_UNSUPPORTED, "request too large for a batch block map");
     }

@@ -95,6 +95,8 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints,
 // Sub-chunk sizes and the blk_off rows per slice of a partition request
 // whose scatter runs with these threads and particles per thread.
 void set_part_blocks(bk::PartArgs& a, int scatter_threads, int ppt);
+// Workgroups of the split-tile merge launch (a.max_slots and a.lay set).
+int32_t merge_blocks(const bk::PartArgs& a, int cus);
 // Enqueue the kernels of a prepared request.
 int enqueue(const Prepared& p, hipStream_t s, bk::KTimer* tm);
 // Human-readable plan.

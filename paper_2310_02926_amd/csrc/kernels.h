@@ -150,6 +150,8 @@ struct PartArgs {
   uint32_t* items;     // [max_items][3]: tile, first slice, end slice
   uint32_t* n_items;   // [1]
   uint32_t* tile_items;  // [ntiles][3]: first item, item count, first partial slot
+  uint32_t* split_list;  // [ntiles + 1]: tiles binned by several items; count at [ntiles]
+  int32_t merge_blocks;  // workgroups of the merge launch
   void* partial;       // max_slots partial slots (items of split tiles)
   int32_t max_slots, pad;
   Outs out;
@@ -163,7 +165,7 @@ struct PartBatch {
   const uint32_t* map_wg;    // scatter blocks (index = workgroup slice)
   const uint32_t* map_walk;  // item walk blocks (index = group of 16 tiles)
   const uint32_t* map_item;  // binning blocks (index = work item)
-  const uint32_t* map_tile;  // merge blocks (index = tile)
+  const uint32_t* map_tile;  // merge blocks (index = merge workgroup of the request)
   int32_t nreq, n_wg_blocks, n_walk_blocks, n_item_blocks, n_tile_blocks;
 };
 

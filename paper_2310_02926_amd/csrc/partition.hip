@@ -384,9 +384,17 @@ __device__ __forceinline__ void part_items_place_body(const PartArgs& a) {
       sown += ni[q] > 1 ? ni[q] : 0u;
     }
   }
-  uint32_t tot, stot;
+  uint32_t nsplit = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) nsplit += ni[q] > 1 ? 1u : 0u;
+  uint32_t tot, stot, ntot;
   uint32_t first = block_scan_excl<1024>(own, wave_tot, tot);
   uint32_t sfirst = block_scan_excl<1024>(sown, wave_tot, stot);
+  uint32_t lfirst = block_scan_excl<1024>(nsplit, wave_tot, ntot);
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (ni[q] > 1) a.split_list[lfirst++] = (uint32_t)(t0 + q);
+  if (threadIdx.x == 0) a.split_list[T] = ntot;
   const uint32_t cap = (uint32_t)a.max_items;  // a proven upper bound; the guards keep stores in range
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -561,29 +569,35 @@ __global__ __launch_bounds__(1024) void part_bin_batched(const PartArgs* __restr
   part_bin_body<AT, PREC>(d[m >> 16], (int)(m & 0xFFFFu));
 }
 
-// One block per tile; only split tiles do work.
+// Merge of split tiles: work unit u = (split tile, 1024-bin chunk), one bin
+// per thread; merge_blocks workgroups stride over the units.
 template <typename AT, int PREC>
-__device__ __forceinline__ void part_merge_body(const PartArgs& a, int t) {
-  const uint32_t nit = a.tile_items[3 * t + 1];
-  if (nit <= 1) return;
-  const uint32_t slot0 = a.tile_items[3 * t + 2];
-  if (slot0 + nit > (uint32_t)a.max_slots) return;  // cannot happen (proven bound)
+__device__ __forceinline__ void part_merge_body(const PartArgs& a, int blk) {
+  const uint32_t nsplit = a.split_list[a.ntiles];
   const int shift = a.lay.tile_shift;
-  const int64_t b0 = (int64_t)t << shift;
   const int TB = 1 << shift;
-  const int nbt = (int)((b0 + TB <= a.nbins) ? TB : a.nbins - b0);
-  for (int b = threadIdx.x; b < nbt; b += blockDim.x)
-    Tile<AT, PREC>::merge_emit(static_cast<const unsigned char*>(a.partial), a.lay.slot_bytes, slot0, nit, a.lay,
-                               a.out, a.k, b, b0 + b);
+  const uint32_t chunks = (uint32_t)((TB + 1023) >> 10);
+  for (uint32_t u = blk; u < nsplit * chunks; u += (uint32_t)a.merge_blocks) {
+    const uint32_t t = a.split_list[u / chunks];
+    const int b = (int)(u % chunks) * 1024 + threadIdx.x;
+    const uint32_t nit = a.tile_items[3 * t + 1];
+    const uint32_t slot0 = a.tile_items[3 * t + 2];
+    if (slot0 + nit > (uint32_t)a.max_slots) continue;  // cannot happen (proven bound)
+    const int64_t b0 = (int64_t)t << shift;
+    const int nbt = (int)((b0 + TB <= a.nbins) ? TB : a.nbins - b0);
+    if (b < nbt)
+      Tile<AT, PREC>::merge_emit(static_cast<const unsigned char*>(a.partial), a.lay.slot_bytes, slot0, nit, a.lay,
+                                 a.out, a.k, b, b0 + b);
+  }
 }
 
 template <typename AT, int PREC>
-__global__ __launch_bounds__(256) void part_merge_kernel(PartArgs a) {
+__global__ __launch_bounds__(1024) void part_merge_kernel(PartArgs a) {
   part_merge_body<AT, PREC>(a, blockIdx.x);
 }
 template <typename AT, int PREC>
-__global__ __launch_bounds__(256) void part_merge_batched(const PartArgs* __restrict__ d,
-                                                          const uint32_t* __restrict__ map) {
+__global__ __launch_bounds__(1024) void part_merge_batched(const PartArgs* __restrict__ d,
+                                                           const uint32_t* __restrict__ map) {
   const uint32_t m = map[blockIdx.x];
   part_merge_body<AT, PREC>(d[m >> 16], (int)(m & 0xFFFFu));
 }
@@ -624,7 +638,7 @@ static hipError_t launch_part_t(const PartArgs& a, const PartCfg& c, hipStream_t
   BK_LAUNCH("part_items_walk_kernel", part_items_walk_kernel, (a.ntiles + 15) / 16, 1024, 0, a);
   BK_LAUNCH("part_items_kernel", part_items_kernel, 1, 1024, 0, a);
   BK_LAUNCH("part_bin_kernel", (part_bin_kernel<AT, PREC>), (a.max_items + 7) / 8 * 8, c.bin_block, c.bin_lds, a);
-  BK_LAUNCH("part_merge_kernel", (part_merge_kernel<AT, PREC>), a.ntiles, 256, 0, a);
+  BK_LAUNCH("part_merge_kernel", (part_merge_kernel<AT, PREC>), a.merge_blocks, 1024, 0, a);
   return hipSuccess;
 }
 
@@ -636,7 +650,7 @@ static hipError_t launch_part_batch_t(const PartBatch& b, const PartCfg& c, hipS
   BK_LAUNCH("part_items_kernel", part_items_batched, b.nreq, 1024, 0, b.descs);
   BK_LAUNCH("part_bin_kernel", (part_bin_batched<AT, PREC>), b.n_item_blocks, c.bin_block, c.bin_lds, b.descs,
             b.map_item);
-  BK_LAUNCH("part_merge_kernel", (part_merge_batched<AT, PREC>), b.n_tile_blocks, 256, 0, b.descs, b.map_tile);
+  BK_LAUNCH("part_merge_kernel", (part_merge_batched<AT, PREC>), b.n_tile_blocks, 1024, 0, b.descs, b.map_tile);
   return hipSuccess;
 }
 #undef BK_SC

@@ -50,6 +50,15 @@ int64_t slice_blocks(const bk::PartArgs& a, int64_t w) {
 
 }  // namespace
 
+// Merge workgroups: enough for every (split tile, 1024-bin chunk) unit when
+// all possible split tiles occur (each has two or more slots), at most two
+// per CU.
+int32_t merge_blocks(const bk::PartArgs& a, int cus) {
+  const int64_t chunks = ceil_div((int64_t)1 << a.lay.tile_shift, 1024);
+  const int64_t units = (int64_t)(a.max_slots / 2) * chunks;
+  return (int32_t)std::min<int64_t>(std::max<int64_t>(units, 0), 2 * (int64_t)cus);
+}
+
 void set_part_blocks(bk::PartArgs& a, int scatter_threads, int ppt) {
   a.sub = scatter_threads * ppt;
   a.sub_tail = 4 * scatter_threads;
@@ -232,7 +241,7 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints_
     for (int j = 0; j < nk; ++j) aligned = aligned && ((uintptr_t)a.attr[j] % 16 == 0);
     a.vec = aligned ? 1 : 0;
     // split length: no split when tiles are balanced, bounded work otherwise
-    int64_t L = std::max<int64_t>({ceil_div(3 * n, 2 * ntiles), ceil_div(n, 2 * (int64_t)cus), 16384});
+    int64_t L = std::max<int64_t>({ceil_div(2 * n, ntiles), ceil_div(n, (int64_t)cus), 16384});
     if (hints.split_len) L = hints.split_len;
     a.split_len = (uint32_t)std::min<int64_t>(L, 0x7FFFFFFF);
     // Items group whole slices greedily; two consecutive items of a tile
@@ -281,12 +290,14 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints_
     a.items = static_cast<uint32_t*>(cv.take(12 * (size_t)a.max_items));
     a.n_items = static_cast<uint32_t*>(cv.take(4));
     a.tile_items = static_cast<uint32_t*>(cv.take(12 * (size_t)T));
+    a.split_list = static_cast<uint32_t*>(cv.take(4 * ((size_t)T + 1)));
     a.rec_bin = static_cast<uint16_t*>(cv.take(2 * (size_t)std::max<int64_t>(n, 1)));
     for (int j = 0; j < nk; ++j) a.rec_val[j] = cv.take(asz * (size_t)std::max<int64_t>(n, 1));
     // Partial slots only for items of split tiles (ni >= 2 items each):
     // sum over split tiles of ni <= 2 * sum of (ni - 1) <= 2 * (max_items - ntiles).
     a.max_slots = (int32_t)std::min<int64_t>(a.max_items, 2 * (a.max_items - ntiles));
     a.partial = a.max_slots > 0 ? cv.take((size_t)a.lay.slot_bytes * a.max_slots) : nullptr;
+    a.merge_blocks = merge_blocks(a, cus);
     p->scratch_bytes = cv.used;
     p->cfg.grid = a.max_items;
     p->cfg.block = c.bin_block;

@@ -95,6 +95,24 @@ def test_partition_split_tiles_clustered():
         G.assert_parity(got, G.oracle(ws), B.OPS_ALL, plain=(prec == "plain"), what=f"split {prec}")
 
 
+@pytest.mark.parametrize("split_len", [1024, 5000, 65536])
+def test_partition_forced_split_lengths(split_len):
+    """Short split lengths: most tiles are binned by many items (each a
+    range of whole workgroup slices) and merged; a contiguous hot block puts
+    most particles into a handful of tiles."""
+    from paper_2310_02926_amd import binding as B
+    _case(f"partition split_len={split_len}")
+    ws = synth.hotspot_f32(n=2_000_000, seed=3, side=512, contiguous=True)
+    ref = G.oracle(ws)
+    B.bin_set_tuning(B.TUNE_SPLIT_LEN, split_len)
+    B.bin_set_tuning(B.TUNE_PART_WG, 700)
+    try:
+        got = _bin(ws, 2)
+    finally:
+        B.reset_tuning()
+    G.assert_parity(got, ref, 31, what=f"split_len={split_len}")
+
+
 def _ws(coords, attrs, nx, ny, bounds=(0.0, 1.0, 0.0, 1.0), axes=(0, 1), ops=31):
     return synth.Workload([np.ascontiguousarray(c) for c in coords], [np.ascontiguousarray(a) for a in attrs],
                           axes=axes, bounds=bounds, nx=nx, ny=ny, ops=ops)
