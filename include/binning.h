@@ -267,7 +267,8 @@ int bin_set_plan_override(int32_t strategy, int32_t block, int32_t grid);
 /* Tuning parameters of the partition strategy for later calls made by this
  * thread (autotuner, tests); value 0 restores the planner's choice.
  *  BIN_TUNE_PART_WG          workgroups of the count and scatter passes
- *  BIN_TUNE_SCATTER_PPT      particles per thread per scatter sub-chunk (4, 8, 16 or 32)
+ *  BIN_TUNE_SCATTER_PPT      particles per thread per scatter sub-chunk (4, 8, 12, 16 or
+ *                            32; 12 with 1024 threads only, else taken as 8)
  *  BIN_TUNE_SCATTER_THREADS  threads per scatter workgroup (256, 512 or 1024)
  *  BIN_TUNE_TILE_SHIFT       log2 of the largest tile (6..15)
  *  BIN_TUNE_SPLIT_LEN        max records per binning work item (>= 1024)

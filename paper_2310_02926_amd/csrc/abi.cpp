@@ -194,8 +194,8 @@ int bin_set_tuning(int32_t param, int64_t value) {
       t_hints.part_wg = (int)value;
       return BIN_OK;
     case BIN_TUNE_SCATTER_PPT:
-      if (value && value != 4 && value != 8 && value != 16 && value != 32)
-        return fail(BIN_ERR_INVALID_ARG, "BIN_TUNE_SCATTER_PPT must be 4, 8, 16 or 32");
+      if (value && value != 4 && value != 8 && value != 12 && value != 16 && value != 32)
+        return fail(BIN_ERR_INVALID_ARG, "BIN_TUNE_SCATTER_PPT must be 4, 8, 12, 16 or 32");
       t_hints.scatter_ppt = (int)value;
       return BIN_OK;
     case BIN_TUNE_SCATTER_THREADS:

@@ -135,7 +135,7 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
     for (int r = 0; r < R; ++r) {
       const Prepared& p = bp->preps[g.idx[r]];
       const size_t sv = al16(16 * (size_t)p.part.ntiles + 4 * S);
-      scatter_lds = std::max(scatter_lds, sv + S * p.part.k * asz);
+      scatter_lds = std::max(scatter_lds, sv + (p.part.k ? S * asz : 0));
     }
     g.cfg.ppt = ppt;
     g.cfg.scatter_threads = nt;

@@ -223,6 +223,56 @@ struct Tile {
     }
   }
 
+  // add() for R records at once (lb[u] < 0: no record).  Every LDS read
+  // of the R records (the min/max filter, the compensated sum's old value)
+  // is issued before any of them is used, so the wave waits for LDS once
+  // per group instead of once per record.
+  template <int R>
+  __device__ static void add_batch(unsigned char* smem, const TileLayout& L, int j, const int* lb, const AT* v) {
+    if (L.want_sum) {
+      unsigned char* base = smem + L.lds_sum_off[j];
+      if constexpr (PREC == PREC_F64) {
+#pragma unroll
+        for (int u = 0; u < R; ++u)
+          if (lb[u] >= 0) atomicAdd(reinterpret_cast<double*>(base) + lb[u], (double)v[u]);
+      } else if constexpr (PREC == PREC_PLAIN) {
+#pragma unroll
+        for (int u = 0; u < R; ++u)
+          if (lb[u] >= 0) atomicAdd(reinterpret_cast<float*>(base) + lb[u], (float)v[u]);
+      } else {
+        float* S = reinterpret_cast<float*>(base);
+        float old[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) old[u] = lb[u] >= 0 ? atomicAdd(S + lb[u], (float)v[u]) : 0.0f;
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          if (lb[u] < 0) continue;
+          const float fv = (float)v[u];
+          const float e = two_sum_err(old[u], fv, old[u] + fv);
+          if (e != 0.0f) atomicAdd(S + L.tb + lb[u], e);
+        }
+      }
+    }
+    if (L.want_min || L.want_max) {
+      K kv[R], cmin[R], cmax[R];
+      K* mn = reinterpret_cast<K*>(smem + L.lds_min_off[j]);
+      K* mx = reinterpret_cast<K*>(smem + L.lds_max_off[j]);
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        kv[u] = fkey(v[u]);
+        const int b = lb[u] >= 0 ? lb[u] : 0;
+        cmin[u] = L.want_min ? __hip_atomic_load(mn + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : K(0);
+        cmax[u] = L.want_max ? __hip_atomic_load(mx + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : K(0);
+      }
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        if (lb[u] < 0) continue;
+        if (L.want_min && kv[u] < cmin[u]) atomicMin(mn + lb[u], kv[u]);
+        if (L.want_max && kv[u] > cmax[u]) atomicMax(mx + lb[u], kv[u]);
+      }
+    }
+  }
+
   __device__ static uint32_t cnt_get(const unsigned char* smem, int b) {
     return reinterpret_cast<const uint32_t*>(smem)[b];
   }

@@ -105,10 +105,10 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t* wave_t
 // request are read with 16-byte loads and no bounds tests, and the next
 // one's coordinates are loaded while the current one is sorted and written;
 // the remainder (and unaligned requests) take a bounds-tested path with 4
-// particles per thread.  Three barriers per sub-chunk: the tile counters are
-// double-buffered, and one wave scans them, adds them to the slice totals
-// and clears the other buffer.
-// LDS: cnt[2][T] | off[T] | tot[T] | (tile << 16 | local bin)[S] | values[k][S]
+// particles per thread.  Three barriers per sub-chunk (two more per extra
+// attribute): the tile counters are double-buffered, and one wave scans
+// them, adds them to the slice totals and clears the other buffer.
+// LDS: cnt[2][T] | off[T] | tot[T] | (tile << 16 | local bin)[S] | values[S]
 // ---------------------------------------------------------------------------
 struct ScatterShared {
   uint32_t nsub;
@@ -136,8 +136,11 @@ __device__ __forceinline__ void scatter_sub(const PartArgs& a, unsigned char* sm
   // attribute's values are loaded before the bins are located, so their
   // latency hides behind locating, ranking and the scan.
   const uint32_t lane4 = 4u * threadIdx.x;
-  AT v0[PPT];
-  if (k > 0) {
+  // (Sub-chunks of 16 or more particles per thread have no registers to
+  // spare for this: they load the values when they stage them.)
+  constexpr bool kPre = PPT <= 12;
+  AT v0[kPre ? PPT : 1];
+  if (kPre && k > 0) {
     if constexpr (FULL) {
       const AT* ab = static_cast<const AT*>(a.attr[0]) + base;
 #pragma unroll
@@ -214,11 +217,40 @@ __device__ __forceinline__ void scatter_sub(const PartArgs& a, unsigned char* sm
     stg_tb[pos[u]] = tb[u];
   }
   if (k > 0) {
+    if constexpr (kPre) {
 #pragma unroll
-    for (int u = 0; u < PPT; ++u)
-      if (tb[u] != 0xFFFFFFFFu) stg_v[pos[u]] = v0[u];
+      for (int u = 0; u < PPT; ++u)
+        if (tb[u] != 0xFFFFFFFFu) stg_v[pos[u]] = v0[kPre ? u : 0];
+    } else {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        AT v[4];
+        if constexpr (FULL)
+          ld4v<AT>(static_cast<const AT*>(a.attr[0]) + base, lane4 + 4u * q * NT, v);
+        else
+          ld4<AT>(a.attr[0], base + 4 * ((int64_t)q * NT + threadIdx.x), hi, false, v);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (tb[4 * q + e] != 0xFFFFFFFFu) stg_v[pos[4 * q + e]] = v[e];
+      }
+    }
   }
+  __syncthreads();
+  // One contiguous stream of records over [base, base + nsub).
+  uint16_t* rb = a.rec_bin + base;
+  for (uint32_t p = threadIdx.x; p < nsub; p += NT) rb[p] = (uint16_t)(stg_tb[p] & 0xFFFFu);
+  if (k > 0) {
+    AT* rv = static_cast<AT*>(a.rec_val[0]) + base;
+    for (uint32_t p = threadIdx.x; p < nsub; p += NT) rv[p] = stg_v[p];
+  }
+  // Further attributes reuse the one value stage (the positions are the
+  // same), so the stage is as large for k attributes as for one.  Keeping
+  // the positions live costs registers: requests with two or more
+  // attributes run sub-chunks of at most 8192 particles (the planner's
+  // rule), and only those instances carry this loop.
+  if constexpr (S <= 8192)
   for (int j = 1; j < k; ++j) {
+    __syncthreads();  // the previous attribute's copy-out has read the stage
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       AT v[4];
@@ -228,16 +260,11 @@ __device__ __forceinline__ void scatter_sub(const PartArgs& a, unsigned char* sm
         ld4<AT>(a.attr[j], base + 4 * ((int64_t)q * NT + threadIdx.x), hi, false, v);
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        if (tb[4 * q + e] != 0xFFFFFFFFu) stg_v[(int64_t)j * S + pos[4 * q + e]] = v[e];
+        if (tb[4 * q + e] != 0xFFFFFFFFu) stg_v[pos[4 * q + e]] = v[e];
     }
-  }
-  __syncthreads();
-  // One contiguous stream of records over [base, base + nsub).
-  uint16_t* rb = a.rec_bin + base;
-  for (uint32_t p = threadIdx.x; p < nsub; p += NT) rb[p] = (uint16_t)(stg_tb[p] & 0xFFFFu);
-  for (int j = 0; j < k; ++j) {
+    __syncthreads();
     AT* rv = static_cast<AT*>(a.rec_val[j]) + base;
-    for (uint32_t p = threadIdx.x; p < nsub; p += NT) rv[p] = stg_v[(int64_t)j * S + p];
+    for (uint32_t p = threadIdx.x; p < nsub; p += NT) rv[p] = stg_v[p];
   }
 }
 
@@ -369,10 +396,11 @@ __device__ __forceinline__ void part_items_walk_body(const PartArgs& a, int blk)
 // tiles, 4 tiles per thread) and writes them out.
 __device__ __forceinline__ void part_items_place_body(const PartArgs& a) {
   __shared__ uint32_t wave_tot[16];
+  __shared__ uint32_t fi[4096];  // first item of each tile (T <= 4096)
   const int T = a.ntiles;
   const int t0 = 4 * threadIdx.x;
   uint32_t ni[4], nrec[4];
-  uint32_t own = 0, sown = 0;
+  uint32_t own = 0, sown = 0, nsplit = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     ni[q] = 0;
@@ -382,39 +410,50 @@ __device__ __forceinline__ void part_items_place_body(const PartArgs& a) {
       ni[q] = nrec[q] ? a.tile_items[3 * (t0 + q) + 1] : 1u;
       own += ni[q];
       sown += ni[q] > 1 ? ni[q] : 0u;
+      nsplit += ni[q] > 1 ? 1u : 0u;
     }
   }
-  uint32_t nsplit = 0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) nsplit += ni[q] > 1 ? 1u : 0u;
   uint32_t tot, stot, ntot;
   uint32_t first = block_scan_excl<1024>(own, wave_tot, tot);
   uint32_t sfirst = block_scan_excl<1024>(sown, wave_tot, stot);
   uint32_t lfirst = block_scan_excl<1024>(nsplit, wave_tot, ntot);
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
-    if (ni[q] > 1) a.split_list[lfirst++] = (uint32_t)(t0 + q);
-  if (threadIdx.x == 0) a.split_list[T] = ntot;
-  const uint32_t cap = (uint32_t)a.max_items;  // a proven upper bound; the guards keep stores in range
-#pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int t = t0 + q;
     if (t >= T) continue;
+    if (ni[q] > 1) a.split_list[lfirst++] = (uint32_t)t;
     a.tile_items[3 * t] = first;
     a.tile_items[3 * t + 1] = ni[q];
     a.tile_items[3 * t + 2] = sfirst;
-    const uint32_t* list = a.ilist + (int64_t)t * a.nwg;
-    for (uint32_t i = 0; i < ni[q]; ++i) {
-      const uint32_t it = first + i;
-      if (it >= cap) break;
-      a.items[3 * it] = (uint32_t)t;
-      a.items[3 * it + 1] = nrec[q] ? list[i] : 0u;
-      a.items[3 * it + 2] = nrec[q] ? (i + 1 < ni[q] ? list[i + 1] : (uint32_t)a.nwg) : 0u;
-    }
+    // an empty tile's item has no slices: its end slice is written as 0 below
+    fi[t] = first | (nrec[q] ? 0u : 0x80000000u);
     first += ni[q];
     sfirst += ni[q] > 1 ? ni[q] : 0u;
   }
-  if (threadIdx.x == 0) *a.n_items = tot < cap ? tot : cap;
+  if (threadIdx.x == 0) a.split_list[T] = ntot;
+  __syncthreads();
+  // Item i: its tile is the last one whose first item is <= i (every tile
+  // has at least one item, so the firsts strictly increase).
+  const uint32_t cap = (uint32_t)a.max_items;  // a proven upper bound; the guards keep stores in range
+  const uint32_t nitems = tot < cap ? tot : cap;
+  for (uint32_t i = threadIdx.x; i < nitems; i += blockDim.x) {
+    int lo = 0, hi = T - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if ((fi[mid] & 0x7FFFFFFFu) <= i) lo = mid;
+      else hi = mid - 1;
+    }
+    const int t = lo;
+    const uint32_t f = fi[t] & 0x7FFFFFFFu;
+    const bool empty = (fi[t] >> 31) != 0;
+    const uint32_t idx = i - f;
+    const uint32_t nxt = t + 1 < T ? (fi[t + 1] & 0x7FFFFFFFu) : tot;
+    const uint32_t* list = a.ilist + (int64_t)t * a.nwg;
+    a.items[3 * i] = (uint32_t)t;
+    a.items[3 * i + 1] = empty ? 0u : list[idx];
+    a.items[3 * i + 2] = empty ? 0u : (i + 1 < nxt ? list[idx + 1] : (uint32_t)a.nwg);
+  }
+  if (threadIdx.x == 0) *a.n_items = nitems;
 }
 
 __global__ __launch_bounds__(1024) void part_items_walk_kernel(PartArgs a) { part_items_walk_body(a, blockIdx.x); }
@@ -474,11 +513,18 @@ __device__ __forceinline__ void part_bin_body(const PartArgs& a, int item) {
       }
     }
   };
+  // Groups of 64 sub-chunks; with fewer groups than waves, wpg waves share
+  // a group and take every wpg-th window of its records.
+  const uint32_t ngroups = (nblk + 63) / 64;
+  uint32_t wpg = 1;
+  while (wpg < nwaves && ngroups * wpg * 2 <= nwaves) wpg *= 2;
+  const uint32_t gstride = nwaves / wpg;
+  const uint32_t sub = wid % wpg;
   uint32_t nlen, nrs;  // the next group's run, read while this group is binned
-  run_of(wid * 64 + lane, nlen, nrs);
-  for (uint32_t c0 = wid * 64; c0 < nblk; c0 += nwaves * 64) {
+  run_of((wid / wpg) * 64 + lane, nlen, nrs);
+  for (uint32_t g = wid / wpg; g < ngroups; g += gstride) {
     const uint32_t len = nlen, rs = nrs;  // first record of the lane's run
-    run_of(c0 + nwaves * 64 + lane, nlen, nrs);
+    run_of((g + gstride) * 64 + lane, nlen, nrs);
     uint32_t incl = len;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -489,18 +535,17 @@ __device__ __forceinline__ void part_bin_body(const PartArgs& a, int item) {
     const uint32_t start = rs - (incl - len);  // record = start + q for q in the lane's run
     // R windows of 64 records at a time: all their loads are issued before
     // the first LDS update, so R gathers per wave are in flight.
-    constexpr int R = 8;
-    for (uint32_t r = 0; r < total; r += 64 * R) {
+    constexpr int R = sizeof(AT) == 8 ? 4 : 8;
+    for (uint32_t wb = 0; 64 * (sub + wpg * wb) < total; wb += R) {
       uint32_t rec[R];
       int lb[R];
-      AT v0[R];
 #pragma unroll
       for (int u = 0; u < R; ++u) {
         // Window of records [w0q, w0q + 64): the runs holding its first and
         // last records are found with two ballots (wave-uniform), and each
         // lane picks the last run in that range starting at or before its
         // record, reading run starts with readlane (no LDS traffic).
-        const uint32_t w0q = r + 64 * u;
+        const uint32_t w0q = 64 * (sub + wpg * (wb + u));
         uint32_t recu = 0xFFFFFFFFu;
         if (w0q < total) {
           const uint32_t wl = w0q + 63 < total ? w0q + 63 : total - 1;
@@ -517,26 +562,30 @@ __device__ __forceinline__ void part_bin_body(const PartArgs& a, int item) {
         }
         rec[u] = recu;
       }
+      // Every load of the R windows - bins and the first four attributes -
+      // is issued before the first LDS update.
+      constexpr int KV = sizeof(AT) == 8 ? 2 : 4;
+      AT v[KV][R];
 #pragma unroll
-      for (int u = 0; u < R; ++u) {
+      for (int u = 0; u < R; ++u)
         lb[u] = rec[u] != 0xFFFFFFFFu ? (int)__builtin_nontemporal_load(a.rec_bin + rec[u]) : -1;
-        v0[u] = (rec[u] != 0xFFFFFFFFu && k > 0) ? ld<AT>(a.rec_val[0], rec[u]) : AT(0);
-      }
+#pragma unroll
+      for (int jj = 0; jj < KV; ++jj)
+        if (jj < k) {
+#pragma unroll
+          for (int u = 0; u < R; ++u) v[jj][u] = rec[u] != 0xFFFFFFFFu ? ld<AT>(a.rec_val[jj], rec[u]) : AT(0);
+        }
 #pragma unroll
       for (int u = 0; u < R; ++u)
         if (lb[u] >= 0) TL::count(smem, lb[u]);
-      if (k > 0) {
 #pragma unroll
-        for (int u = 0; u < R; ++u)
-          if (lb[u] >= 0) TL::add(smem, a.lay, 0, lb[u], v0[u]);
-      }
-      for (int jj = 1; jj < k; ++jj) {
-        AT v[R];
+      for (int jj = 0; jj < KV; ++jj)
+        if (jj < k) TL::template add_batch<R>(smem, a.lay, jj, lb, v[jj]);
+      for (int jj = KV; jj < k; ++jj) {
+        AT w[R];
 #pragma unroll
-        for (int u = 0; u < R; ++u) v[u] = lb[u] >= 0 ? ld<AT>(a.rec_val[jj], rec[u]) : AT(0);
-#pragma unroll
-        for (int u = 0; u < R; ++u)
-          if (lb[u] >= 0) TL::add(smem, a.lay, jj, lb[u], v[u]);
+        for (int u = 0; u < R; ++u) w[u] = rec[u] != 0xFFFFFFFFu ? ld<AT>(a.rec_val[jj], rec[u]) : AT(0);
+        TL::template add_batch<R>(smem, a.lay, jj, lb, w);
       }
     }
   }
@@ -622,7 +671,7 @@ __global__ __launch_bounds__(1024) void part_merge_batched(const PartArgs* __res
     BK_SC(KERNEL, GRID, 512, 4, __VA_ARGS__) BK_SC(KERNEL, GRID, 512, 8, __VA_ARGS__)         \
     BK_SC(KERNEL, GRID, 512, 16, __VA_ARGS__) BK_SC(KERNEL, GRID, 512, 32, __VA_ARGS__)       \
     BK_SC(KERNEL, GRID, 1024, 4, __VA_ARGS__) BK_SC(KERNEL, GRID, 1024, 8, __VA_ARGS__)       \
-    BK_SC(KERNEL, GRID, 1024, 16, __VA_ARGS__)                                                \
+    BK_SC(KERNEL, GRID, 1024, 12, __VA_ARGS__) BK_SC(KERNEL, GRID, 1024, 16, __VA_ARGS__)     \
     default:                                                                                  \
       return hipErrorInvalidConfiguration;                                                    \
   }
@@ -692,7 +741,7 @@ hipError_t set_partition_lds_limit(size_t bytes) {
   BK_SETF(K<CT, AT, 4, NT>) BK_SETF(K<CT, AT, 8, NT>) BK_SETF(K<CT, AT, 16, NT>)
 #define BK_SET_CA(K, CT, AT) \
   BK_SET_NT(K, CT, AT, 256) BK_SETF(K<CT, AT, 32, 256>) BK_SET_NT(K, CT, AT, 512) BK_SETF(K<CT, AT, 32, 512>) \
-  BK_SET_NT(K, CT, AT, 1024)
+  BK_SET_NT(K, CT, AT, 1024) BK_SETF(K<CT, AT, 12, 1024>)
 #define BK_SET_TYPES(K) \
   BK_SET_CA(K, float, float) BK_SET_CA(K, float, double) BK_SET_CA(K, double, float) BK_SET_CA(K, double, double)
   BK_SET_TYPES(part_scatter_kernel)

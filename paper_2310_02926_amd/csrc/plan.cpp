@@ -167,6 +167,13 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints_
     tile_lds = tile_layout(1 << shift, nk, want_sum, want_min, want_max, p->prec, asz, &tl);
     if (tile_lds <= lds_budget) break;
   }
+  // Smaller tiles while the grid would give fewer than two tiles per CU:
+  // the tile binning then runs one item per tile on every CU, each with a
+  // smaller LDS footprint, instead of splitting a few tiles into many
+  // partial slots that have to be merged.
+  if (!hints.tile_shift)
+    while (shift > 6 && ceil_div(nb, (int64_t)1 << shift) < 2 * (int64_t)cus) --shift;
+  tile_lds = tile_layout(1 << std::max(shift, 6), nk, want_sum, want_min, want_max, p->prec, asz, &tl);
   tl.tile_shift = shift;
   const int64_t ntiles = ceil_div(nb, (int64_t)1 << shift);
   int strat;
@@ -240,15 +247,20 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints_
     bool aligned = ((uintptr_t)a.x % 16 == 0) && ((uintptr_t)a.y % 16 == 0);
     for (int j = 0; j < nk; ++j) aligned = aligned && ((uintptr_t)a.attr[j] % 16 == 0);
     a.vec = aligned ? 1 : 0;
-    // split length: no split when tiles are balanced, bounded work otherwise
-    int64_t L = std::max<int64_t>({ceil_div(2 * n, ntiles), ceil_div(n, (int64_t)cus), 16384});
+    // Split length.  With at least one tile per CU the tiles alone fill the
+    // device: only tiles above twice the average are split.  With fewer
+    // tiles, items of about n / (2 CUs) records keep every CU busy.
+    int64_t L = ntiles >= cus ? std::max<int64_t>(ceil_div(2 * n, ntiles), ceil_div(n, 2 * (int64_t)cus))
+                              : ceil_div(n, 2 * (int64_t)cus);
+    L = std::max<int64_t>(L, 16384);
     if (hints.split_len) L = hints.split_len;
     a.split_len = (uint32_t)std::min<int64_t>(L, 0x7FFFFFFF);
     // Items group whole slices greedily; two consecutive items of a tile
     // hold more than split_len records together, so a tile with R records
     // has at most 2 + 2 R / split_len items.
     a.max_items = (int32_t)(2 * ntiles + 2 * ceil_div(n, (int64_t)a.split_len));
-    // scatter LDS: 4 T counters, S tile/bin words, S * k values
+    // scatter LDS: 4 T counters, S tile/bin words, S values (one attribute
+    // at a time)
     // 1024-thread scatter workgroups measured fastest on MI355X for both the
     // 1- and 4-attribute workloads (one workgroup per CU, LDS-bound).
     // Largest scatter stage that fits LDS: 1024 threads first (fastest on
@@ -261,11 +273,14 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints_
     size_t sc = 0;
     const bool wide = p->coord_f64 || p->attr_f64;
     for (int tnt = hints.scatter_threads ? hints.scatter_threads : 1024; tnt >= 256 && !ppt; tnt /= 2) {
-      const int cap = tnt >= 1024 ? (wide ? 8 : 16) : (p->coord_f64 ? 16 : 32);
-      for (int tp = std::min(hints.scatter_ppt ? hints.scatter_ppt : 16, cap); tp >= 4; tp /= 2) {
+      int cap = tnt >= 1024 ? (wide ? 8 : 16) : (p->coord_f64 ? 16 : 32);
+      if (nk >= 2) cap = std::min(cap, 8192 / tnt);  // multi-attribute sub-chunks hold <= 8192
+      int tp0 = std::min(hints.scatter_ppt ? hints.scatter_ppt : 16, cap);
+      if (tp0 == 12 && tnt != 1024) tp0 = 8;  // 12 per thread exists for 1024 threads only
+      for (int tp = tp0; tp >= 4; tp = tp == 12 ? 8 : tp / 2) {
         const size_t S = (size_t)tnt * tp;
         const int32_t svo = (int32_t)align16(16 * (size_t)T + 4 * S);
-        const size_t need = svo + S * nk * asz;
+        const size_t need = svo + (nk ? S * asz : 0);
         if (need + kScatterStatic <= lds_budget) {
           nt = tnt;
           ppt = tp;
@@ -281,7 +296,8 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints_
     c.scatter_threads = nt;
     c.scatter_lds = std::max<size_t>(sc, 16);
     c.bin_lds = tile_lds;
-    c.bin_block = 1024;
+    // Half-size workgroups when two tiles fit a CU's LDS: two items per CU.
+    c.bin_block = 2 * tile_lds <= dev.lds_per_cu ? 512 : 1024;
     set_part_blocks(a, nt, ppt);
     // scratch
     a.counts = static_cast<uint32_t*>(cv.take(4 * (size_t)ntiles * a.nwg));
