@@ -202,7 +202,7 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
       g.block = std::max(g.block, p.cfg.block);
       for (int s = 0; s < a.nslots; ++s) g.map_slot.push_back(((uint32_t)r << 16) | (uint32_t)s);
       if (a.nslots > 1)
-        for (int64_t c = 0; c < cdiv(a.nbins, 256); ++c) g.map_merge.push_back(((uint32_t)r << 16) | (uint32_t)c);
+        for (int64_t c = 0; c < cdiv(a.nbins, 64); ++c) g.map_merge.push_back(((uint32_t)r << 16) | (uint32_t)c);
     }
     g.b.nreq = R;
     g.b.n_slot_blocks = (int32_t)g.map_slot.size();

@@ -338,6 +338,71 @@ struct Tile {
     }
   }
 
+  // Combine slots first..first+nslot-1 for 64 consecutive bins [b0, b0+64)
+  // (local index lb = gb - goff) with a 1024-thread workgroup: 16 threads
+  // per bin each fold every 16th slot, then the 16 partials are combined in
+  // LDS and the finished bin is emitted.  Many slots are merged in
+  // parallel instead of one slot after another.
+  __device__ static void merge_emit64(const unsigned char* slots, int64_t slot_bytes, uint32_t first, uint32_t nslot,
+                                      const TileLayout& L, const Outs& o, int k, int64_t b0, int64_t nb,
+                                      int64_t goff) {
+    __shared__ double red_s[16][64];
+    __shared__ K red_mn[16][64];
+    __shared__ K red_mx[16][64];
+    __shared__ uint32_t red_c[16][64];
+    const int bl = threadIdx.x & 63;
+    const int sg = threadIdx.x >> 6;  // 16 slot groups (blockDim.x == 1024)
+    const int64_t gb = b0 + bl;
+    const bool live = gb < nb;
+    const int lb = (int)(gb - goff);
+    uint32_t c = 0;
+    if (live)
+      for (uint32_t q = sg; q < nslot; q += 16)
+        c += reinterpret_cast<const uint32_t*>(slots + (int64_t)(first + q) * slot_bytes)[lb];
+    red_c[sg][bl] = c;
+    __syncthreads();
+    if (sg == 0) {
+      for (int g = 1; g < 16; ++g) c += red_c[g][bl];
+      red_c[0][bl] = c;
+      if (live && o.cnt) o.cnt[gb] = c;
+    }
+    __syncthreads();
+    c = red_c[0][bl];
+    for (int j = 0; j < k; ++j) {
+      double s = 0.0;
+      K kmin = fkey((AT)INFINITY), kmax = fkey((AT)-INFINITY);
+      if (live)
+        for (uint32_t q = sg; q < nslot; q += 16) {
+          const unsigned char* slot = slots + (int64_t)(first + q) * slot_bytes;
+          if (L.want_sum) {
+            if constexpr (PREC == PREC_PLAIN) s += (double)reinterpret_cast<const float*>(slot + L.slot_sum_off[j])[lb];
+            else s += reinterpret_cast<const double*>(slot + L.slot_sum_off[j])[lb];
+          }
+          if (L.want_min) {
+            const K m = reinterpret_cast<const K*>(slot + L.slot_min_off[j])[lb];
+            kmin = m < kmin ? m : kmin;
+          }
+          if (L.want_max) {
+            const K m = reinterpret_cast<const K*>(slot + L.slot_max_off[j])[lb];
+            kmax = m > kmax ? m : kmax;
+          }
+        }
+      red_s[sg][bl] = s;
+      red_mn[sg][bl] = kmin;
+      red_mx[sg][bl] = kmax;
+      __syncthreads();
+      if (sg == 0 && live) {
+        for (int g = 1; g < 16; ++g) {
+          s += red_s[g][bl];
+          kmin = red_mn[g][bl] < kmin ? red_mn[g][bl] : kmin;
+          kmax = red_mx[g][bl] > kmax ? red_mx[g][bl] : kmax;
+        }
+        emit_attr(o, j, gb, c, s, kmin, kmax);
+      }
+      __syncthreads();
+    }
+  }
+
   // Combine slots first..first+nslot-1 for local bin b and emit it.
   __device__ static void merge_emit(const unsigned char* slots, int64_t slot_bytes, uint32_t first, uint32_t nslot,
                                     const TileLayout& L, const Outs& o, int k, int b, int64_t gb) {

@@ -197,26 +197,21 @@ __global__ __launch_bounds__(1024) void bin_lds_batched(const LdsArgs* __restric
   bin_lds_body<CT, AT, PREC>(d[m >> 16], (int)(m & 0xFFFFu));
 }
 
-// Merge the slots of bins [b0, b0 + blockDim.x).
+// Merge the slots of bins [b0, b0 + 64) (1024-thread workgroups).
 template <typename AT, int PREC>
-__device__ __forceinline__ void lds_merge_body(const LdsArgs& a, int64_t b0) {
-  const int64_t b = b0 + threadIdx.x;
-  if (b < a.nbins)
-    Tile<AT, PREC>::merge_emit(static_cast<const unsigned char*>(a.partial), a.lay.slot_bytes, 0u,
-                               (uint32_t)a.nslots, a.lay, a.out, a.k, (int)b, b);
-}
-
-template <typename AT, int PREC>
-__global__ __launch_bounds__(256) void lds_merge_kernel(LdsArgs a) {
-  for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x; b0 < a.nbins; b0 += (int64_t)gridDim.x * blockDim.x)
-    lds_merge_body<AT, PREC>(a, b0);
+__global__ __launch_bounds__(1024) void lds_merge_kernel(LdsArgs a) {
+  for (int64_t b0 = (int64_t)blockIdx.x * 64; b0 < a.nbins; b0 += (int64_t)gridDim.x * 64)
+    Tile<AT, PREC>::merge_emit64(static_cast<const unsigned char*>(a.partial), a.lay.slot_bytes, 0u,
+                                 (uint32_t)a.nslots, a.lay, a.out, a.k, b0, a.nbins, 0);
 }
 template <typename AT, int PREC>
-__global__ __launch_bounds__(256) void lds_merge_batched(const LdsArgs* __restrict__ d,
-                                                         const uint32_t* __restrict__ map) {
+__global__ __launch_bounds__(1024) void lds_merge_batched(const LdsArgs* __restrict__ d,
+                                                          const uint32_t* __restrict__ map) {
   const uint32_t m = map[blockIdx.x];
   const LdsArgs& a = d[m >> 16];
-  if (a.nslots > 1) lds_merge_body<AT, PREC>(a, (int64_t)(m & 0xFFFFu) * 256);
+  if (a.nslots > 1)
+    Tile<AT, PREC>::merge_emit64(static_cast<const unsigned char*>(a.partial), a.lay.slot_bytes, 0u,
+                                 (uint32_t)a.nslots, a.lay, a.out, a.k, (int64_t)(m & 0xFFFFu) * 64, a.nbins, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -238,9 +233,9 @@ static hipError_t launch_lds_t(const LdsArgs& a, const LaunchCfg& c, hipStream_t
   if (tm) tm->end("bin_lds_kernel", s);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (a.nslots > 1) {
-    const int64_t g = (a.nbins + 255) / 256;
+    const int64_t g = (a.nbins + 63) / 64;
     if (tm) tm->begin(s);
-    hipLaunchKernelGGL((lds_merge_kernel<AT, PREC>), dim3((int)(g < 4096 ? g : 4096)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((lds_merge_kernel<AT, PREC>), dim3((int)(g < 4096 ? g : 4096)), dim3(1024), 0, s, a);
     if (tm) tm->end("lds_merge_kernel", s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
@@ -259,7 +254,7 @@ static hipError_t launch_lds_batch_t(const LdsBatch& b, size_t lds_bytes, int bl
   }
   if (b.n_merge_blocks > 0) {
     if (tm) tm->begin(s);
-    hipLaunchKernelGGL((lds_merge_batched<AT, PREC>), dim3(b.n_merge_blocks), dim3(256), 0, s, b.descs, b.map_merge);
+    hipLaunchKernelGGL((lds_merge_batched<AT, PREC>), dim3(b.n_merge_blocks), dim3(1024), 0, s, b.descs, b.map_merge);
     if (tm) tm->end("lds_merge_kernel", s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
