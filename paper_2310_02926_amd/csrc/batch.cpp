@@ -328,6 +328,7 @@ int run_batch(const bin_request* reqs, int nreq, hipStream_t s, const PlanHints&
   int st = validate_requests(reqs, nreq);
   if (st) return st;
   if (nreq == 0) return BIN_OK;
+  if (nreq == 1) return run_request(reqs[0], s, hints);  // the single-request kernels
   DeviceInfo dev;
   st = device_info(&dev);
   if (st) return st;

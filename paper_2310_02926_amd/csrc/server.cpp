@@ -283,7 +283,9 @@ bool dispatch_one(binsrv* s, std::unique_lock<std::mutex>& lk) {
   hipEvent_t ev = sl.done;
   // Launch outside the lock: submitters and waiters keep going.
   lk.unlock();
-  int st = run_batch(brs.data(), (int)brs.size(), stream, PlanHints{});
+  // A lone request takes the single-request kernels (their tuned shapes).
+  int st = brs.size() == 1 ? run_request(brs[0], stream, PlanHints{})
+                           : run_batch(brs.data(), (int)brs.size(), stream, PlanHints{});
   hipError_t e = hipSuccess;
   if (st == BIN_OK) e = hipEventRecord(ev, stream);
   lk.lock();
