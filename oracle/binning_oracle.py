@@ -26,7 +26,8 @@ the HIP path) are:
 * R5 avg = sum / count, formed from the binary64 sum.
 * R6 min and max follow IEEE 754 totalOrder on non-NaN values (so -0 < +0).
 * R7 bins are cells, stored row-major ``[ny][nx]`` with flat index
-  ``iy * nx + ix``.
+  ``iy * nx + ix``; with one or three axes (``bin_particles_nd``) axis 0
+  still varies fastest: ``[nz][ny][nx]``, flat ``(iz * ny + iy) * nx + ix``.
 * R8 sums are reference values in binary64; besides them the oracle reports
   ``abs_sum`` = per-bin sum of |a|, the scale used by sum tolerances.
 * R9 bounds taken from the data (``bounds=None``): per axis the minimum and
@@ -36,8 +37,10 @@ the HIP path) are:
   no finite value leaves every bin empty.
 
 Parity pins: brute force (exact rational index, exactly rounded sums) on
-small inputs; SciPy ``binned_statistic_2d`` and NumPy ``histogram2d``;
-invariants and metamorphic relations.  See tests/test_oracle_pins.py.
+small inputs; SciPy ``binned_statistic_2d`` / ``binned_statistic`` /
+``binned_statistic_dd`` and NumPy ``histogram2d`` / ``histogram`` /
+``histogramdd``; hand-worked cases; marginals of 3-D meshes; invariants and
+metamorphic relations.  See tests/test_oracle_pins.py.
 """
 from __future__ import annotations
 
@@ -115,12 +118,49 @@ def bin_particles(coords: Sequence[np.ndarray], attrs: Sequence[np.ndarray], axe
     Every op is computed; ``ops`` is accepted for signature symmetry only.
     Also ``inside`` = the number of particles inside the mesh.
     """
-    nb = nx * ny
     if bounds is None:
         bounds = auto_bounds(coords, axes)
     inside, b = flat_bins(coords, axes, bounds, nx, ny)
+    return _reduce_bins(inside, b, attrs, (ny, nx))
+
+
+def bin_particles_nd(coords: Sequence[np.ndarray], attrs: Sequence[np.ndarray], axes=(0, 1, 2),
+                     bounds=(0.0, 1.0, 0.0, 1.0, 0.0, 1.0), dims=(16, 16, 16),
+                     ops: int = ALL_OPS) -> Dict[str, object]:
+    """Bin onto a mesh of one, two or three axes (Section 4.2: the mesh axes
+    are any chosen subset of the particle variables).
+
+    ``axes[j]`` names the column of axis j, ``bounds[2j], bounds[2j+1]`` its
+    lower and upper bound, ``dims[j]`` its number of bins.  Every axis follows
+    R1-R3 on its own; a particle is inside iff it is inside on every axis.
+    Row-major generalised from R7: axis 0 varies fastest, so the result arrays
+    have shape ``dims`` reversed and the flat index is
+    ``i0 + dims[0] * (i1 + dims[1] * i2)``.  ``bounds=None`` takes every axis's
+    bounds from the data (R9).
+    """
+    d = len(axes)
+    if not 1 <= d <= 3 or len(dims) != d:
+        raise ValueError("one to three axes, one bin count per axis")
+    if bounds is None:
+        bounds = auto_bounds(coords, axes)
+    n = len(coords[axes[0]])
+    inside = np.ones(n, dtype=bool)
+    flat = np.zeros(n, dtype=np.int64)
+    stride = 1
+    for j in range(d):
+        inj, ij = axis_index(coords[axes[j]], bounds[2 * j], bounds[2 * j + 1], dims[j])
+        inside &= inj
+        flat += ij * stride
+        stride *= int(dims[j])
+    return _reduce_bins(inside, flat[inside], attrs, tuple(int(v) for v in reversed(dims)))
+
+
+def _reduce_bins(inside, b, attrs, shape) -> Dict[str, object]:
+    """Per-bin count, and per attribute sum/min/max/avg/abs_sum (R4-R6, R8),
+    of the inside particles whose flat bin indices are ``b``."""
+    nb = int(np.prod(shape))
     count = np.bincount(b, minlength=nb).astype(np.int64)
-    res = {"count": count.reshape(ny, nx), "sum": [], "min": [], "max": [], "avg": [],
+    res = {"count": count.reshape(shape), "sum": [], "min": [], "max": [], "avg": [],
            "abs_sum": [], "inside": int(inside.sum())}
     empty = count == 0
     for a in attrs:
@@ -137,11 +177,11 @@ def bin_particles(coords: Sequence[np.ndarray], attrs: Sequence[np.ndarray], axe
         with np.errstate(invalid="ignore", divide="ignore"):
             avg = np.where(empty, np.nan, s / np.maximum(count, 1))
         s = np.where(empty, 0.0, s)
-        res["sum"].append(s.reshape(ny, nx))
-        res["min"].append(mn.reshape(ny, nx))
-        res["max"].append(mx.reshape(ny, nx))
-        res["avg"].append(avg.reshape(ny, nx))
-        res["abs_sum"].append(asum.reshape(ny, nx))
+        res["sum"].append(s.reshape(shape))
+        res["min"].append(mn.reshape(shape))
+        res["max"].append(mx.reshape(shape))
+        res["avg"].append(avg.reshape(shape))
+        res["abs_sum"].append(asum.reshape(shape))
     return res
 
 
@@ -219,6 +259,45 @@ def bin_particles_bruteforce(coords, attrs, axes=(0, 1), bounds=(0.0, 1.0, 0.0, 
         res["max"].append(mx.reshape(ny, nx))
         res["avg"].append(avg.reshape(ny, nx))
         res["abs_sum"].append(asum)
+    return res
+
+
+def bin_particles_nd_bruteforce(coords, attrs, axes, bounds, dims) -> Dict[str, object]:
+    """Brute force for one to three axes: the exact rational bin on every
+    axis, particles collected per cell tuple, cells laid out by NumPy's own
+    C order over the shape ``dims`` reversed (so no flat-index arithmetic of
+    its own), exactly rounded per-bin sums."""
+    d = len(axes)
+    if bounds is None:
+        bl = []
+        for ax in axes:
+            vals = [float(v) for v in coords[ax] if math.isfinite(float(v))]
+            bl += [min(vals), max(vals)] if vals else [math.inf, -math.inf]
+        bounds = tuple(bl)
+    shape = tuple(int(v) for v in reversed(dims))
+    members: Dict[tuple, List[int]] = {cell: [] for cell in np.ndindex(*shape)}
+    for i in range(len(coords[axes[0]])):
+        idx = [_exact_index(float(coords[axes[j]][i]), bounds[2 * j], bounds[2 * j + 1], dims[j])
+               for j in range(d)]
+        if any(v is None for v in idx):
+            continue
+        members[tuple(reversed(idx))].append(i)
+    count = np.zeros(shape, dtype=np.int64)
+    for cell, m in members.items():
+        count[cell] = len(m)
+    res = {"count": count, "sum": [], "min": [], "max": [], "avg": [], "abs_sum": [],
+           "inside": int(count.sum())}
+    for a in attrs:
+        s, asum, mn, mx, avg = (np.zeros(shape) for _ in range(5))
+        for cell, m in members.items():
+            v = [float(a[i]) for i in m]
+            s[cell] = math.fsum(v)
+            asum[cell] = math.fsum(abs(x) for x in v)
+            mn[cell] = min(v, key=_total_order_sort_key) if v else math.inf
+            mx[cell] = max(v, key=_total_order_sort_key) if v else -math.inf
+            avg[cell] = float(Fraction(math.fsum(v)) / len(v)) if v else math.nan
+        for key, arr in (("sum", s), ("min", mn), ("max", mx), ("avg", avg), ("abs_sum", asum)):
+            res[key].append(arr)
     return res
 
 

@@ -331,3 +331,164 @@ def pin_auto_bounds(orc):
 
 
 ALL_PINS.append(pin_auto_bounds)
+
+
+# --------------------------------------------------------------------------
+# One to three axes (Section 4.2: any subset of the variables spans the mesh).
+# --------------------------------------------------------------------------
+
+def orc_bruteforce_nd(coords, attrs, axes, bounds, dims):
+    from oracle import binning_oracle as real
+    return real.bin_particles_nd_bruteforce(coords, attrs, axes, bounds, dims)
+
+
+def _same_result(r, ref, nattr, sum_rel=1e-13, what=""):
+    assert r["inside"] == ref["inside"], what
+    assert r["count"].shape == ref["count"].shape, what
+    assert np.array_equal(r["count"], ref["count"]), what
+    for j in range(nattr):
+        assert np.all(np.abs(r["sum"][j] - ref["sum"][j]) <= sum_rel * ref["abs_sum"][j]), (what, "sum")
+        assert same_bits(r["min"][j], ref["min"][j]), (what, "min")
+        assert same_bits(r["max"][j], ref["max"][j]), (what, "max")
+        cnt = ref["count"]
+        ok = np.where(cnt == 0, np.isnan(r["avg"][j]),
+                      np.abs(r["avg"][j] - ref["avg"][j]) <= sum_rel * ref["abs_sum"][j] / np.maximum(cnt, 1))
+        assert np.all(ok), (what, "avg")
+
+
+def pin_nd_golden(orc):
+    with open(os.path.join(HERE, "golden", "hand_cases_nd.json")) as f:
+        cases = json.load(f)["cases"]
+    for case in cases:
+        cols = [np.array([_num(v) for v in case[c]]) for c in ("x", "y", "z") if c in case]
+        attrs = [np.array([_num(v) for v in case["a"]])]
+        r = orc.bin_particles_nd(cols, attrs, tuple(case["axes"]), tuple(case["bounds"]), tuple(case["dims"]), ALL)
+        name = case["name"]
+        assert r["inside"] == case["inside"], name
+        assert r["count"].shape == tuple(reversed(case["dims"])), name
+        assert np.array_equal(r["count"], np.array(case["count"])), name
+        assert np.array_equal(r["sum"][0], _arr(case["sum"][0])), (name, "sum")
+        for key in ("min", "max", "avg"):
+            assert same_bits(r[key][0], _arr(case[key][0])), (name, key)
+
+
+def pin_nd_bruteforce(orc):
+    """Random particles on dyadic 1-D and 3-D meshes of unequal sides (so a
+    transposed layout changes the shape or the cell), plus given-bounds and
+    data-bounds cases, against the per-cell rational brute force."""
+    rng = np.random.default_rng(31)
+    n = 700
+    cols = [rng.uniform(-0.1, 1.1, n), rng.uniform(-2.2, 2.2, n), rng.uniform(0.2, 0.8, n), rng.standard_normal(n)]
+    cols[0][:4] = [np.nan, 1.0, 0.0, np.inf]
+    cols[2][4:6] = [0.25, 0.75]
+    a = rng.standard_normal(n) * 3
+    m = rng.lognormal(0, 1, n)
+    for axes, bounds, dims in [((0, 1, 2), (0.0, 1.0, -2.0, 2.0, 0.25, 0.75), (8, 4, 2)),
+                               ((2, 0, 1), (0.25, 0.75, 0.0, 1.0, -2.0, 2.0), (2, 16, 4)),
+                               ((1, 2, 0), (-2.0, 2.0, 0.25, 0.75, 0.0, 1.0), (1, 1, 1)),
+                               ((0, 1, 2), (0.0, 1.0, -2.0, 2.0, 0.25, 0.75), (3, 5, 7)),
+                               ((1,), (-2.0, 2.0), (16,)),
+                               ((2,), (0.25, 0.75), (1,)),
+                               ((0, 3), (0.0, 1.0, -1.0, 1.0), (4, 8))]:
+        r = orc.bin_particles_nd(cols, [a, m], axes, bounds, dims, ALL)
+        _same_result(r, orc_bruteforce_nd(cols, [a, m], axes, bounds, dims), 2, what=str((axes, dims)))
+    for axes, dims in [((0, 1, 3), (4, 3, 5)), ((3,), (9,))]:
+        r = orc.bin_particles_nd(cols, [a], axes, None, dims, ALL)
+        _same_result(r, orc_bruteforce_nd(cols, [a], axes, None, dims), 1, what=f"auto {axes}")
+
+
+def pin_nd_libraries(orc):
+    """NumPy histogram/histogramdd and SciPy binned_statistic(_dd) on dyadic
+    meshes (count, sum, min, max, mean); their arrays are indexed [axis 0]
+    [axis 1][axis 2], ours the reverse."""
+    from scipy.stats import binned_statistic, binned_statistic_dd
+    rng = np.random.default_rng(41)
+    n = 20000
+    x, y, z = rng.random(n), rng.random(n) * 2 - 1, rng.random(n) * 4
+    x[:40] = 1.0
+    y[40:80] = 1.0
+    z[80:120] = 4.0
+    a = rng.standard_normal(n) + 0.25
+    # one axis
+    r = orc.bin_particles_nd([x, y, z], [a], (2,), (0.0, 4.0), (32,), ALL)
+    e = np.linspace(0, 4, 33)
+    assert np.array_equal(r["count"], np.histogram(z, bins=e)[0])
+    full = r["count"] > 0
+    for stat, key in (("sum", "sum"), ("mean", "avg")):
+        ref = binned_statistic(z, a, stat, bins=e).statistic
+        assert np.allclose(r[key][0][full], ref[full], rtol=1e-12, atol=1e-12), key
+    for stat in ("min", "max"):
+        assert np.array_equal(r[stat][0][full], binned_statistic(z, a, stat, bins=e).statistic[full]), stat
+    # three axes
+    dims = (8, 4, 16)
+    edges = [np.linspace(0, 1, 9), np.linspace(-1, 1, 5), np.linspace(0, 4, 17)]
+    r = orc.bin_particles_nd([x, y, z], [a], (0, 1, 2), (0.0, 1.0, -1.0, 1.0, 0.0, 4.0), dims, ALL)
+    h, _ = np.histogramdd(np.stack([x, y, z], axis=1), bins=edges)
+    assert np.array_equal(r["count"], h.transpose(2, 1, 0).astype(np.int64))
+    full = r["count"] > 0
+    for stat, key in (("sum", "sum"), ("mean", "avg"), ("min", "min"), ("max", "max")):
+        ref = binned_statistic_dd(np.stack([x, y, z], axis=1), a, stat, bins=edges).statistic.transpose(2, 1, 0)
+        if key in ("min", "max"):
+            assert np.array_equal(r[key][0][full], ref[full]), key
+        else:
+            assert np.allclose(r[key][0][full], ref[full], rtol=1e-12, atol=1e-12), key
+
+
+def pin_nd_reductions(orc):
+    """Marginals: summing a 3-D result over an axis gives the 2-D result over
+    the other two axes (when every particle is inside the summed axis's
+    bounds), a single z bin gives the 2-D mesh, and two axes through
+    bin_particles_nd give bin_particles bit for bit."""
+    rng = np.random.default_rng(43)
+    n = 40000
+    x, y, z = rng.uniform(-0.1, 1.1, n), rng.uniform(0, 3, n), rng.uniform(-1, 1, n)
+    a = rng.standard_normal(n)
+    b3 = (0.0, 1.0, 0.0, 3.0, -1.0, 1.0)
+    r3 = orc.bin_particles_nd([x, y, z], [a], (0, 1, 2), b3, (10, 6, 5), ALL)
+    r2 = orc.bin_particles([x, y, z], [a], (0, 1), b3[:4], 10, 6, ALL)
+    assert np.array_equal(r3["count"].sum(axis=0), r2["count"])
+    assert np.allclose(r3["sum"][0].sum(axis=0), r2["sum"][0], rtol=1e-12, atol=1e-12)
+    mn = np.min(np.where(r3["count"] > 0, r3["min"][0], np.inf), axis=0)
+    assert np.array_equal(mn[r2["count"] > 0], r2["min"][0][r2["count"] > 0])
+    rx = orc.bin_particles_nd([x, y, z], [a], (2, 1), (-1.0, 1.0, 0.0, 3.0), (5, 6), ALL)
+    ins_x = (x >= 0) & (x <= 1)
+    rxz = orc.bin_particles_nd([x[ins_x], y[ins_x], z[ins_x]], [a[ins_x]], (2, 1), (-1.0, 1.0, 0.0, 3.0), (5, 6), ALL)
+    assert np.array_equal(r3["count"].sum(axis=2), rxz["count"].T)
+    assert rx["inside"] == n
+    r1 = orc.bin_particles_nd([x, y, z], [a], (0, 1, 2), b3, (10, 6, 1), ALL)
+    assert r1["count"].shape == (1, 6, 10)
+    for key in ("count",):
+        assert np.array_equal(r1[key][0], r2[key])
+    for key in ("sum", "min", "max", "avg"):
+        assert same_bits(r1[key][0][0], r2[key][0]), key
+    rnd = orc.bin_particles_nd([x, y, z], [a], (1, 0), (0.0, 3.0, 0.0, 1.0), (7, 9), ALL)
+    r2b = orc.bin_particles([x, y, z], [a], (1, 0), (0.0, 3.0, 0.0, 1.0), 7, 9, ALL)
+    assert np.array_equal(rnd["count"], r2b["count"])
+    for key in ("sum", "min", "max", "avg"):
+        assert same_bits(rnd[key][0], r2b[key][0]), key
+
+
+def pin_nd_lattice(orc):
+    """One particle at every cell centre of a 3-D mesh with non-dyadic bounds,
+    valued by its cell's position in C order over [nz][ny][nx], and a line of
+    cell centres in 1-D."""
+    nx, ny, nz = 5, 3, 4
+    lo = (-1.0, 0.5, 10.0)
+    hi = (2.0, 4.0, 10.7)
+    iz, iy, ix = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    x = lo[0] + (ix.ravel() + 0.5) * (hi[0] - lo[0]) / nx
+    y = lo[1] + (iy.ravel() + 0.5) * (hi[1] - lo[1]) / ny
+    z = lo[2] + (iz.ravel() + 0.5) * (hi[2] - lo[2]) / nz
+    v = np.arange(nx * ny * nz, dtype=np.float64) * 1.5 - 7.0
+    perm = np.random.default_rng(2).permutation(v.size)
+    r = orc.bin_particles_nd([x[perm], y[perm], z[perm]], [v[perm]], (0, 1, 2),
+                             (lo[0], hi[0], lo[1], hi[1], lo[2], hi[2]), (nx, ny, nz), ALL)
+    assert np.array_equal(r["count"], np.ones((nz, ny, nx), np.int64))
+    for key in ("sum", "min", "max", "avg"):
+        assert np.array_equal(r[key][0], v.reshape(nz, ny, nx)), key
+    w = np.arange(7, dtype=np.float64)
+    r = orc.bin_particles_nd([w * 0.5 + 0.25], [w + 1], (0,), (0.0, 3.5), (7,), ALL)
+    assert np.array_equal(r["count"], np.ones(7, np.int64)) and np.array_equal(r["sum"][0], w + 1)
+
+
+ALL_PINS += [pin_nd_golden, pin_nd_bruteforce, pin_nd_libraries, pin_nd_reductions, pin_nd_lattice]

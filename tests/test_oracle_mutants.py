@@ -53,6 +53,17 @@ MUTANTS += [
 ]
 
 
+MUTANTS += [
+    ("nd_transposed_flat", "flat += ij * stride", "flat = flat * int(dims[j]) + ij"),
+    ("nd_no_stride", "stride *= int(dims[j])", "stride *= 1"),
+    ("nd_first_axis_inside", "inside &= inj", "inside = inside if j else inj"),
+    ("nd_axis0_bounds", "inj, ij = axis_index(coords[axes[j]], bounds[2 * j], bounds[2 * j + 1], dims[j])",
+     "inj, ij = axis_index(coords[axes[j]], bounds[0], bounds[1], dims[j])"),
+    ("nd_unreversed_shape", "attrs, tuple(int(v) for v in reversed(dims)))", "attrs, tuple(int(v) for v in dims))"),
+    ("nd_axis_column_order", "inj, ij = axis_index(coords[axes[j]]", "inj, ij = axis_index(coords[axes[d - 1 - j]]"),
+]
+
+
 def _mutant_module(old, new):
     src = open(SRC).read()
     assert src.count(old) == 1, f"mutation anchor not unique/found: {old!r}"
