@@ -161,6 +161,33 @@ int bin_validate(const bin_columns* coords, const bin_columns* attrs, int64_t n,
                  const int32_t axes[2], const double bounds[4], int32_t nx, int32_t ny,
                  uint32_t ops, const bin_output* out);
 
+/* ---- meshes of one, two or three axes ----------------------------------- */
+/* The mesh axes are any chosen subset of the particle variables (paper,
+ * Section 4.2); this entry point takes one, two or three of them.
+ *  ndim     1, 2 or 3.
+ *  axes     host array of ndim coordinate column indices (repeats allowed).
+ *  bounds   host array of 2*ndim doubles {lo0, hi0, lo1, hi1, ...}, finite,
+ *           lo < hi; or NULL for bounds from the data (as bin_particles).
+ *  dims     host array of ndim bin counts, each >= 1, product <= 2^31 - 1.
+ *           With f32 coordinates and ndim = 3, dims[1] * dims[2] <= 2^24.
+ * Every axis follows the readings above (closed upper edge, binary64 index);
+ * a particle is inside iff it is inside on every axis.  Axis 0 varies
+ * fastest: the flat bin is (i2 * dims[1] + i1) * dims[0] + i0 and every
+ * output grid is row-major [dims[2]][dims[1]][dims[0]], prod(dims) elements.
+ * Other arguments, outputs, errors and stream semantics as bin_particles.
+ * ndim = 2 is bin_particles.  With ndim = 3 the library first folds axes 1
+ * and 2 into one composite coordinate column in its scratch (one extra pass
+ * over those two columns), then bins the two-axis mesh dims[0] by
+ * dims[1] * dims[2], which gives the same bins exactly. */
+int bin_particles_nd(const bin_columns* coords, const bin_columns* attrs, int64_t n, int32_t ndim,
+                     const int32_t* axes, const double* bounds, const int32_t* dims, uint32_t ops,
+                     const bin_output* out, void* stream);
+
+/* Argument checks of bin_particles_nd, without touching the GPU. */
+int bin_validate_nd(const bin_columns* coords, const bin_columns* attrs, int64_t n, int32_t ndim,
+                    const int32_t* axes, const double* bounds, const int32_t* dims, uint32_t ops,
+                    const bin_output* out);
+
 /* ---- batched entry point ------------------------------------------------ */
 /* Run nreq independent requests (uneven n and grid sizes allowed) in one
  * persistent kernel launch on 'stream' (plus one initialisation and one

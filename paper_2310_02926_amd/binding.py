@@ -29,7 +29,7 @@ MAX_ATTRS = 16
 
 #: Every function declared in include/binning.h.
 EXPORTS = (
-    "bin_particles", "bin_validate", "bin_particles_async", "bin_particles_batched", "bin_particles_multi", "bin_graph_create", "bin_graph_launch",
+    "bin_particles", "bin_validate", "bin_particles_nd", "bin_validate_nd", "bin_particles_async", "bin_particles_batched", "bin_particles_multi", "bin_graph_create", "bin_graph_launch",
     "bin_graph_destroy", "bin_autotune", "bin_status_string", "bin_last_error_message",
     "bin_stream_status", "bin_release_workspace", "bin_version", "bin_timing_enable", "bin_timing_read",
     "bin_timing_report",
@@ -103,6 +103,10 @@ def lib() -> ctypes.CDLL:
                                   POINTER(c_double), c_int32, c_int32, c_uint32, POINTER(Output), c_void_p]),
         "bin_validate": (c_int, [POINTER(Columns), POINTER(Columns), c_int64, POINTER(c_int32),
                                  POINTER(c_double), c_int32, c_int32, c_uint32, POINTER(Output)]),
+        "bin_particles_nd": (c_int, [POINTER(Columns), POINTER(Columns), c_int64, c_int32, POINTER(c_int32),
+                                     POINTER(c_double), POINTER(c_int32), c_uint32, POINTER(Output), c_void_p]),
+        "bin_validate_nd": (c_int, [POINTER(Columns), POINTER(Columns), c_int64, c_int32, POINTER(c_int32),
+                                    POINTER(c_double), POINTER(c_int32), c_uint32, POINTER(Output)]),
         "bin_particles_async": (c_int, [POINTER(Columns), POINTER(Columns), c_int64, POINTER(c_int32),
                                         POINTER(c_double), c_int32, c_int32, c_uint32, POINTER(Output), c_void_p,
                                         c_void_p]),
@@ -227,6 +231,49 @@ def bin_particles(coords, attrs, n: int, axes, bounds, nx: int, ny: int, ops: in
     st = lib().bin_particles(ctypes.byref(c), ctypes.byref(a) if a is not None else None, n, ax, bd,
                              nx, ny, ops, ctypes.byref(o), _stream_handle(stream))
     check(st)
+
+
+def _nd_args(axes, bounds, dims):
+    d = len(axes)
+    ax = (c_int32 * d)(*axes)
+    dm = (c_int32 * len(dims))(*dims)
+    bd = (c_double * (2 * d))(*bounds) if bounds is not None else None
+    return d, ax, bd, dm
+
+
+def bin_particles_nd(coords, attrs, n: int, axes, bounds, dims, ops: int, out: Dict, stream=None,
+                     coord_dtype=None, attr_dtype=None) -> None:
+    """Enqueue one request on a mesh of len(axes) = 1, 2 or 3 axes;
+    ``bounds`` = (lo0, hi0, lo1, hi1, ...) or None; ``dims`` = bins per
+    axis.  Output grids hold prod(dims) elements, axis 0 fastest."""
+    c, ck = columns(coords, coord_dtype)
+    a, ak = columns(attrs, attr_dtype) if attrs is not None else (None, None)
+    o, ok = output(out.get("count"), out.get("sum"), out.get("min"), out.get("max"), out.get("avg"))
+    d, ax, bd, dm = _nd_args(axes, bounds, dims)
+    check(lib().bin_particles_nd(ctypes.byref(c), ctypes.byref(a) if a is not None else None, n, d, ax, bd, dm,
+                                 ops, ctypes.byref(o), _stream_handle(stream)))
+
+
+def bin_validate_nd(coords, attrs, n, axes, bounds, dims, ops, out, coord_dtype=None, attr_dtype=None,
+                    ndim=None) -> int:
+    """Host-only argument check of bin_particles_nd; returns the status.
+    ``ndim`` overrides len(axes) (to test the ndim check itself)."""
+    c, ck = columns(coords, coord_dtype)
+    a, ak = columns(attrs, attr_dtype) if attrs is not None else (None, None)
+    o, ok = output(out.get("count"), out.get("sum"), out.get("min"), out.get("max"), out.get("avg"))
+    d, ax, bd, dm = _nd_args(axes, bounds, dims)
+    return lib().bin_validate_nd(ctypes.byref(c), ctypes.byref(a) if a is not None else None, n,
+                                 d if ndim is None else ndim, ax, bd, dm, ops, ctypes.byref(o))
+
+
+def alloc_outputs_nd(attrs, dims, ops: int, device) -> Dict:
+    """Output grids shaped dims reversed ([d2][d1][d0]) for bin_particles_nd."""
+    nb = 1
+    for v in dims:
+        nb *= int(v)
+    out = alloc_outputs(attrs, nb, 1, ops, device)
+    shape = tuple(int(v) for v in reversed(dims))
+    return {k: (v.view(shape) if not isinstance(v, list) else [t.view(shape) for t in v]) for k, v in out.items()}
 
 
 def bin_particles_async(coords, attrs, n: int, axes, bounds, nx: int, ny: int, ops: int, out: Dict,

@@ -93,6 +93,70 @@ int run_auto_bounds(const bin_request& r0, hipStream_t s) {
   if (e != hipSuccess) return hip_fail(e, "launch bounds kernels");
   return enqueue(p, s, tm);
 }
+
+// Three axes: fold axes 1 and 2 into a composite column in scratch (one
+// pass), then bin (axis 0, composite) on a dims[0] x dims[1] * dims[2] mesh
+// whose second axis is [0, dims[1] * dims[2]].  Scratch: 256 bytes of
+// bounds keys (0-5: the three axes from the data, 8-11: the folded mesh),
+// the composite column, then the plan's own scratch.
+int run_fold3(const bin_columns* coords, const bin_columns* attrs, int64_t n, const int32_t* axes,
+              const double* bounds, const int32_t* dims, uint32_t ops, const bin_output* out, hipStream_t s) {
+  const bool f64 = coords->dtype == BIN_F64;
+  const size_t csz = f64 ? 8 : 4;
+  const int32_t nyz = dims[1] * dims[2];
+  const void* cols2[2] = {coords->cols[axes[0]], nullptr};
+  const bin_columns c2{cols2, 2, coords->dtype};
+  const int32_t ax2[2] = {0, 1};
+  const double b4[4] = {bounds ? bounds[0] : 0.0, bounds ? bounds[1] : 1.0, 0.0, (double)nyz};
+  bin_request r = make_request(&c2, attrs, n, ax2, b4, dims[0], nyz, ops, out);
+  DeviceInfo dev;
+  int st = device_info(&dev);
+  if (st) return st;
+  st = precheck_stream(s);
+  if (st) return st;
+  const PlanHints& hints = thread_hints();
+  Prepared p;
+  st = prepare(r, dev, hints, nullptr, &p);
+  if (st) return st;
+  const size_t comp_bytes = ((size_t)n * csz + 255) & ~size_t(255);
+  void* scratch = nullptr;
+  st = scratch_get(dev.device, s, 256 + comp_bytes + p.scratch_bytes, &scratch);
+  if (st) return st;
+  unsigned char* base = static_cast<unsigned char*>(scratch);
+  long long* keys = reinterpret_cast<long long*>(base);
+  cols2[1] = base + 256;  // r.coords.cols points at cols2
+  st = prepare(r, dev, hints, base + 256 + comp_bytes, &p);
+  if (st) return st;
+  bk::FoldArgs fa;
+  std::memset(&fa, 0, sizeof fa);
+  fa.y = coords->cols[axes[1]];
+  fa.z = coords->cols[axes[2]];
+  fa.out = base + 256;
+  fa.n = n;
+  fa.vec = (reinterpret_cast<uintptr_t>(fa.y) % 16 == 0 && reinterpret_cast<uintptr_t>(fa.z) % 16 == 0) ? 1 : 0;
+  if (bounds) {
+    fa.ay = bk::Axis{bounds[2], bounds[3], (double)dims[1] / (bounds[3] - bounds[2]), dims[1], 0};
+    fa.az = bk::Axis{bounds[4], bounds[5], (double)dims[2] / (bounds[5] - bounds[4]), dims[2], 0};
+  } else {
+    fa.ay = bk::Axis{0.0, 1.0, 0.0, dims[1], 0};
+    fa.az = bk::Axis{0.0, 1.0, 0.0, dims[2], 0};
+  }
+  bk::KTimer* tm = timing_timer();
+  if (!bounds) {
+    hipError_t e = bk::launch_bounds(coords->cols[axes[0]], coords->cols[axes[1]], f64, n, keys, dev.cus, s, tm);
+    if (e == hipSuccess)
+      e = bk::launch_bounds(coords->cols[axes[2]], coords->cols[axes[2]], f64, n, keys + 4, dev.cus, s, tm);
+    if (e != hipSuccess) return hip_fail(e, "launch bounds kernels");
+    fa.dyn_in = keys;
+    fa.dyn_out = keys + 8;
+    p.bin.dyn = keys + 8;
+    p.lds.dyn = keys + 8;
+    p.part.dyn = keys + 8;
+  }
+  const hipError_t e = bk::launch_fold(fa, f64, dev.cus, s, tm);
+  if (e != hipSuccess) return hip_fail(e, "launch fold kernel");
+  return enqueue(p, s, tm);
+}
 }  // namespace binimpl
 
 extern "C" {
@@ -171,6 +235,36 @@ int bin_particles_async(const bin_columns* coords, const bin_columns* attrs, int
     return bounds ? run_request(r, bs, thread_hints()) : run_auto_bounds(r, bs);
   };
   return stage_run(dev.device, ss, bs, bytes, copy, bin);
+}
+
+int bin_validate_nd(const bin_columns* coords, const bin_columns* attrs, int64_t n, int32_t ndim,
+                    const int32_t* axes, const double* bounds, const int32_t* dims, uint32_t ops,
+                    const bin_output* out) {
+  clear_error();
+  return validate_nd(coords, attrs, n, ndim, axes, bounds, dims, ops, out);
+}
+
+int bin_particles_nd(const bin_columns* coords, const bin_columns* attrs, int64_t n, int32_t ndim,
+                     const int32_t* axes, const double* bounds, const int32_t* dims, uint32_t ops,
+                     const bin_output* out, void* stream) {
+  clear_error();
+  int st = validate_nd(coords, attrs, n, ndim, axes, bounds, dims, ops, out);
+  if (st) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (ndim == 3) return run_fold3(coords, attrs, n, axes, bounds, dims, ops, out, s);
+  // One axis: the two-axis mesh dims[0] x 1 whose second axis is the first
+  // one again; its inside test repeats the first one's and its index is 0.
+  const int32_t a2[2] = {axes[0], ndim == 2 ? axes[1] : axes[0]};
+  double b4[4];
+  if (bounds) {
+    b4[0] = bounds[0];
+    b4[1] = bounds[1];
+    b4[2] = ndim == 2 ? bounds[2] : bounds[0];
+    b4[3] = ndim == 2 ? bounds[3] : bounds[1];
+  }
+  bin_request r = make_request(coords, attrs, n, a2, bounds ? b4 : nullptr, dims[0], ndim == 2 ? dims[1] : 1,
+                               ops, out);
+  return bounds ? run_request(r, s, thread_hints()) : run_auto_bounds(r, s);
 }
 
 int bin_set_plan_override(int32_t strategy, int32_t block, int32_t grid) {

@@ -139,6 +139,47 @@ int validate(const bin_columns* coords, const bin_columns* attrs, int64_t n, con
   return BIN_OK;
 }
 
+// Meshes of one to three axes: the checks of the two-axis request the call
+// maps to, then those of the axes that mapping does not show.
+int validate_nd(const bin_columns* coords, const bin_columns* attrs, int64_t n, int32_t ndim,
+                const int32_t* axes, const double* bounds, const int32_t* dims, uint32_t ops,
+                const bin_output* out) {
+  if (ndim < 1 || ndim > 3) return fail(BIN_ERR_INVALID_ARG, "ndim = %d outside [1, 3]", ndim);
+  if (!axes) return fail(BIN_ERR_INVALID_ARG, "axes is NULL");
+  if (!dims) return fail(BIN_ERR_INVALID_ARG, "dims is NULL");
+  int64_t nb = 1;
+  for (int d = 0; d < ndim; ++d) {
+    if (dims[d] < 1) return fail(BIN_ERR_INVALID_ARG, "dims[%d] = %d must be >= 1", d, dims[d]);
+    nb *= dims[d];
+    if (nb > 0x7FFFFFFFll) return fail(BIN_ERR_INVALID_ARG, "the product of dims exceeds 2^31 - 1");
+  }
+  const int32_t a2[2] = {axes[0], ndim > 1 ? axes[1] : axes[0]};
+  const int32_t nx = dims[0], ny = ndim == 1 ? 1 : (ndim == 2 ? dims[1] : dims[1] * dims[2]);
+  int st = validate(coords, attrs, n, a2, nullptr, nx, ny, ops, out, true);
+  if (st) return st;
+  if (ndim == 3) {
+    if (axes[2] < 0 || axes[2] >= coords->ncols)
+      return fail(BIN_ERR_INVALID_ARG, "axes[2] = %d outside [0, %d)", axes[2], coords->ncols);
+    const size_t csz = coords->dtype == BIN_F64 ? 8 : 4;
+    if (n > 0) {
+      const void* p = coords->cols[axes[2]];
+      if (!p) return fail(BIN_ERR_INVALID_ARG, "coordinate column %d is NULL", axes[2]);
+      if (!aligned(p, csz)) return fail(BIN_ERR_INVALID_ARG, "coordinate column %d is misaligned", axes[2]);
+    }
+    if (coords->dtype == BIN_F32 && (int64_t)dims[1] * dims[2] > (1ll << 24))
+      return fail(BIN_ERR_INVALID_ARG, "f32 coordinates need dims[1] * dims[2] <= 2^24 (got %lld)",
+                  (long long)dims[1] * dims[2]);
+  }
+  if (bounds) {
+    static const char* const names[3] = {"axis 0", "axis 1", "axis 2"};
+    for (int d = 0; d < ndim; ++d) {
+      st = check_axis(names[d], bounds[2 * d], bounds[2 * d + 1], dims[d]);
+      if (st) return st;
+    }
+  }
+  return BIN_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Device facts, queried once per device.
 // ---------------------------------------------------------------------------

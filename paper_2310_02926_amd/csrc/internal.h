@@ -38,6 +38,9 @@ const char* last_error();
 int validate(const bin_columns* coords, const bin_columns* attrs, int64_t n, const int32_t axes[2],
              const double bounds[4], int32_t nx, int32_t ny, uint32_t ops, const bin_output* out,
              bool allow_null_bounds);
+int validate_nd(const bin_columns* coords, const bin_columns* attrs, int64_t n, int32_t ndim,
+                const int32_t* axes, const double* bounds, const int32_t* dims, uint32_t ops,
+                const bin_output* out);
 
 struct DeviceInfo {
   int device = 0;

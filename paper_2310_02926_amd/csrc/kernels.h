@@ -176,6 +176,20 @@ struct PartCfg {
   int bin_block;
 };
 
+// Three-axis meshes: axes 1 and 2 folded into one composite coordinate
+// column (out, same type as the coordinates, n entries).
+struct FoldArgs {
+  const void* y;
+  const void* z;
+  void* out;
+  Axis ay, az;
+  const long long* dyn_in;  // six keys (axes 0, 1, 2) or null for given bounds
+  long long* dyn_out;       // four keys for the folded two-axis mesh, or null
+  int64_t n;
+  int32_t vec;              // y, z and out 16-byte aligned
+  int32_t pad;
+};
+
 // Optional per-kernel timing: begin() records an event before a launch,
 // end(name) one after it; both on the launch stream.
 struct KTimer {
@@ -207,6 +221,7 @@ hipError_t set_dynamic_lds_limit(const void* fn, size_t total);
 hipError_t launch_bounds(const void* x, const void* y, bool coord_f64, int64_t n, long long* keys, int cus,
                          hipStream_t s, KTimer* tm);
 hipError_t set_partition_lds_limit(size_t bytes);
+hipError_t launch_fold(const FoldArgs& a, bool coord_f64, int cus, hipStream_t s, KTimer* tm);
 
 }  // namespace bk
 

@@ -151,3 +151,51 @@ def test_async_rejects_before_any_hip_call():
     with pytest.raises(B.BinError) as ei:
         B.bin_particles_async(**good(axes=(0, 5)), src_stream=0, bin_stream=0)
     assert ei.value.status == B.BIN_ERR_INVALID_ARG
+
+
+def good_nd(**over):
+    a = good()
+    args = dict(coords=a["coords"], attrs=a["attrs"], n=1000, axes=(0, 1, 2),
+                bounds=(0.0, 1.0, 0.0, 1.0, -1.0, 1.0), dims=(16, 8, 4), ops=B.OPS_ALL, out=a["out"],
+                coord_dtype=B.BIN_F32, attr_dtype=B.BIN_F32)
+    args.update(over)
+    return args
+
+
+def test_nd_valid_requests_pass():
+    assert B.bin_validate_nd(**good_nd()) == B.BIN_OK
+    assert B.bin_validate_nd(**good_nd(axes=(2,), bounds=(0.0, 1.0), dims=(100,))) == B.BIN_OK
+    assert B.bin_validate_nd(**good_nd(axes=(2, 0), bounds=(0.0, 1.0, 5.0, 6.0), dims=(3, 7))) == B.BIN_OK
+    assert B.bin_validate_nd(**good_nd(axes=(1, 1, 1))) == B.BIN_OK
+    assert B.bin_validate_nd(**good_nd(bounds=None)) == B.BIN_OK
+    # f32 coordinates: the folded axes 1 and 2 must stay exact in binary32
+    assert B.bin_validate_nd(**good_nd(dims=(1, 4096, 4096))) == B.BIN_OK
+    assert B.bin_validate_nd(**good_nd(dims=(1, 4097, 4096), coord_dtype=B.BIN_F64)) == B.BIN_OK
+
+
+@pytest.mark.parametrize("over,frag", [
+    (dict(ndim=0), "ndim"),
+    (dict(ndim=4, axes=(0, 1, 2, 0), dims=(2, 2, 2, 2), bounds=(0.0, 1.0) * 4), "ndim"),
+    (dict(axes=(0, 1, 3)), "axes[2]"),
+    (dict(axes=(0, 3, 1)), "axes[1]"),
+    (dict(dims=(16, 0, 4)), "dims[1]"),
+    (dict(dims=(65536, 65536, 1)), "product"),
+    (dict(dims=(1, 4097, 4096)), "2^24"),
+    (dict(bounds=(0.0, 1.0, 0.0, 1.0, 1.0, 1.0)), "axis 2"),
+    (dict(bounds=(0.0, 1.0, float("nan"), 1.0, 0.0, 1.0)), "axis 1"),
+    (dict(axes=(0,), bounds=(2.0, 1.0), dims=(4,)), "axis 0"),
+    (dict(coords=[F, F + 0x100, 0]), "column 2 is NULL"),
+    (dict(coords=[F, F + 0x100, F + 0x202]), "column 2 is misaligned"),
+    (dict(attrs=[], ops=B.OPS_ALL, out={"count": F}), "no attribute"),
+])
+def test_nd_invalid_arguments_rejected(over, frag):
+    assert B.bin_validate_nd(**good_nd(**over)) == B.BIN_ERR_INVALID_ARG
+    assert frag in B.last_error(), B.last_error()
+
+
+def test_nd_rejects_before_any_hip_call():
+    with pytest.raises(B.BinError) as ei:
+        B.bin_particles_nd(**good_nd(dims=(16, 8, 0)), stream=0)
+    assert ei.value.status == B.BIN_ERR_INVALID_ARG
+    L = B.lib()
+    assert L.bin_particles_nd(None, None, 0, 3, None, None, None, 1, None, None) == B.BIN_ERR_INVALID_ARG
