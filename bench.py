@@ -73,11 +73,18 @@ def make_workload(name: str, scale: int):
         n = 65536 >> scale
         return synth.uniform_f64(n, seed=0), {"workload": "uniform_64K_64sq_f64", "n": n, "grid": "64x64",
                                                "attrs": "1 x f64", "coords": "2 x f64", "ops": "count,sum,min,max,avg"}
+    if name == "nd3":
+        n = (1 << 26) >> scale
+        return synth.halos3d_f32(n=n, seed=0, side=128), {
+            "workload": "halos3d_64M_128cube", "n": n, "grid": "128x128x128 (axes x, y, z)",
+            "attrs": "1 x f32 (mass ~ lognormal(0,1))", "coords": "3 x f32",
+            "clustered": "80% of particles in 64 Gaussian halos", "ops": "count,sum,min,max,avg"}
     raise SystemExit(f"unknown workload {name}")
 
 
 def algorithmic_bytes(ws):
-    ins = sum(c.itemsize * c.size for c in ws.coords[:2]) + sum(a.itemsize * a.size for a in ws.attrs)
+    naxes = len(ws.meta["nd"][0]) if "nd" in ws.meta else 2
+    ins = sum(c.itemsize * c.size for c in ws.coords[:naxes]) + sum(a.itemsize * a.size for a in ws.attrs)
     nb = ws.nx * ws.ny
     a64 = bool(ws.attrs) and ws.attrs[0].dtype == np.float64
     per_attr = (8 + 8 + 8 + 8) if a64 else (8 + 4 + 4 + 8)  # sum, min, max, avg (default precision)
@@ -94,7 +101,12 @@ def cpu_baseline(ws, target_s: float = 12.0):
     m = min(n, 1 << 20)
     while True:
         t0 = time.perf_counter()
-        orc.bin_particles([c[:m] for c in ws.coords], [a[:m] for a in ws.attrs], ws.axes, ws.bounds, ws.nx, ws.ny)
+        if "nd" in ws.meta:
+            axes, bounds, dims = ws.meta["nd"]
+            orc.bin_particles_nd([c[:m] for c in ws.coords], [a[:m] for a in ws.attrs], axes, bounds, dims)
+        else:
+            orc.bin_particles([c[:m] for c in ws.coords], [a[:m] for a in ws.attrs], ws.axes, ws.bounds, ws.nx,
+                              ws.ny)
         dt = time.perf_counter() - t0
         if dt >= 0.5 * target_s or m >= n:
             break
@@ -109,7 +121,11 @@ def kernel_algorithmic_bytes(name: str, ws) -> int:
     kernel: the particle columns it must read, or the result grid it must
     write.  Intermediate records, counts and partials are not counted."""
     ins, outs = algorithmic_bytes(ws)
+    if name == "fold_axes_kernel":  # axes 1 and 2 in, the composite column out
+        return 3 * ws.coords[1].itemsize * ws.n
     if name in ("part_scatter_kernel", "bin_global_kernel", "bin_lds_kernel"):
+        if "nd" in ws.meta:  # axis 0, the composite column and the attributes
+            return ins - ws.coords[2].itemsize * ws.n
         return ins
     if name in ("part_bin_kernel", "part_merge_kernel", "lds_merge_kernel", "bin_finalize_kernel"):
         return outs
@@ -451,7 +467,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="hotspot", choices=["hotspot", "gmm", "uniform", "batched", "served", "insitu"])
+    ap.add_argument("--workload", default="hotspot", choices=["hotspot", "gmm", "uniform", "nd3", "batched", "served", "insitu"])
     ap.add_argument("--prec", default="default", choices=["default", "comp", "plain", "f64"])
     ap.add_argument("--scale", type=int, default=0, help="shrink n by 2^scale (quick runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -479,8 +495,18 @@ def main():
     attrs = [torch.from_numpy(a).to(dev) for a in ws.attrs]
     flag = {"default": 0, "comp": B.PREC_COMP, "plain": B.PREC_PLAIN, "f64": B.PREC_F64}[args.prec]
     ops = B.OPS_ALL | flag
-    out = B.alloc_outputs(attrs, ws.nx, ws.ny, ops, dev)
     stream = torch.cuda.Stream()
+    if "nd" in ws.meta:
+        nd_axes, nd_bounds, nd_dims = ws.meta["nd"]
+        out = B.alloc_outputs_nd(attrs, nd_dims, ops, dev)
+
+        def call():
+            B.bin_particles_nd(coords, attrs, ws.n, nd_axes, nd_bounds, nd_dims, ops, out, stream=stream)
+    else:
+        out = B.alloc_outputs(attrs, ws.nx, ws.ny, ops, dev)
+
+        def call():
+            B.bin_particles(coords, attrs, ws.n, ws.axes, ws.bounds, ws.nx, ws.ny, ops, out, stream=stream)
     torch.cuda.synchronize()
 
     if args.copy_calibration:
@@ -491,11 +517,14 @@ def main():
         log("copy calibration: 1 GiB device-to-device copy done")
         del src, dst
 
-    req, keep = B.request(coords, attrs, ws.n, ws.axes, ws.bounds, ws.nx, ws.ny, ops, out)
+    # (for three axes: the plan of the folded two-axis mesh nx by ny * nz)
+    req, keep = B.request(coords, attrs, ws.n, ws.axes, ws.bounds, ws.nx, ws.ny, ops,
+                          {k: (v.view(-1) if not isinstance(v, list) else [t.view(-1) for t in v])
+                           for k, v in out.items()})
     plan = B.bin_describe_plan(req)
     log(f"plan: {plan}")
     for _ in range(args.warmup):
-        B.bin_particles(coords, attrs, ws.n, ws.axes, ws.bounds, ws.nx, ws.ny, ops, out, stream=stream)
+        call()
     stream.synchronize()
     log(f"warmup {args.warmup} done")
 
@@ -505,7 +534,7 @@ def main():
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     for _ in range(args.steps):
-        B.bin_particles(coords, attrs, ws.n, ws.axes, ws.bounds, ws.nx, ws.ny, ops, out, stream=stream)
+        call()
     ev1.record(stream)
     stream.synchronize()
     torch.cuda.synchronize()
@@ -514,7 +543,7 @@ def main():
     # Timed region 2: the same calls with the library's per-kernel event pairs.
     B.bin_timing_enable(True)
     for _ in range(args.steps):
-        B.bin_particles(coords, attrs, ws.n, ws.axes, ws.bounds, ws.nx, ws.ny, ops, out, stream=stream)
+        call()
     stream.synchronize()
     B.bin_timing_enable(False)
     rep = B.bin_timing_report()

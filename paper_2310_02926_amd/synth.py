@@ -16,6 +16,9 @@ is not available, so the generators below stand in for it:
 * ``batch_instances`` - many independent requests of uneven size.
 * ``insitu_table``  - ten N-body-like variables binned over nine coordinate
   systems (the multi-grid in situ load of Section 4.3).
+* ``halos3d_f32``   - clustered 3-D positions (64 Gaussian halos plus a
+  uniform background reaching past the unit cube), lognormal mass, for
+  meshes of three axes.
 
 Every generator uses NumPy's PCG64 (``numpy.random.default_rng``) and returns
 particles in shuffled order (no spatial locality), columns as separate
@@ -171,6 +174,36 @@ def hotspot_f32(n: int = 1 << 27, seed: int = 0, side: int = 2048, hot_frac: flo
     return Workload([x, y], [mass], nx=side, ny=side,
                     name=f"hotspot_f32_n{n}_{side}x{side}",
                     meta={"hot_bins": np.sort(hot), "n_hot": n_hot})
+
+
+def halos3d_f32(n: int = 1 << 26, seed: int = 0, side: int = 128, halo_frac: float = 0.8,
+                nhalo: int = 64) -> Workload:
+    """Clustered 3-D f32 positions for a ``side``^3 mesh over [0,1]^3.
+
+    round(halo_frac * n) particles belong to one of ``nhalo`` equal-weight
+    isotropic Gaussian halos (centres U(0.1,0.9)^3, sigma U(0.01,0.08));
+    the rest are uniform on [-0.05,1.05)^3, so some fall outside the mesh
+    (as do halo particles in the tails).  mass ~ lognormal(0,1).  Columns:
+    x, y, z; axes (0, 1, 2) in ``meta["nd"]`` with bounds and dims."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(0.1, 0.9, size=(nhalo, 3))
+    sigmas = rng.uniform(0.01, 0.08, size=nhalo)
+    n_halo = int(round(halo_frac * n))
+    comp = rng.integers(0, nhalo, n_halo)
+    cols = []
+    for d in range(3):
+        c = np.empty(n, np.float32)
+        c[:n_halo] = (centres[comp, d] + sigmas[comp] * rng.standard_normal(n_halo, dtype=np.float32))
+        c[n_halo:] = rng.uniform(-0.05, 1.05, n - n_halo).astype(np.float32)
+        cols.append(c)
+    del comp
+    mass = rng.lognormal(0.0, 1.0, n).astype(np.float32)
+    perm = rng.permutation(n)
+    cols = [c[perm] for c in cols]
+    mass = mass[perm]
+    return Workload(cols, [mass], axes=(0, 1), bounds=(0.0, 1.0, 0.0, 1.0), nx=side, ny=side * side,
+                    name=f"halos3d_f32_n{n}_{side}cube",
+                    meta={"nd": ((0, 1, 2), (0.0, 1.0, 0.0, 1.0, 0.0, 1.0), (side, side, side))})
 
 
 def random_ops(rng: np.random.Generator) -> int:

@@ -56,3 +56,17 @@ def test_poisson_arrivals():
     t = synth.poisson_arrivals(1000.0, 20000, seed=0)
     assert np.all(np.diff(t) > 0)
     assert abs(t[-1] / 20000 - 1e-3) < 5e-5
+
+
+def test_halos3d_shape_and_determinism():
+    a = synth.halos3d_f32(100_000, seed=3, side=16)
+    b = synth.halos3d_f32(100_000, seed=3, side=16)
+    assert all(np.array_equal(x, y) for x, y in zip(a.coords, b.coords))
+    assert len(a.coords) == 3 and all(c.dtype == np.float32 and c.size == 100_000 for c in a.coords)
+    axes, bounds, dims = a.meta["nd"]
+    assert axes == (0, 1, 2) and dims == (16, 16, 16)
+    inside = np.ones(100_000, bool)
+    for c in a.coords:
+        inside &= (c >= 0) & (c <= 1)
+    # the background reaches past the cube, so some particles are outside
+    assert 0.005 < 1 - inside.mean() < 0.2
