@@ -131,11 +131,14 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
     // one: 8 particles per thread at 1024 threads.
     if (nt >= 1024) ppt = std::min(ppt, 8);
     const size_t S = (size_t)nt * ppt;
+    // Per request: tile counters, record stage and values, then its staged
+    // rows of the run table; the launch takes the largest.
     size_t scatter_lds = 16;
     for (int r = 0; r < R; ++r) {
-      const Prepared& p = bp->preps[g.idx[r]];
-      const size_t sv = al16(16 * (size_t)p.part.ntiles + 4 * S);
-      scatter_lds = std::max(scatter_lds, sv + (p.part.k ? S * asz : 0));
+      bk::PartArgs a = bp->preps[g.idx[r]].part;
+      set_part_blocks(a, nt, ppt);
+      const size_t sv = al16(16 * (size_t)a.ntiles + 4 * S);
+      scatter_lds = std::max(scatter_lds, set_off_stage(a, sv + (a.k ? S * asz : 0), dev.lds_per_block - 256));
     }
     g.cfg.ppt = ppt;
     g.cfg.scatter_threads = nt;
@@ -151,8 +154,10 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
       bk::PartArgs a = bp->preps[g.idx[r]].part;
       set_part_blocks(a, nt, ppt);
       const size_t nrec = (size_t)std::max<int64_t>(a.n, 1);
+      a.stage_val_off = (int32_t)al16(16 * (size_t)a.ntiles + 4 * S);
+      set_off_stage(a, a.stage_val_off + (a.k ? S * asz : 0), dev.lds_per_block - 256);
       a.counts = reinterpret_cast<uint32_t*>(take(4 * (size_t)a.ntiles * a.nwg));
-      a.blk_off = reinterpret_cast<uint32_t*>(take(4 * (size_t)a.nwg * a.nbpw * (size_t)(a.ntiles + 1)));
+      a.blk_off = reinterpret_cast<uint16_t*>(take(2 * (size_t)a.nwg * a.nbpw * (size_t)(a.ntiles + 1)));
       a.ilist = reinterpret_cast<uint32_t*>(take(4 * (size_t)a.ntiles * a.nwg));
       a.items = reinterpret_cast<uint32_t*>(take(12 * (size_t)a.max_items));
       a.n_items = n_items ? n_items + r : nullptr;
@@ -160,7 +165,6 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
       a.split_list = reinterpret_cast<uint32_t*>(take(4 * ((size_t)a.ntiles + 1)));
       a.rec_bin = reinterpret_cast<uint16_t*>(take(2 * nrec));
       for (int j = 0; j < a.k; ++j) a.rec_val[j] = take(asz * nrec);
-      a.stage_val_off = (int32_t)al16(16 * (size_t)a.ntiles + 4 * S);
       a.partial = a.max_slots > 0 ? take((size_t)a.lay.slot_bytes * a.max_slots) : nullptr;
       a.merge_blocks = std::min(a.merge_blocks, 16);  // many requests share the launch
       g.args[r] = a;

@@ -98,6 +98,10 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints,
 // Sub-chunk sizes and the blk_off rows per slice of a partition request
 // whose scatter runs with these threads and particles per thread.
 void set_part_blocks(bk::PartArgs& a, int scatter_threads, int ppt);
+// Place the scatter's LDS stage of run-table rows at stage_base (rounded up)
+// with as many rows (a power of two, at most 16 and no more than a slice's
+// sub-chunks need) as fit lds_limit; returns the scatter's LDS bytes.
+size_t set_off_stage(bk::PartArgs& a, size_t stage_base, size_t lds_limit);
 // Workgroups of the split-tile merge launch (a.max_slots and a.lay set).
 int32_t merge_blocks(const bk::PartArgs& a, int cus);
 // Enqueue the kernels of a prepared request.

@@ -140,10 +140,15 @@ struct PartArgs {
   int32_t stage_val_off;  // byte offset of staged values in the scatter LDS
   int32_t sub;         // particles per whole sub-chunk (scatter threads x particles per thread)
   int32_t sub_tail;    // particles per remainder sub-chunk (scatter threads x 4)
-  int32_t nbpw;        // rows of blk_off reserved per slice (upper bound on its sub-chunks)
+  int32_t nbpw;        // rows of the run table reserved per slice (upper bound on its sub-chunks)
   int32_t vec;         // every column 16-byte aligned: whole sub-chunks use wide loads
+  int32_t nfull_a, nblocks_a;  // whole / all sub-chunks of every slice but the last
+  int32_t nfull_z, nblocks_z;  // the same for the last slice
+  int32_t off_shift;   // the scatter stages 2^off_shift rows of the run table in LDS
+  int32_t off_stage;   // byte offset of that stage in the scatter LDS
   uint32_t* counts;    // [ntiles][nwg] records of each tile in each slice
-  uint32_t* blk_off;   // [nwg * nbpw][ntiles + 1] start of each tile's run within its sub-chunk
+  uint16_t* blk_off;   // [ntiles + 1][nwg * nbpw] start of each tile's run within its sub-chunk
+                       // (row w * nbpw + j = sub-chunk j of slice w; entry ntiles = records)
   uint16_t* rec_bin;   // [n] records: a sub-chunk starting at particle i writes its
   void* rec_val[kMaxAttrs];  //   records, grouped by tile, to [i, i + inside)
   uint32_t* ilist;     // [ntiles][nwg] first slice of each of a tile's items

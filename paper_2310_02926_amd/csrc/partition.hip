@@ -50,14 +50,15 @@ struct SliceShape {
   int32_t nfull, nblocks;
 };
 
+// Every slice but the last has the same length, so the two shapes come
+// from the host and no lane divides.
 __device__ __forceinline__ SliceShape slice_shape(const PartArgs& a, int w) {
   SliceShape s;
   s.lo = (int64_t)w * a.chunk;
   s.hi = s.lo + a.chunk < a.n ? s.lo + a.chunk : a.n;
-  const int64_t len = s.hi > s.lo ? s.hi - s.lo : 0;
-  s.nfull = a.vec ? (int32_t)(len / a.sub) : 0;
-  const int64_t rem = len - (int64_t)s.nfull * a.sub;
-  s.nblocks = s.nfull + (int32_t)((rem + a.sub_tail - 1) / a.sub_tail);
+  const bool last = w == a.nwg - 1;
+  s.nfull = last ? a.nfull_z : a.nfull_a;
+  s.nblocks = last ? a.nblocks_z : a.nblocks_a;
   return s;
 }
 
@@ -117,7 +118,8 @@ struct ScatterShared {
 template <typename CT, typename AT, int PPT, int NT, bool FULL>
 __device__ __forceinline__ void scatter_sub(const PartArgs& a, unsigned char* smem, ScatterShared& sh,
                                             const Axis& ax, const Axis& ay, int64_t base, int64_t hi,
-                                            int64_t full_end, int64_t row, int parity, CT* px, CT* py) {
+                                            int64_t full_end, int64_t row0, int j, bool flush, int parity,
+                                            CT* px, CT* py) {
   constexpr int S = NT * PPT;
   constexpr int Q = PPT / 4;
   const int T = a.ntiles;
@@ -208,8 +210,13 @@ __device__ __forceinline__ void scatter_sub(const PartArgs& a, unsigned char* sm
   }
   __syncthreads();
   const uint32_t nsub = sh.nsub;
-  uint32_t* orow = a.blk_off + row * (T + 1);
-  for (int t = threadIdx.x; t <= T; t += NT) orow[t] = t < T ? off[t] : nsub;
+  // The run table is kept per tile (column t lists the tile's run starts in
+  // consecutive sub-chunks), so that part_bin reads it contiguously.  Rows
+  // are staged in LDS as [tile][F] and written F at a time.
+  const int F = 1 << a.off_shift;
+  uint16_t* ost = reinterpret_cast<uint16_t*>(smem + a.off_stage);
+  for (int t = threadIdx.x; t <= T; t += NT)
+    ost[(t << a.off_shift) + (j & (F - 1))] = (uint16_t)(t < T ? off[t] : nsub);
 #pragma unroll
   for (int u = 0; u < PPT; ++u) {
     if (tb[u] == 0xFFFFFFFFu) continue;
@@ -236,6 +243,16 @@ __device__ __forceinline__ void scatter_sub(const PartArgs& a, unsigned char* sm
     }
   }
   __syncthreads();
+  if (flush) {  // rows [j0, j] of the slice: column t gets f consecutive entries
+    const int j0 = j & ~(F - 1);
+    const int f = j - j0 + 1;
+    const int64_t nrows = (int64_t)a.nwg * a.nbpw;
+    const int64_t r0 = row0 + j0;
+    for (int i = threadIdx.x; i < ((T + 1) << a.off_shift); i += NT) {
+      const int t = i >> a.off_shift, jj = i & (F - 1);
+      if (jj < f) a.blk_off[(int64_t)t * nrows + r0 + jj] = ost[i];
+    }
+  }
   // One contiguous stream of records over [base, base + nsub).
   uint16_t* rb = a.rec_bin + base;
   for (uint32_t p = threadIdx.x; p < nsub; p += NT) rb[p] = (uint16_t)(stg_tb[p] & 0xFFFFu);
@@ -301,8 +318,11 @@ __device__ __forceinline__ void part_scatter_body(const PartArgs& a, int wg) {
   __syncthreads();
   int parity = 0;
   int j = 0;
+  const int F = 1 << a.off_shift;
+  auto flush_at = [&](int jj) { return ((jj + 1) & (F - 1)) == 0 || jj + 1 == shp.nblocks; };
   for (int64_t base = lo; base < full_end; base += S, parity ^= 1, ++j)
-    scatter_sub<CT, AT, PPT, NT, true>(a, smem, sh, ax, ay, base, hi, full_end, row0 + j, parity, px, py);
+    scatter_sub<CT, AT, PPT, NT, true>(a, smem, sh, ax, ay, base, hi, full_end, row0, j, flush_at(j), parity, px,
+                                       py);
   // The remainder in sub-chunks of 4 particles per thread (fewer registers;
   // the staging area holds S >= 4 * NT entries).
   constexpr int S4 = 4 * NT;
@@ -314,7 +334,8 @@ __device__ __forceinline__ void part_scatter_body(const PartArgs& a, int wg) {
       tx[e] = i + e < hi ? ld<CT>(a.x, i + e) : CT(0);
       ty[e] = i + e < hi ? ld<CT>(a.y, i + e) : CT(0);
     }
-    scatter_sub<CT, AT, 4, NT, false>(a, smem, sh, ax, ay, base, hi, full_end, row0 + j, parity, tx, ty);
+    scatter_sub<CT, AT, 4, NT, false>(a, smem, sh, ax, ay, base, hi, full_end, row0, j, flush_at(j), parity, tx,
+                                      ty);
   }
   __syncthreads();
   for (int t = threadIdx.x; t < T; t += NT) a.counts[(int64_t)t * a.nwg + wg] = tot[t];
@@ -494,21 +515,24 @@ __device__ __forceinline__ void part_bin_body(const PartArgs& a, int item) {
   const int lane = threadIdx.x & 63;
   const uint32_t wid = threadIdx.x >> 6;
   const uint32_t nwaves = blockDim.x >> 6;
-  const int64_t T1 = a.ntiles + 1;
   const uint32_t nblk = (w1 - w0) * (uint32_t)a.nbpw;
+  // Column t of the run table from the item's first row: consecutive lanes
+  // read consecutive entries.
+  const int64_t nrows = (int64_t)a.nwg * a.nbpw;
+  const uint16_t* col = a.blk_off + (int64_t)t * nrows + (int64_t)w0 * a.nbpw;
   // The lane's run in sub-chunk c of the item (len 0 past the end or for a
   // sub-chunk a short slice does not have).
   auto run_of = [&](uint32_t c, uint32_t& len, uint32_t& rs) {
     len = 0;
     rs = 0;
     if (c < nblk) {
-      const int w = (int)(w0 + c / (uint32_t)a.nbpw);
-      const int j = (int)(c % (uint32_t)a.nbpw);
+      const uint32_t dw = c / (uint32_t)a.nbpw;
+      const int w = (int)(w0 + dw);
+      const int j = (int)(c - dw * (uint32_t)a.nbpw);
       const SliceShape shp = slice_shape(a, w);
       if (j < shp.nblocks) {
-        const uint32_t* row = a.blk_off + ((int64_t)w * a.nbpw + j) * T1;
-        const uint32_t s0 = row[t];
-        len = row[t + 1] - s0;
+        const uint32_t s0 = col[c];
+        len = (uint32_t)col[c + nrows] - s0;
         rs = (uint32_t)(block_base(shp, a, j) + s0);
       }
     }

@@ -63,7 +63,26 @@ void set_part_blocks(bk::PartArgs& a, int scatter_threads, int ppt) {
   a.sub = scatter_threads * ppt;
   a.sub_tail = 4 * scatter_threads;
   // every slice but the last has the first one's length
-  a.nbpw = (int32_t)std::max<int64_t>({slice_blocks(a, 0), slice_blocks(a, a.nwg - 1), 1});
+  auto shape = [&](int64_t w, int32_t& nfull, int32_t& nblocks) {
+    const int64_t lo = w * a.chunk;
+    const int64_t len = std::max<int64_t>(std::min<int64_t>(lo + a.chunk, a.n) - lo, 0);
+    nfull = (int32_t)(a.vec ? len / a.sub : 0);
+    nblocks = (int32_t)slice_blocks(a, w);
+  };
+  shape(0, a.nfull_a, a.nblocks_a);
+  shape(a.nwg - 1, a.nfull_z, a.nblocks_z);
+  a.nbpw = std::max({a.nblocks_a, a.nblocks_z, 1});
+}
+
+size_t set_off_stage(bk::PartArgs& a, size_t stage_base, size_t lds_limit) {
+  a.off_stage = (int32_t)align16(stage_base);
+  const size_t cols = (size_t)a.ntiles + 1;
+  int shift = 0;
+  while (shift < 4 && (1 << shift) < a.nbpw &&
+         a.off_stage + align16(cols * 2 << (shift + 1)) <= lds_limit)
+    ++shift;
+  a.off_shift = shift;
+  return a.off_stage + align16(cols * 2 << shift);
 }
 
 namespace {
@@ -280,8 +299,9 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints_
       for (int tp = tp0; tp >= 4; tp = tp == 12 ? 8 : tp / 2) {
         const size_t S = (size_t)tnt * tp;
         const int32_t svo = (int32_t)align16(16 * (size_t)T + 4 * S);
+        // values, then at least one staged row of the run table
         const size_t need = svo + (nk ? S * asz : 0);
-        if (need + kScatterStatic <= lds_budget) {
+        if (align16(need) + align16(2 * ((size_t)T + 1)) + kScatterStatic <= lds_budget) {
           nt = tnt;
           ppt = tp;
           a.stage_val_off = svo;
@@ -294,14 +314,14 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints_
     if (!ppt) return fail(BIN_ERR_UNSUPPORTED, "partition scatter stage does not fit LDS");
     c.ppt = ppt;
     c.scatter_threads = nt;
-    c.scatter_lds = std::max<size_t>(sc, 16);
     c.bin_lds = tile_lds;
     // Half-size workgroups when two tiles fit a CU's LDS: two items per CU.
     c.bin_block = 2 * tile_lds <= dev.lds_per_cu ? 512 : 1024;
     set_part_blocks(a, nt, ppt);
+    c.scatter_lds = set_off_stage(a, sc, lds_budget - kScatterStatic);
     // scratch
     a.counts = static_cast<uint32_t*>(cv.take(4 * (size_t)ntiles * a.nwg));
-    a.blk_off = static_cast<uint32_t*>(cv.take(4 * (size_t)a.nwg * a.nbpw * (size_t)(ntiles + 1)));
+    a.blk_off = static_cast<uint16_t*>(cv.take(2 * (size_t)a.nwg * a.nbpw * (size_t)(ntiles + 1)));
     a.ilist = static_cast<uint32_t*>(cv.take(4 * (size_t)ntiles * a.nwg));
     a.items = static_cast<uint32_t*>(cv.take(12 * (size_t)a.max_items));
     a.n_items = static_cast<uint32_t*>(cv.take(4));
@@ -421,11 +441,11 @@ std::string describe(const Prepared& p) {
       break;
     case bk::STRAT_PART:
       snprintf(buf, sizeof buf,
-               "partition tiles=%d tile_bins=%d wg=%d chunk=%lld threads=%d ppt=%d sub=%d blocks=%d split=%u "
+               "partition tiles=%d tile_bins=%d wg=%d chunk=%lld threads=%d ppt=%d sub=%d blocks=%d staged_rows=%d split=%u "
                "max_items=%d "
                "scatter_lds=%zu bin_lds=%zu vec=%d prec=%s",
                p.part.ntiles, 1 << p.part.lay.tile_shift, p.part.nwg, (long long)p.part.chunk, p.pcfg.scatter_threads,
-               p.pcfg.ppt, p.part.sub, p.part.nbpw,
+               p.pcfg.ppt, p.part.sub, p.part.nbpw, 1 << p.part.off_shift,
                p.part.split_len, p.part.max_items, p.pcfg.scatter_lds, p.pcfg.bin_lds, p.part.vec, prec);
       break;
     default:
