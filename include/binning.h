@@ -299,12 +299,17 @@ int bin_set_plan_override(int32_t strategy, int32_t block, int32_t grid);
  *  BIN_TUNE_SCATTER_THREADS  threads per scatter workgroup (256, 512 or 1024)
  *  BIN_TUNE_TILE_SHIFT       log2 of the largest tile (6..15)
  *  BIN_TUNE_SPLIT_LEN        max records per binning work item (>= 1024)
+ *  BIN_TUNE_QUADS            1 = gather record by record, 2 = pad each tile's run
+ *                            to whole quads of 4 records and gather a quad per lane
+ *                            (default: quads for at most one f32 attribute and
+ *                            sub-chunks of 16 or more records per tile)
  * Returns BIN_ERR_INVALID_ARG for an unknown parameter or value. */
 #define BIN_TUNE_PART_WG 1
 #define BIN_TUNE_SCATTER_PPT 2
 #define BIN_TUNE_SCATTER_THREADS 3
 #define BIN_TUNE_TILE_SHIFT 4
 #define BIN_TUNE_SPLIT_LEN 5
+#define BIN_TUNE_QUADS 6
 int bin_set_tuning(int32_t param, int64_t value);
 
 /* Describe the strategy the planner picks for a request (no GPU work):

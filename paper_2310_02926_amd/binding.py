@@ -515,7 +515,7 @@ def bin_set_plan_override(strategy: int = -1, block: int = 0, grid: int = 0) -> 
     check(lib().bin_set_plan_override(strategy, block, grid))
 
 
-TUNE_PART_WG, TUNE_SCATTER_PPT, TUNE_SCATTER_THREADS, TUNE_TILE_SHIFT, TUNE_SPLIT_LEN = 1, 2, 3, 4, 5
+TUNE_PART_WG, TUNE_SCATTER_PPT, TUNE_SCATTER_THREADS, TUNE_TILE_SHIFT, TUNE_SPLIT_LEN, TUNE_QUADS = 1, 2, 3, 4, 5, 6
 
 
 def bin_set_tuning(param: int, value: int) -> None:
@@ -523,7 +523,7 @@ def bin_set_tuning(param: int, value: int) -> None:
 
 
 def reset_tuning() -> None:
-    for p in (TUNE_PART_WG, TUNE_SCATTER_PPT, TUNE_SCATTER_THREADS, TUNE_TILE_SHIFT, TUNE_SPLIT_LEN):
+    for p in (TUNE_PART_WG, TUNE_SCATTER_PPT, TUNE_SCATTER_THREADS, TUNE_TILE_SHIFT, TUNE_SPLIT_LEN, TUNE_QUADS):
         bin_set_tuning(p, 0)
     bin_set_plan_override(-1, 0, 0)
 

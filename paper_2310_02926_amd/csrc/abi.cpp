@@ -306,6 +306,10 @@ int bin_set_tuning(int32_t param, int64_t value) {
         return fail(BIN_ERR_INVALID_ARG, "BIN_TUNE_SPLIT_LEN must be in [1024, 2^31)");
       t_hints.split_len = value;
       return BIN_OK;
+    case BIN_TUNE_QUADS:
+      if (value > 2) return fail(BIN_ERR_INVALID_ARG, "BIN_TUNE_QUADS must be 0, 1 or 2");
+      t_hints.quads = (int)value;
+      return BIN_OK;
     default:
       return fail(BIN_ERR_INVALID_ARG, "unknown tuning parameter %d", param);
   }

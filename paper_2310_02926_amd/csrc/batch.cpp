@@ -137,8 +137,9 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
     for (int r = 0; r < R; ++r) {
       bk::PartArgs a = bp->preps[g.idx[r]].part;
       set_part_blocks(a, nt, ppt);
-      const size_t sv = al16(16 * (size_t)a.ntiles + 4 * S);
-      scatter_lds = std::max(scatter_lds, set_off_stage(a, sv + (a.k ? S * asz : 0), dev.lds_per_block - 256));
+      const size_t SP = S;  // batches gather record by record: no padding
+      const size_t sv = al16(16 * (size_t)a.ntiles + 2 * SP);
+      scatter_lds = std::max(scatter_lds, set_off_stage(a, sv + (a.k ? SP * asz : 0), dev.lds_per_block - 256));
     }
     g.cfg.ppt = ppt;
     g.cfg.scatter_threads = nt;
@@ -153,9 +154,13 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
     for (int r = 0; r < R; ++r) {
       bk::PartArgs a = bp->preps[g.idx[r]].part;
       set_part_blocks(a, nt, ppt);
-      const size_t nrec = (size_t)std::max<int64_t>(a.n, 1);
-      a.stage_val_off = (int32_t)al16(16 * (size_t)a.ntiles + 4 * S);
-      set_off_stage(a, a.stage_val_off + (a.k ? S * asz : 0), dev.lds_per_block - 256);
+      a.quads = 0;
+      a.pad_row = 0;
+      const size_t SP = S;
+      const size_t nrec = part_records(a);
+      a.stage_val_off = (int32_t)al16(16 * (size_t)a.ntiles + 2 * SP);
+      set_off_stage(a, a.stage_val_off + (a.k ? SP * asz : 0), dev.lds_per_block - 256);
+      set_part_items(a, dev.cus);
       a.counts = reinterpret_cast<uint32_t*>(take(4 * (size_t)a.ntiles * a.nwg));
       a.blk_off = reinterpret_cast<uint16_t*>(take(2 * (size_t)a.nwg * a.nbpw * (size_t)(a.ntiles + 1)));
       a.ilist = reinterpret_cast<uint32_t*>(take(4 * (size_t)a.ntiles * a.nwg));

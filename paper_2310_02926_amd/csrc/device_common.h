@@ -126,6 +126,7 @@ __device__ __forceinline__ T ld(const void* p, int64_t i) {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 // Elements i .. i+3 of a 16-byte aligned column (i a multiple of 4), read
 // with 16-byte loads: HBM streams at full rate only with wide loads.

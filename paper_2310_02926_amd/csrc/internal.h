@@ -25,6 +25,7 @@ struct PlanHints {
   int scatter_threads = 0;
   int tile_shift = 0;
   int64_t split_len = 0;
+  int quads = 0;  // 0 planner's choice, 1 off, 2 on
 };
 PlanHints& thread_hints_mut();
 
@@ -102,6 +103,14 @@ void set_part_blocks(bk::PartArgs& a, int scatter_threads, int ppt);
 // with as many rows (a power of two, at most 16 and no more than a slice's
 // sub-chunks need) as fit lds_limit; returns the scatter's LDS bytes.
 size_t set_off_stage(bk::PartArgs& a, size_t stage_base, size_t lds_limit);
+// Padding record slots per sub-chunk (runs padded to whole quads) and the
+// record slots a partition request needs.
+bool use_quads(int nk, bool attr_f64, int64_t ntiles, int64_t sub);
+int32_t part_pad_row(int64_t ntiles, int64_t sub);
+size_t part_records(const bk::PartArgs& a);
+// Work-item and partial-slot bounds (max_items, max_slots, merge_blocks) of
+// a partition request whose blocks and padding are set.
+void set_part_items(bk::PartArgs& a, int cus);
 // Workgroups of the split-tile merge launch (a.max_slots and a.lay set).
 int32_t merge_blocks(const bk::PartArgs& a, int cus);
 // Enqueue the kernels of a prepared request.

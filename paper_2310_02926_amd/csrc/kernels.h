@@ -146,11 +146,16 @@ struct PartArgs {
   int32_t nfull_z, nblocks_z;  // the same for the last slice
   int32_t off_shift;   // the scatter stages 2^off_shift rows of the run table in LDS
   int32_t off_stage;   // byte offset of that stage in the scatter LDS
+  int32_t quads;       // runs padded to whole quads of 4 records, gathered a quad per lane
+  int32_t pad_row;     // record slots per sub-chunk beyond its particles (a multiple of 4;
+                       // 0 without quads)
   uint32_t* counts;    // [ntiles][nwg] records of each tile in each slice
   uint16_t* blk_off;   // [ntiles + 1][nwg * nbpw] start of each tile's run within its sub-chunk
                        // (row w * nbpw + j = sub-chunk j of slice w; entry ntiles = records)
-  uint16_t* rec_bin;   // [n] records: a sub-chunk starting at particle i writes its
-  void* rec_val[kMaxAttrs];  //   records, grouped by tile, to [i, i + inside)
+  uint16_t* rec_bin;   // records: sub-chunk j of slice w, starting at particle i, writes
+  void* rec_val[kMaxAttrs];  //   its records, grouped by tile (with quads each tile's run
+                       //   padded to a multiple of 4, pad bin 0xFFFF), from
+                       //   i + (w * nbpw + j) * pad_row
   uint32_t* ilist;     // [ntiles][nwg] first slice of each of a tile's items
   uint32_t* items;     // [max_items][3]: tile, first slice, end slice
   uint32_t* n_items;   // [1]

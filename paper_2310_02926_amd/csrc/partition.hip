@@ -127,7 +127,7 @@ __device__ __forceinline__ void scatter_sub(const PartArgs& a, unsigned char* sm
   uint32_t* cprev = reinterpret_cast<uint32_t*>(smem) + (parity ^ 1) * T;
   uint32_t* off = reinterpret_cast<uint32_t*>(smem) + 2 * T;
   uint32_t* tot = off + T;
-  uint32_t* stg_tb = tot + T;
+  uint16_t* stg_b = reinterpret_cast<uint16_t*>(tot + T);
   AT* stg_v = reinterpret_cast<AT*>(smem + a.stage_val_off);
   const int shift = a.lay.tile_shift;
   const uint32_t lmask = (1u << shift) - 1u;
@@ -186,9 +186,10 @@ __device__ __forceinline__ void scatter_sub(const PartArgs& a, unsigned char* sm
     const int lane = threadIdx.x;
     const int m = (T + 63) >> 6;
     const int t0 = lane * m;
+    const uint32_t padm = a.quads ? 3u : 0u;  // runs padded to whole quads
     uint32_t own = 0;
     for (int q = 0; q < m; ++q)
-      if (t0 + q < T) own += cnt[t0 + q];
+      if (t0 + q < T) own += (cnt[t0 + q] + padm) & ~padm;
     uint32_t x = own;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -199,7 +200,7 @@ __device__ __forceinline__ void scatter_sub(const PartArgs& a, unsigned char* sm
     for (int q = 0; q < m; ++q) {
       const int t = t0 + q;
       if (t < T) {
-        const uint32_t c = cnt[t];
+        const uint32_t c = (cnt[t] + padm) & ~padm;
         tot[t] += c;
         cprev[t] = 0u;
         off[t] = o0;
@@ -215,13 +216,22 @@ __device__ __forceinline__ void scatter_sub(const PartArgs& a, unsigned char* sm
   // are staged in LDS as [tile][F] and written F at a time.
   const int F = 1 << a.off_shift;
   uint16_t* ost = reinterpret_cast<uint16_t*>(smem + a.off_stage);
-  for (int t = threadIdx.x; t <= T; t += NT)
+  for (int t = threadIdx.x; t <= T; t += NT) {
     ost[(t << a.off_shift) + (j & (F - 1))] = (uint16_t)(t < T ? off[t] : nsub);
+    if (a.quads && t < T) {  // pad the tile's run to a whole quad: bin 0xFFFF, value 0
+      const uint32_t c = cnt[t];
+      const uint32_t e = off[t] + ((c + 3u) & ~3u);
+      for (uint32_t p = off[t] + c; p < e; ++p) {
+        stg_b[p] = 0xFFFFu;
+        if (k > 0) stg_v[p] = AT(0);
+      }
+    }
+  }
 #pragma unroll
   for (int u = 0; u < PPT; ++u) {
     if (tb[u] == 0xFFFFFFFFu) continue;
     pos[u] += off[tb[u] >> 16];
-    stg_tb[pos[u]] = tb[u];
+    stg_b[pos[u]] = (uint16_t)(tb[u] & 0xFFFFu);
   }
   if (k > 0) {
     if constexpr (kPre) {
@@ -253,35 +263,50 @@ __device__ __forceinline__ void scatter_sub(const PartArgs& a, unsigned char* sm
       if (jj < f) a.blk_off[(int64_t)t * nrows + r0 + jj] = ost[i];
     }
   }
-  // One contiguous stream of records over [base, base + nsub).
-  uint16_t* rb = a.rec_bin + base;
-  for (uint32_t p = threadIdx.x; p < nsub; p += NT) rb[p] = (uint16_t)(stg_tb[p] & 0xFFFFu);
-  if (k > 0) {
-    AT* rv = static_cast<AT*>(a.rec_val[0]) + base;
-    for (uint32_t p = threadIdx.x; p < nsub; p += NT) rv[p] = stg_v[p];
+  // One contiguous stream of records over [rbase, rbase + nsub); with quads
+  // (nsub and rbase multiples of 4) as 8-byte bin and 16-byte value stores.
+  const int64_t rbase = base + (row0 + j) * (int64_t)a.pad_row;
+  if (a.quads) {
+    u32x2* rb = reinterpret_cast<u32x2*>(a.rec_bin + rbase);
+    const u32x2* sb = reinterpret_cast<const u32x2*>(stg_b);
+    for (uint32_t p = threadIdx.x; p < nsub / 4; p += NT) rb[p] = sb[p];
+  } else {
+    uint16_t* rb = a.rec_bin + rbase;
+    for (uint32_t p = threadIdx.x; p < nsub; p += NT) rb[p] = stg_b[p];
   }
+  auto copy_values = [&](int jx) {
+    if (a.quads) {
+      constexpr uint32_t kVq = sizeof(AT) / 4;  // 16-byte units per quad of values
+      u32x4* rv = reinterpret_cast<u32x4*>(static_cast<AT*>(a.rec_val[jx]) + rbase);
+      const u32x4* sv = reinterpret_cast<const u32x4*>(stg_v);
+      for (uint32_t p = threadIdx.x; p < nsub / 4 * kVq; p += NT) rv[p] = sv[p];
+    } else {
+      AT* rv = static_cast<AT*>(a.rec_val[jx]) + rbase;
+      for (uint32_t p = threadIdx.x; p < nsub; p += NT) rv[p] = stg_v[p];
+    }
+  };
+  if (k > 0) copy_values(0);
   // Further attributes reuse the one value stage (the positions are the
   // same), so the stage is as large for k attributes as for one.  Keeping
   // the positions live costs registers: requests with two or more
   // attributes run sub-chunks of at most 8192 particles (the planner's
   // rule), and only those instances carry this loop.
   if constexpr (S <= 8192)
-  for (int j = 1; j < k; ++j) {
+  for (int jx = 1; jx < k; ++jx) {
     __syncthreads();  // the previous attribute's copy-out has read the stage
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       AT v[4];
       if constexpr (FULL)
-        ld4v<AT>(static_cast<const AT*>(a.attr[j]) + base, lane4 + 4u * q * NT, v);
+        ld4v<AT>(static_cast<const AT*>(a.attr[jx]) + base, lane4 + 4u * q * NT, v);
       else
-        ld4<AT>(a.attr[j], base + 4 * ((int64_t)q * NT + threadIdx.x), hi, false, v);
+        ld4<AT>(a.attr[jx], base + 4 * ((int64_t)q * NT + threadIdx.x), hi, false, v);
 #pragma unroll
       for (int e = 0; e < 4; ++e)
         if (tb[4 * q + e] != 0xFFFFFFFFu) stg_v[pos[4 * q + e]] = v[e];
     }
     __syncthreads();
-    AT* rv = static_cast<AT*>(a.rec_val[j]) + base;
-    for (uint32_t p = threadIdx.x; p < nsub; p += NT) rv[p] = stg_v[p];
+    copy_values(jx);
   }
 }
 
@@ -496,7 +521,18 @@ __global__ __launch_bounds__(1024) void part_items_batched(const PartArgs* __res
 // the concatenated runs onto the lanes 64 records at a time (a binary
 // search over the scan for the lane's run).
 // ---------------------------------------------------------------------------
-template <typename AT, int PREC>
+// The 4 values of quad q (16-byte loads; zeros for no quad).
+template <typename AT>
+__device__ __forceinline__ void ld_quad(const void* p, uint32_t q, AT* out) {
+  if (q == 0xFFFFFFFFu) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out[e] = AT(0);
+    return;
+  }
+  ld4v<AT, int64_t>(p, (int64_t)q * 4, out);
+}
+
+template <typename AT, int PREC, bool QUAD>
 __device__ __forceinline__ void part_bin_body(const PartArgs& a, int item) {
   using TL = Tile<AT, PREC>;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -513,7 +549,7 @@ __device__ __forceinline__ void part_bin_body(const PartArgs& a, int item) {
   __syncthreads();
 
   const int lane = threadIdx.x & 63;
-  const uint32_t wid = threadIdx.x >> 6;
+  const uint32_t wid = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // wave-uniform
   const uint32_t nwaves = blockDim.x >> 6;
   const uint32_t nblk = (w1 - w0) * (uint32_t)a.nbpw;
   // Column t of the run table from the item's first row: consecutive lanes
@@ -522,94 +558,201 @@ __device__ __forceinline__ void part_bin_body(const PartArgs& a, int item) {
   const uint16_t* col = a.blk_off + (int64_t)t * nrows + (int64_t)w0 * a.nbpw;
   // The lane's run in sub-chunk c of the item (len 0 past the end or for a
   // sub-chunk a short slice does not have).
-  auto run_of = [&](uint32_t c, uint32_t& len, uint32_t& rs) {
-    len = 0;
-    rs = 0;
-    if (c < nblk) {
-      const uint32_t dw = c / (uint32_t)a.nbpw;
-      const int w = (int)(w0 + dw);
-      const int j = (int)(c - dw * (uint32_t)a.nbpw);
-      const SliceShape shp = slice_shape(a, w);
-      if (j < shp.nblocks) {
-        const uint32_t s0 = col[c];
-        len = (uint32_t)col[c + nrows] - s0;
-        rs = (uint32_t)(block_base(shp, a, j) + s0);
+  if constexpr (QUAD) {
+    // The lane's run in sub-chunk c of the item, in quads of 4 records: its
+    // length and the quad index of its first quad (len 0 past the end or for
+    // a sub-chunk a short slice does not have).
+    auto run_of = [&](uint32_t c, uint32_t& len, uint32_t& rs) {
+      len = 0;
+      rs = 0;
+      if (c < nblk) {
+        const uint32_t dw = c / (uint32_t)a.nbpw;
+        const int w = (int)(w0 + dw);
+        const int j = (int)(c - dw * (uint32_t)a.nbpw);
+        const SliceShape shp = slice_shape(a, w);
+        if (j < shp.nblocks) {
+          const uint32_t s0 = col[c];
+          len = ((uint32_t)col[c + nrows] - s0) >> 2;
+          const int64_t r0 = block_base(shp, a, j) + ((int64_t)w * a.nbpw + j) * a.pad_row + s0;
+          rs = (uint32_t)(r0 >> 2);
+        }
       }
-    }
-  };
-  // Groups of 64 sub-chunks; with fewer groups than waves, wpg waves share
-  // a group and take every wpg-th window of its records.
-  const uint32_t ngroups = (nblk + 63) / 64;
-  uint32_t wpg = 1;
-  while (wpg < nwaves && ngroups * wpg * 2 <= nwaves) wpg *= 2;
-  const uint32_t gstride = nwaves / wpg;
-  const uint32_t sub = wid % wpg;
-  uint32_t nlen, nrs;  // the next group's run, read while this group is binned
-  run_of((wid / wpg) * 64 + lane, nlen, nrs);
-  for (uint32_t g = wid / wpg; g < ngroups; g += gstride) {
-    const uint32_t len = nlen, rs = nrs;  // first record of the lane's run
-    run_of((g + gstride) * 64 + lane, nlen, nrs);
-    uint32_t incl = len;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t y = __shfl_up(incl, o);
-      if (lane >= o) incl += y;
-    }
-    const uint32_t total = __shfl(incl, 63);
-    const uint32_t start = rs - (incl - len);  // record = start + q for q in the lane's run
-    // R windows of 64 records at a time: all their loads are issued before
-    // the first LDS update, so R gathers per wave are in flight.
-    constexpr int R = sizeof(AT) == 8 ? 4 : 8;
-    for (uint32_t wb = 0; 64 * (sub + wpg * wb) < total; wb += R) {
-      uint32_t rec[R];
-      int lb[R];
-#pragma unroll
-      for (int u = 0; u < R; ++u) {
-        // Window of records [w0q, w0q + 64): the runs holding its first and
-        // last records are found with two ballots (wave-uniform), and each
-        // lane picks the last run in that range starting at or before its
-        // record, reading run starts with readlane (no LDS traffic).
-        const uint32_t w0q = 64 * (sub + wpg * (wb + u));
-        uint32_t recu = 0xFFFFFFFFu;
-        if (w0q < total) {
-          const uint32_t wl = w0q + 63 < total ? w0q + 63 : total - 1;
-          const int la = __builtin_ctzll(__ballot(incl > w0q));
-          const int lb = __builtin_ctzll(__ballot(incl > wl));
+    };
+    // Groups of 64 sub-chunks; with fewer groups than waves, wpg waves share
+    // a group and take every wpg-th window of its quads.
+    const uint32_t ngroups = (nblk + 63) / 64;
+    uint32_t wpg = 1;
+    while (wpg < nwaves && ngroups * wpg * 2 <= nwaves) wpg *= 2;
+    const uint32_t gstride = nwaves / wpg;
+    const uint32_t sub = wid % wpg;
+    uint32_t nlen, nrs;  // the next group's run, read while this group is binned
+    run_of((wid / wpg) * 64 + lane, nlen, nrs);
+    for (uint32_t g = wid / wpg; g < ngroups; g += gstride) {
+      const uint32_t len = nlen, rs = nrs;  // first quad of the lane's run
+      run_of((g + gstride) * 64 + lane, nlen, nrs);
+      uint32_t incl = len;
+  #pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+      }
+      // Wave-uniform scalars (readlane), so the window tests below stay on the
+      // scalar unit: every vector instruction here costs 4 cycles per wave.
+      const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+      const uint32_t start = rs - (incl - len);  // quad = start + q for q in the lane's run
+      // R windows of 64 quads at a time: all their loads are issued before the
+      // first LDS update, so R gathers of 4 records per lane are in flight.
+      constexpr int R = sizeof(AT) == 8 ? 1 : 2;
+      constexpr int N = 4 * R;
+      for (uint32_t wb = 0; 64 * (sub + wpg * wb) < total; wb += R) {
+        uint32_t quad[R];
+  #pragma unroll
+        for (int u = 0; u < R; ++u) {
+          // Window of quads [w0q, w0q + 64): lane q's run is the number of
+          // runs that end at or before q (incl is sorted), found by a
+          // branch-free binary search over the wave's lanes (cross-lane reads
+          // through ds_bpermute), so the R windows' searches overlap and the
+          // cost does not grow with the number of runs a window spans.
+          const uint32_t w0q = 64 * (sub + wpg * (wb + u));
           const uint32_t q = w0q + lane;
-          uint32_t st = (uint32_t)__builtin_amdgcn_readlane((int)start, la);
-          for (int x = la + 1; x <= lb; ++x) {
-            const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)incl, x - 1);  // first record of run x
-            const uint32_t sx = (uint32_t)__builtin_amdgcn_readlane((int)start, x);
-            if (q >= e) st = sx;
+          int pos = 0;
+  #pragma unroll
+          for (int step = 32; step >= 1; step >>= 1) {
+            const uint32_t e = (uint32_t)__builtin_amdgcn_ds_bpermute((pos + step - 1) << 2, (int)incl);
+            pos += e <= q ? step : 0;
           }
-          if (q < total) recu = st + q;
+          // pos == 64 only for q >= total
+          const uint32_t st = (uint32_t)__builtin_amdgcn_ds_bpermute((pos & 63) << 2, (int)start);
+          quad[u] = q < total ? st + q : 0xFFFFFFFFu;
         }
-        rec[u] = recu;
+        // Every load of the R windows - bins and the first attributes - is
+        // issued before the first LDS update: one 8-byte load of 4 bins and
+        // 16-byte loads of their values per quad.
+        constexpr int KV = sizeof(AT) == 8 ? 2 : 4;
+        int lb[N];
+        AT v[KV][N];
+  #pragma unroll
+        for (int u = 0; u < R; ++u) {
+          u32x2 bq = {0xFFFFFFFFu, 0xFFFFFFFFu};
+          if (quad[u] != 0xFFFFFFFFu) bq = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(a.rec_bin) + quad[u]);
+  #pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const uint32_t b = ((e < 2 ? bq.x : bq.y) >> (16 * (e & 1))) & 0xFFFFu;
+            lb[4 * u + e] = b == 0xFFFFu ? -1 : (int)b;  // 0xFFFF: padding (or no quad)
+          }
+        }
+  #pragma unroll
+        for (int jj = 0; jj < KV; ++jj)
+          if (jj < k) {
+  #pragma unroll
+            for (int u = 0; u < R; ++u) ld_quad<AT>(a.rec_val[jj], quad[u], v[jj] + 4 * u);
+          }
+  #pragma unroll
+        for (int e = 0; e < N; ++e)
+          if (lb[e] >= 0) TL::count(smem, lb[e]);
+  #pragma unroll
+        for (int jj = 0; jj < KV; ++jj)
+          if (jj < k) TL::template add_batch<N>(smem, a.lay, jj, lb, v[jj]);
+        for (int jj = KV; jj < k; ++jj) {
+          AT w[N];
+  #pragma unroll
+          for (int u = 0; u < R; ++u) ld_quad<AT>(a.rec_val[jj], quad[u], w + 4 * u);
+          TL::template add_batch<N>(smem, a.lay, jj, lb, w);
+        }
       }
-      // Every load of the R windows - bins and the first four attributes -
-      // is issued before the first LDS update.
-      constexpr int KV = sizeof(AT) == 8 ? 2 : 4;
-      AT v[KV][R];
-#pragma unroll
-      for (int u = 0; u < R; ++u)
-        lb[u] = rec[u] != 0xFFFFFFFFu ? (int)__builtin_nontemporal_load(a.rec_bin + rec[u]) : -1;
-#pragma unroll
-      for (int jj = 0; jj < KV; ++jj)
-        if (jj < k) {
-#pragma unroll
-          for (int u = 0; u < R; ++u) v[jj][u] = rec[u] != 0xFFFFFFFFu ? ld<AT>(a.rec_val[jj], rec[u]) : AT(0);
+    }
+  } else {
+    // Records one per lane (no padding): 64-record windows, each lane's run
+    // picked among the window's runs with readlane.
+    auto run_of = [&](uint32_t c, uint32_t& len, uint32_t& rs) {
+      len = 0;
+      rs = 0;
+      if (c < nblk) {
+        const uint32_t dw = c / (uint32_t)a.nbpw;
+        const int w = (int)(w0 + dw);
+        const int j = (int)(c - dw * (uint32_t)a.nbpw);
+        const SliceShape shp = slice_shape(a, w);
+        if (j < shp.nblocks) {
+          const uint32_t s0 = col[c];
+          len = (uint32_t)col[c + nrows] - s0;
+          rs = (uint32_t)(block_base(shp, a, j) + s0);
         }
-#pragma unroll
-      for (int u = 0; u < R; ++u)
-        if (lb[u] >= 0) TL::count(smem, lb[u]);
-#pragma unroll
-      for (int jj = 0; jj < KV; ++jj)
-        if (jj < k) TL::template add_batch<R>(smem, a.lay, jj, lb, v[jj]);
-      for (int jj = KV; jj < k; ++jj) {
-        AT w[R];
-#pragma unroll
-        for (int u = 0; u < R; ++u) w[u] = rec[u] != 0xFFFFFFFFu ? ld<AT>(a.rec_val[jj], rec[u]) : AT(0);
-        TL::template add_batch<R>(smem, a.lay, jj, lb, w);
+      }
+    };
+    // Groups of 64 sub-chunks; with fewer groups than waves, wpg waves share
+    // a group and take every wpg-th window of its records.
+    const uint32_t ngroups = (nblk + 63) / 64;
+    uint32_t wpg = 1;
+    while (wpg < nwaves && ngroups * wpg * 2 <= nwaves) wpg *= 2;
+    const uint32_t gstride = nwaves / wpg;
+    const uint32_t sub = wid % wpg;
+    uint32_t nlen, nrs;  // the next group's run, read while this group is binned
+    run_of((wid / wpg) * 64 + lane, nlen, nrs);
+    for (uint32_t g = wid / wpg; g < ngroups; g += gstride) {
+      const uint32_t len = nlen, rs = nrs;  // first record of the lane's run
+      run_of((g + gstride) * 64 + lane, nlen, nrs);
+      uint32_t incl = len;
+  #pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+      }
+      const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+      const uint32_t start = rs - (incl - len);  // record = start + q for q in the lane's run
+      // R windows of 64 records at a time: all their loads are issued before
+      // the first LDS update, so R gathers per wave are in flight.
+      constexpr int R = sizeof(AT) == 8 ? 4 : 8;
+      for (uint32_t wb = 0; 64 * (sub + wpg * wb) < total; wb += R) {
+        uint32_t rec[R];
+        int lb[R];
+  #pragma unroll
+        for (int u = 0; u < R; ++u) {
+          // Window of records [w0q, w0q + 64): the runs holding its first and
+          // last records are found with two ballots (wave-uniform), and each
+          // lane picks the last run in that range starting at or before its
+          // record, reading run starts with readlane (no LDS traffic).
+          const uint32_t w0q = 64 * (sub + wpg * (wb + u));
+          uint32_t recu = 0xFFFFFFFFu;
+          if (w0q < total) {
+            const uint32_t wl = w0q + 63 < total ? w0q + 63 : total - 1;
+            const int la = __builtin_amdgcn_readfirstlane(__builtin_ctzll(__ballot(incl > w0q)));
+            const int lb = __builtin_amdgcn_readfirstlane(__builtin_ctzll(__ballot(incl > wl)));
+            const uint32_t q = w0q + lane;
+            uint32_t st = (uint32_t)__builtin_amdgcn_readlane((int)start, la);
+            for (int x = la + 1; x <= lb; ++x) {
+              const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)incl, x - 1);  // first record of run x
+              const uint32_t sx = (uint32_t)__builtin_amdgcn_readlane((int)start, x);
+              if (q >= e) st = sx;
+            }
+            if (q < total) recu = st + q;
+          }
+          rec[u] = recu;
+        }
+        // Every load of the R windows - bins and the first four attributes -
+        // is issued before the first LDS update.
+        constexpr int KV = sizeof(AT) == 8 ? 2 : 4;
+        AT v[KV][R];
+  #pragma unroll
+        for (int u = 0; u < R; ++u)
+          lb[u] = rec[u] != 0xFFFFFFFFu ? (int)__builtin_nontemporal_load(a.rec_bin + rec[u]) : -1;
+  #pragma unroll
+        for (int jj = 0; jj < KV; ++jj)
+          if (jj < k) {
+  #pragma unroll
+            for (int u = 0; u < R; ++u) v[jj][u] = rec[u] != 0xFFFFFFFFu ? ld<AT>(a.rec_val[jj], rec[u]) : AT(0);
+          }
+  #pragma unroll
+        for (int u = 0; u < R; ++u)
+          if (lb[u] >= 0) TL::count(smem, lb[u]);
+  #pragma unroll
+        for (int jj = 0; jj < KV; ++jj)
+          if (jj < k) TL::template add_batch<R>(smem, a.lay, jj, lb, v[jj]);
+        for (int jj = KV; jj < k; ++jj) {
+          AT w[R];
+  #pragma unroll
+          for (int u = 0; u < R; ++u) w[u] = rec[u] != 0xFFFFFFFFu ? ld<AT>(a.rec_val[jj], rec[u]) : AT(0);
+          TL::template add_batch<R>(smem, a.lay, jj, lb, w);
+        }
       }
     }
   }
@@ -627,19 +770,20 @@ __device__ __forceinline__ void part_bin_body(const PartArgs& a, int item) {
 // (b % 8) * P + b / 8 with P = ceil(items / 8), so each XCD takes a
 // contiguous range of tiles and neighbouring tiles' runs, which share cache
 // lines, are read through the same L2.
-template <typename AT, int PREC>
+template <typename AT, int PREC, bool QUAD>
 __global__ __launch_bounds__(1024) void part_bin_kernel(PartArgs a) {
   const uint32_t n = *a.n_items;
   const uint32_t per = (n + 7) / 8;
   const uint32_t s = blockIdx.x / 8;
   if (s >= per) return;
-  part_bin_body<AT, PREC>(a, (int)((blockIdx.x % 8) * per + s));
+  part_bin_body<AT, PREC, QUAD>(a, (int)((blockIdx.x % 8) * per + s));
 }
+// Batches gather record by record (their requests are planned without quads).
 template <typename AT, int PREC>
 __global__ __launch_bounds__(1024) void part_bin_batched(const PartArgs* __restrict__ d,
                                                          const uint32_t* __restrict__ map) {
   const uint32_t m = map[blockIdx.x];
-  part_bin_body<AT, PREC>(d[m >> 16], (int)(m & 0xFFFFu));
+  part_bin_body<AT, PREC, false>(d[m >> 16], (int)(m & 0xFFFFu));
 }
 
 // Merge of split tiles: work unit u = (split tile, 1024-bin chunk), one bin
@@ -710,7 +854,12 @@ static hipError_t launch_part_t(const PartArgs& a, const PartCfg& c, hipStream_t
   BK_SCATTER_SWITCH(part_scatter_kernel, a.nwg, a)
   BK_LAUNCH("part_items_walk_kernel", part_items_walk_kernel, (a.ntiles + 15) / 16, 1024, 0, a);
   BK_LAUNCH("part_items_kernel", part_items_kernel, 1, 1024, 0, a);
-  BK_LAUNCH("part_bin_kernel", (part_bin_kernel<AT, PREC>), (a.max_items + 7) / 8 * 8, c.bin_block, c.bin_lds, a);
+  if (a.quads)
+    BK_LAUNCH("part_bin_kernel", (part_bin_kernel<AT, PREC, true>), (a.max_items + 7) / 8 * 8, c.bin_block, c.bin_lds,
+              a);
+  else
+    BK_LAUNCH("part_bin_kernel", (part_bin_kernel<AT, PREC, false>), (a.max_items + 7) / 8 * 8, c.bin_block, c.bin_lds,
+              a);
   BK_LAUNCH("part_merge_kernel", (part_merge_kernel<AT, PREC>), a.merge_blocks, 1024, 0, a);
   return hipSuccess;
 }
@@ -770,10 +919,14 @@ hipError_t set_partition_lds_limit(size_t bytes) {
   BK_SET_CA(K, float, float) BK_SET_CA(K, float, double) BK_SET_CA(K, double, float) BK_SET_CA(K, double, double)
   BK_SET_TYPES(part_scatter_kernel)
   BK_SET_TYPES(part_scatter_batched)
-  BK_SETF(part_bin_kernel<float, PREC_F64>)
-  BK_SETF(part_bin_kernel<float, PREC_COMP>)
-  BK_SETF(part_bin_kernel<float, PREC_PLAIN>)
-  BK_SETF(part_bin_kernel<double, PREC_F64>)
+  BK_SETF(part_bin_kernel<float, PREC_F64, false>)
+  BK_SETF(part_bin_kernel<float, PREC_COMP, false>)
+  BK_SETF(part_bin_kernel<float, PREC_PLAIN, false>)
+  BK_SETF(part_bin_kernel<double, PREC_F64, false>)
+  BK_SETF(part_bin_kernel<float, PREC_F64, true>)
+  BK_SETF(part_bin_kernel<float, PREC_COMP, true>)
+  BK_SETF(part_bin_kernel<float, PREC_PLAIN, true>)
+  BK_SETF(part_bin_kernel<double, PREC_F64, true>)
   BK_SETF(part_bin_batched<float, PREC_F64>)
   BK_SETF(part_bin_batched<float, PREC_COMP>)
   BK_SETF(part_bin_batched<float, PREC_PLAIN>)

@@ -74,6 +74,35 @@ void set_part_blocks(bk::PartArgs& a, int scatter_threads, int ppt) {
   a.nbpw = std::max({a.nblocks_a, a.nblocks_z, 1});
 }
 
+void set_part_items(bk::PartArgs& a, int cus) {
+  // Items group whole slices greedily; two consecutive items of a tile hold
+  // more than split_len records together, so a tile with R records (padding
+  // included) has at most 2 + 2 R / split_len items.
+  a.max_items = (int32_t)(2 * (int64_t)a.ntiles + 2 * ceil_div((int64_t)part_records(a), (int64_t)a.split_len));
+  // Partial slots only for items of split tiles (ni >= 2 items each):
+  // sum over split tiles of ni <= 2 * sum of (ni - 1) <= 2 * (max_items - ntiles).
+  a.max_slots = (int32_t)std::min<int64_t>(a.max_items, 2 * ((int64_t)a.max_items - a.ntiles));
+  a.merge_blocks = merge_blocks(a, cus);
+}
+
+bool use_quads(int nk, bool attr_f64, int64_t ntiles, int64_t sub) {
+  // Whole quads per lane pay off where runs are long (a sub-chunk averages
+  // 16 or more records per tile) and a quad carries at most one f32
+  // attribute: there the padding is small and the gather's per-record work
+  // drops.  With more attributes, or short runs, the padding costs more.
+  return nk <= 1 && !attr_f64 && sub >= 16 * ntiles;
+}
+
+int32_t part_pad_row(int64_t ntiles, int64_t sub) {
+  // each tile's run in a sub-chunk gains at most 3 padding records, and only
+  // a tile with a record has a run
+  return (int32_t)((3 * std::min<int64_t>(ntiles, sub) + 3) & ~int64_t(3));
+}
+
+size_t part_records(const bk::PartArgs& a) {
+  return (size_t)std::max<int64_t>(a.n, 0) + (size_t)a.nwg * a.nbpw * (size_t)a.pad_row + 4;
+}
+
 size_t set_off_stage(bk::PartArgs& a, size_t stage_base, size_t lds_limit) {
   a.off_stage = (int32_t)align16(stage_base);
   const size_t cols = (size_t)a.ntiles + 1;
@@ -274,10 +303,6 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints_
     L = std::max<int64_t>(L, 16384);
     if (hints.split_len) L = hints.split_len;
     a.split_len = (uint32_t)std::min<int64_t>(L, 0x7FFFFFFF);
-    // Items group whole slices greedily; two consecutive items of a tile
-    // hold more than split_len records together, so a tile with R records
-    // has at most 2 + 2 R / split_len items.
-    a.max_items = (int32_t)(2 * ntiles + 2 * ceil_div(n, (int64_t)a.split_len));
     // scatter LDS: 4 T counters, S tile/bin words, S values (one attribute
     // at a time)
     // 1024-thread scatter workgroups measured fastest on MI355X for both the
@@ -298,9 +323,11 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints_
       if (tp0 == 12 && tnt != 1024) tp0 = 8;  // 12 per thread exists for 1024 threads only
       for (int tp = tp0; tp >= 4; tp = tp == 12 ? 8 : tp / 2) {
         const size_t S = (size_t)tnt * tp;
-        const int32_t svo = (int32_t)align16(16 * (size_t)T + 4 * S);
+        const bool quads = hints.quads ? hints.quads == 2 : use_quads(nk, p->attr_f64, T, (int64_t)S);
+        const size_t SP = S + (quads ? part_pad_row(T, (int64_t)S) : 0);  // staged records incl. padding
+        const int32_t svo = (int32_t)align16(16 * (size_t)T + 2 * SP);
         // values, then at least one staged row of the run table
-        const size_t need = svo + (nk ? S * asz : 0);
+        const size_t need = svo + (nk ? SP * asz : 0);
         if (align16(need) + align16(2 * ((size_t)T + 1)) + kScatterStatic <= lds_budget) {
           nt = tnt;
           ppt = tp;
@@ -318,7 +345,10 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints_
     // Half-size workgroups when two tiles fit a CU's LDS: two items per CU.
     c.bin_block = 2 * tile_lds <= dev.lds_per_cu ? 512 : 1024;
     set_part_blocks(a, nt, ppt);
+    a.quads = (hints.quads ? hints.quads == 2 : use_quads(nk, p->attr_f64, T, (int64_t)nt * ppt)) ? 1 : 0;
+    a.pad_row = a.quads ? part_pad_row(T, (int64_t)nt * ppt) : 0;
     c.scatter_lds = set_off_stage(a, sc, lds_budget - kScatterStatic);
+    set_part_items(a, cus);
     // scratch
     a.counts = static_cast<uint32_t*>(cv.take(4 * (size_t)ntiles * a.nwg));
     a.blk_off = static_cast<uint16_t*>(cv.take(2 * (size_t)a.nwg * a.nbpw * (size_t)(ntiles + 1)));
@@ -327,13 +357,9 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints_
     a.n_items = static_cast<uint32_t*>(cv.take(4));
     a.tile_items = static_cast<uint32_t*>(cv.take(12 * (size_t)T));
     a.split_list = static_cast<uint32_t*>(cv.take(4 * ((size_t)T + 1)));
-    a.rec_bin = static_cast<uint16_t*>(cv.take(2 * (size_t)std::max<int64_t>(n, 1)));
-    for (int j = 0; j < nk; ++j) a.rec_val[j] = cv.take(asz * (size_t)std::max<int64_t>(n, 1));
-    // Partial slots only for items of split tiles (ni >= 2 items each):
-    // sum over split tiles of ni <= 2 * sum of (ni - 1) <= 2 * (max_items - ntiles).
-    a.max_slots = (int32_t)std::min<int64_t>(a.max_items, 2 * (a.max_items - ntiles));
+    a.rec_bin = static_cast<uint16_t*>(cv.take(2 * part_records(a)));
+    for (int j = 0; j < nk; ++j) a.rec_val[j] = cv.take(asz * part_records(a));
     a.partial = a.max_slots > 0 ? cv.take((size_t)a.lay.slot_bytes * a.max_slots) : nullptr;
-    a.merge_blocks = merge_blocks(a, cus);
     p->scratch_bytes = cv.used;
     p->cfg.grid = a.max_items;
     p->cfg.block = c.bin_block;
@@ -441,11 +467,11 @@ std::string describe(const Prepared& p) {
       break;
     case bk::STRAT_PART:
       snprintf(buf, sizeof buf,
-               "partition tiles=%d tile_bins=%d wg=%d chunk=%lld threads=%d ppt=%d sub=%d blocks=%d staged_rows=%d split=%u "
+               "partition tiles=%d tile_bins=%d wg=%d chunk=%lld threads=%d ppt=%d sub=%d blocks=%d staged_rows=%d quads=%d split=%u "
                "max_items=%d "
                "scatter_lds=%zu bin_lds=%zu vec=%d prec=%s",
                p.part.ntiles, 1 << p.part.lay.tile_shift, p.part.nwg, (long long)p.part.chunk, p.pcfg.scatter_threads,
-               p.pcfg.ppt, p.part.sub, p.part.nbpw, 1 << p.part.off_shift,
+               p.pcfg.ppt, p.part.sub, p.part.nbpw, 1 << p.part.off_shift, p.part.quads,
                p.part.split_len, p.part.max_items, p.pcfg.scatter_lds, p.pcfg.bin_lds, p.part.vec, prec);
       break;
     default:

@@ -113,6 +113,51 @@ def test_partition_forced_split_lengths(split_len):
     G.assert_parity(got, ref, 31, what=f"split_len={split_len}")
 
 
+def _quad_cases():
+    rng = np.random.default_rng(77)
+    n = 1_500_001  # ragged: the last slice and sub-chunk are partial
+    x, y = rng.random(n), rng.random(n)
+    yield "hotspot k=1", synth.hotspot_f32(n=2_000_000, seed=5, side=512, contiguous=True), 0
+    yield "gmm k=4", synth.gmm_f32(n=1_000_000, seed=6, nx=1024, ny=1024, k=4), 0
+    yield "f64 attrs k=2", _ws([x.astype(np.float32), y.astype(np.float32)],
+                               [rng.standard_normal(n), rng.lognormal(0, 1, n)], 700, 900), 0
+    yield "f64 coords count only", _ws([x, y], [], 2048, 1000, ops=1), 0
+    e = synth.edge_points(0.0, 1.0, 1024, np.float32)
+    yield "edges", _ws([rng.choice(e, n), rng.choice(e, n)], [rng.standard_normal(n).astype(np.float32)],
+                       1024, 1024), 0
+    yield "sparse tiles (runs of 1-3 records)", _ws([x.astype(np.float32) * 0.999, y.astype(np.float32)],
+                                                   [rng.standard_normal(n).astype(np.float32)], 4096, 4096), 0
+    yield "unaligned columns", _ws([x.astype(np.float32), y.astype(np.float32)],
+                                   [rng.standard_normal(n).astype(np.float32)], 1500, 1500), 1
+
+
+@pytest.mark.parametrize("quads", [1, 2], ids=["records", "quads"])
+def test_partition_record_and_quad_gathers(quads):
+    """Both gathers of the tile binning - record by record, and whole quads
+    of 4 records (each tile's run padded with empty records) - on the cases
+    the planner would send to either: one or several attributes, f64
+    attributes and coordinates, count only, bin edges, sparse tiles with
+    runs of a few records, a ragged size and unaligned columns."""
+    from paper_2310_02926_amd import binding as B
+    for name, ws, shift in _quad_cases():
+        _case(f"partition gather quads={quads}: {name}")
+        ref = G.oracle(ws)
+        coords, attrs = G.to_device(ws)
+        if shift:  # views at an element offset: no 16-byte loads
+            coords = [torch.cat([c[:1], c])[1:] for c in coords]
+            attrs = [torch.cat([a[:1], a])[1:] for a in attrs]
+        B.bin_set_tuning(B.TUNE_QUADS, quads)
+        try:
+            got = _bin(ws, 2, coords=coords, attrs=attrs)
+            out = B.alloc_outputs(attrs, ws.nx, ws.ny, ws.ops, "cuda")
+            req, keep = B.request(coords, attrs, ws.n, ws.axes, ws.bounds, ws.nx, ws.ny, ws.ops, out)
+            plan = B.bin_describe_plan(req)
+        finally:
+            B.reset_tuning()
+        assert plan.startswith("partition") and f"quads={quads - 1}" in plan, plan
+        G.assert_parity(got, ref, ws.ops, what=f"quads={quads} {name}")
+
+
 def _ws(coords, attrs, nx, ny, bounds=(0.0, 1.0, 0.0, 1.0), axes=(0, 1), ops=31):
     return synth.Workload([np.ascontiguousarray(c) for c in coords], [np.ascontiguousarray(a) for a in attrs],
                           axes=axes, bounds=bounds, nx=nx, ny=ny, ops=ops)
