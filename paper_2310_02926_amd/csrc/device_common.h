@@ -122,6 +122,11 @@ template <typename T>
 __device__ __forceinline__ T ld(const void* p, int64_t i) {
   return __builtin_nontemporal_load(static_cast<const T*>(p) + i);
 }
+// Plain (temporal) load: for data that other workgroups read soon after.
+template <typename T>
+__device__ __forceinline__ T ld_keep(const void* p, int64_t i) {
+  return static_cast<const T*>(p)[i];
+}
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));

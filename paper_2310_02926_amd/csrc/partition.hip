@@ -521,7 +521,11 @@ __global__ __launch_bounds__(1024) void part_items_batched(const PartArgs* __res
 // the concatenated runs onto the lanes 64 records at a time (a binary
 // search over the scan for the lane's run).
 // ---------------------------------------------------------------------------
-// The 4 values of quad q (16-byte loads; zeros for no quad).
+// The 4 values of quad q (16-byte loads; zeros for no quad).  Records are
+// read with plain loads: the cache lines at the ends of a run are shared
+// with the neighbouring tiles' runs, which other workgroups gather at about
+// the same time, so the lines should stay in L2 rather than be streamed
+// past it.
 template <typename AT>
 __device__ __forceinline__ void ld_quad(const void* p, uint32_t q, AT* out) {
   if (q == 0xFFFFFFFFu) {
@@ -529,7 +533,20 @@ __device__ __forceinline__ void ld_quad(const void* p, uint32_t q, AT* out) {
     for (int e = 0; e < 4; ++e) out[e] = AT(0);
     return;
   }
-  ld4v<AT, int64_t>(p, (int64_t)q * 4, out);
+  if constexpr (sizeof(AT) == 4) {
+    const f32x4 v = reinterpret_cast<const f32x4*>(p)[q];
+    out[0] = v.x;
+    out[1] = v.y;
+    out[2] = v.z;
+    out[3] = v.w;
+  } else {
+    const f64x2* d = reinterpret_cast<const f64x2*>(p) + 2 * (int64_t)q;
+    const f64x2 a = d[0], b = d[1];
+    out[0] = a.x;
+    out[1] = a.y;
+    out[2] = b.x;
+    out[3] = b.y;
+  }
 }
 
 template <typename AT, int PREC, bool QUAD>
@@ -634,7 +651,7 @@ __device__ __forceinline__ void part_bin_body(const PartArgs& a, int item) {
   #pragma unroll
         for (int u = 0; u < R; ++u) {
           u32x2 bq = {0xFFFFFFFFu, 0xFFFFFFFFu};
-          if (quad[u] != 0xFFFFFFFFu) bq = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(a.rec_bin) + quad[u]);
+          if (quad[u] != 0xFFFFFFFFu) bq = reinterpret_cast<const u32x2*>(a.rec_bin)[quad[u]];
   #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const uint32_t b = ((e < 2 ? bq.x : bq.y) >> (16 * (e & 1))) & 0xFFFFu;
@@ -734,12 +751,12 @@ __device__ __forceinline__ void part_bin_body(const PartArgs& a, int item) {
         AT v[KV][R];
   #pragma unroll
         for (int u = 0; u < R; ++u)
-          lb[u] = rec[u] != 0xFFFFFFFFu ? (int)__builtin_nontemporal_load(a.rec_bin + rec[u]) : -1;
+          lb[u] = rec[u] != 0xFFFFFFFFu ? (int)a.rec_bin[rec[u]] : -1;
   #pragma unroll
         for (int jj = 0; jj < KV; ++jj)
           if (jj < k) {
   #pragma unroll
-            for (int u = 0; u < R; ++u) v[jj][u] = rec[u] != 0xFFFFFFFFu ? ld<AT>(a.rec_val[jj], rec[u]) : AT(0);
+            for (int u = 0; u < R; ++u) v[jj][u] = rec[u] != 0xFFFFFFFFu ? ld_keep<AT>(a.rec_val[jj], rec[u]) : AT(0);
           }
   #pragma unroll
         for (int u = 0; u < R; ++u)
@@ -750,7 +767,7 @@ __device__ __forceinline__ void part_bin_body(const PartArgs& a, int item) {
         for (int jj = KV; jj < k; ++jj) {
           AT w[R];
   #pragma unroll
-          for (int u = 0; u < R; ++u) w[u] = rec[u] != 0xFFFFFFFFu ? ld<AT>(a.rec_val[jj], rec[u]) : AT(0);
+          for (int u = 0; u < R; ++u) w[u] = rec[u] != 0xFFFFFFFFu ? ld_keep<AT>(a.rec_val[jj], rec[u]) : AT(0);
           TL::template add_batch<R>(smem, a.lay, jj, lb, w);
         }
       }
