@@ -269,20 +269,20 @@ __device__ __forceinline__ void scatter_sub(const PartArgs& a, unsigned char* sm
   if (a.quads) {
     u32x2* rb = reinterpret_cast<u32x2*>(a.rec_bin + rbase);
     const u32x2* sb = reinterpret_cast<const u32x2*>(stg_b);
-    for (uint32_t p = threadIdx.x; p < nsub / 4; p += NT) rb[p] = sb[p];
+    for (uint32_t p = threadIdx.x; p < nsub / 4; p += NT) __builtin_nontemporal_store(sb[p], rb + p);
   } else {
     uint16_t* rb = a.rec_bin + rbase;
-    for (uint32_t p = threadIdx.x; p < nsub; p += NT) rb[p] = stg_b[p];
+    for (uint32_t p = threadIdx.x; p < nsub; p += NT) __builtin_nontemporal_store(stg_b[p], rb + p);
   }
   auto copy_values = [&](int jx) {
     if (a.quads) {
       constexpr uint32_t kVq = sizeof(AT) / 4;  // 16-byte units per quad of values
       u32x4* rv = reinterpret_cast<u32x4*>(static_cast<AT*>(a.rec_val[jx]) + rbase);
       const u32x4* sv = reinterpret_cast<const u32x4*>(stg_v);
-      for (uint32_t p = threadIdx.x; p < nsub / 4 * kVq; p += NT) rv[p] = sv[p];
+      for (uint32_t p = threadIdx.x; p < nsub / 4 * kVq; p += NT) __builtin_nontemporal_store(sv[p], rv + p);
     } else {
       AT* rv = static_cast<AT*>(a.rec_val[jx]) + rbase;
-      for (uint32_t p = threadIdx.x; p < nsub; p += NT) rv[p] = stg_v[p];
+      for (uint32_t p = threadIdx.x; p < nsub; p += NT) __builtin_nontemporal_store(stg_v[p], rv + p);
     }
   };
   if (k > 0) copy_values(0);
