@@ -475,7 +475,7 @@ def main():
                     help="also run one plain device copy of known size (for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     if args.workload == "batched":
         return run_batched(args)

@@ -57,7 +57,7 @@ extern "C" {
 typedef enum bin_status {
   BIN_OK = 0,
   BIN_ERR_INVALID_ARG = -1, /* an argument breaks the contract below        */
-  BIN_ERR_UNSUPPORTED = -2, /* valid request this build does not implement  */
+  BIN_ERR_UNSUPPORTED = -2, /* valid request the library does not implement */
   BIN_ERR_OOM = -3,         /* device scratch allocation failed             */
   BIN_ERR_DEVICE = -4,      /* a HIP call or enqueued kernel failed         */
   BIN_ERR_ADMISSION = -5,   /* server: request can never fit the budget     */
