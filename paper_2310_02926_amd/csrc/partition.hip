@@ -108,8 +108,10 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t* wave_t
 // the remainder (and unaligned requests) take a bounds-tested path with 4
 // particles per thread.  Three barriers per sub-chunk (two more per extra
 // attribute): the tile counters are double-buffered, and one wave scans
-// them, adds them to the slice totals and clears the other buffer.
-// LDS: cnt[2][T] | off[T] | tot[T] | (tile << 16 | local bin)[S] | values[S]
+// them, adds them to the slice totals and clears the other buffer.  With
+// quads each tile's run is padded to a multiple of 4 records (bin 0xFFFF).
+// LDS: cnt[2][T] | off[T] | tot[T] | local bin u16[S + pad_row] |
+//      values[S + pad_row] | staged run-table rows u16[T + 1][2^off_shift]
 // ---------------------------------------------------------------------------
 struct ScatterShared {
   uint32_t nsub;
