@@ -316,6 +316,15 @@ int bin_set_tuning(int32_t param, int64_t value);
  * writes a short NUL-terminated text such as "lds wg=256 ppt=8" into buf. */
 int bin_describe_plan(const bin_request* req, char* buf, size_t buflen);
 
+/* The plan bin_describe_plan gives for a device with 'cus' compute units and
+ * the given LDS bytes per workgroup and per CU, without any HIP call (for
+ * capacity planning and for tests on machines without a GPU).  MI355X:
+ * 256, 163840, 163840.  Same errors as bin_describe_plan, plus
+ * BIN_ERR_INVALID_ARG for cus < 1 or LDS sizes outside
+ * 1024 <= lds_per_block <= lds_per_cu. */
+int bin_describe_plan_on(const bin_request* req, int32_t cus, int64_t lds_per_block, int64_t lds_per_cu, char* buf,
+                         size_t buflen);
+
 /* ---- serving --------------------------------------------------------------- */
 /* A request server with continuous batching: binsrv_submit may be called
  * from any thread while earlier requests run; a dispatcher thread admits

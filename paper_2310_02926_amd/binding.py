@@ -33,7 +33,7 @@ EXPORTS = (
     "bin_graph_destroy", "bin_autotune", "bin_status_string", "bin_last_error_message",
     "bin_stream_status", "bin_release_workspace", "bin_version", "bin_timing_enable", "bin_timing_read",
     "bin_timing_report",
-    "bin_describe_plan", "bin_set_plan_override", "bin_set_tuning", "bin_copy_to_host", "binsrv_create", "binsrv_submit", "binsrv_wait", "binsrv_release",
+    "bin_describe_plan", "bin_describe_plan_on", "bin_set_plan_override", "bin_set_tuning", "bin_copy_to_host", "binsrv_create", "binsrv_submit", "binsrv_wait", "binsrv_release",
     "binsrv_get_stats", "binsrv_destroy",
 )
 
@@ -126,6 +126,7 @@ def lib() -> ctypes.CDLL:
         "bin_timing_read": (c_int, [POINTER(c_int64), POINTER(c_double)]),
         "bin_timing_report": (c_int, [c_char_p, c_size_t]),
         "bin_describe_plan": (c_int, [POINTER(Request), c_char_p, c_size_t]),
+        "bin_describe_plan_on": (c_int, [POINTER(Request), c_int32, c_int64, c_int64, c_char_p, c_size_t]),
         "bin_set_plan_override": (c_int, [c_int32, c_int32, c_int32]),
         "bin_set_tuning": (c_int, [c_int32, c_int64]),
         "bin_copy_to_host": (c_int, [c_void_p, c_void_p, c_size_t]),
@@ -508,6 +509,13 @@ class Server:
 def bin_describe_plan(req: Request) -> str:
     buf = ctypes.create_string_buffer(256)
     check(lib().bin_describe_plan(ctypes.byref(req), buf, 256))
+    return buf.value.decode()
+
+
+def bin_describe_plan_on(req: Request, cus: int = 256, lds_per_block: int = 163840, lds_per_cu: int = 163840) -> str:
+    """The plan for a device of the given size, without a GPU (MI355X by default)."""
+    buf = ctypes.create_string_buffer(512)
+    check(lib().bin_describe_plan_on(ctypes.byref(req), cus, lds_per_block, lds_per_cu, buf, 512))
     return buf.value.decode()
 
 

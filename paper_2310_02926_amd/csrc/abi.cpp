@@ -385,4 +385,27 @@ int bin_describe_plan(const bin_request* req, char* buf, size_t buflen) {
   return BIN_OK;
 }
 
+int bin_describe_plan_on(const bin_request* req, int32_t cus, int64_t lds_per_block, int64_t lds_per_cu, char* buf,
+                         size_t buflen) {
+  clear_error();
+  if (!req || !buf || buflen == 0) return fail(BIN_ERR_INVALID_ARG, "NULL request or buffer");
+  if (cus < 1 || lds_per_block < 1024 || lds_per_cu < lds_per_block)
+    return fail(BIN_ERR_INVALID_ARG, "need cus >= 1 and 1024 <= lds_per_block <= lds_per_cu");
+  int st = validate(&req->coords, &req->attrs, req->n, req->axes, req->bounds, req->nx, req->ny, req->ops,
+                    &req->out, false);
+  if (st) return st;
+  DeviceInfo dev;
+  dev.device = -1;
+  dev.cus = cus;
+  dev.lds_per_block = (size_t)lds_per_block;
+  dev.lds_per_cu = (size_t)lds_per_cu;
+  Prepared p;
+  st = prepare(*req, dev, thread_hints(), nullptr, &p);
+  if (st) return st;
+  std::string d = describe(p);
+  std::strncpy(buf, d.c_str(), buflen - 1);
+  buf[buflen - 1] = 0;
+  return BIN_OK;
+}
+
 }  // extern "C"
