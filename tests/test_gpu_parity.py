@@ -401,3 +401,19 @@ def test_unaligned_columns_take_the_narrow_load_path(strategy, dtype, shift):
     finally:
         B.bin_set_plan_override(-1, 0, 0)
     G.assert_parity(got, G.oracle(ws), 31, what=f"unaligned shift={shift}")
+
+
+def test_plan_without_gpu_matches_device_plan():
+    """bin_describe_plan_on with this device's sizes gives the plan the
+    library makes on the device (so the planner tests on the CPU test the
+    plans that run here)."""
+    from paper_2310_02926_amd import binding as B
+    props = torch.cuda.get_device_properties(0)
+    cus = props.multi_processor_count
+    lds = props.shared_memory_per_block
+    for (n, side, k) in [(1 << 27, 2048, 1), (1 << 24, 1024, 4), (1 << 24, 128, 1), (1 << 24, 64, 1), (65536, 64, 1)]:
+        coords = [torch.empty(8, device="cuda") for _ in range(2)]
+        attrs = [torch.empty(8, device="cuda") for _ in range(k)]
+        out = B.alloc_outputs(attrs, side, side, 31, "cuda")
+        req, keep = B.request(coords, attrs, n, (0, 1), (0.0, 1.0, 0.0, 1.0), side, side, 31, out)
+        assert B.bin_describe_plan(req) == B.bin_describe_plan_on(req, cus, lds, lds), (n, side, k)
