@@ -2,11 +2,14 @@
 (same generators and seeds) and in its launch configuration (automatic plan,
 a side stream, all five operations): hotspot 2^27 particles on 2048^2,
 Gaussian mixture 2^24 with four attributes on 1024^2, 64 halos 2^26 on a
-128^3 mesh.  The oracle bins the whole set in seconds, so every bin is
-compared: count/min/max bit-exact, sum/avg within 1e-5 * sum|a| (the plain
+128^3 mesh, and the batch of 256 requests (2.7e8 particles) after the
+autotuner, as one batched call and as a graph.  The oracle bins the whole
+set in seconds, so every bin is compared (for the batch: every bin of a
+seeded sample of 40 requests, the largest and smallest among them): count/min/max bit-exact, sum/avg within 1e-5 * sum|a| (the plain
 FP32 mode within its sequential error bound).  The largest relative sum error
 of each precision mode is printed beside the check."""
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -112,3 +115,80 @@ def test_full_size_workload(name, prec):
     G.assert_parity(got, ref, B.OPS_ALL, plain=(prec == "plain"), what=f"{name} {prec}")
     print(f"[error] {name} {prec}: largest |sum - oracle| / sum|a| = {_max_rel_sum_error(got, ref):.3e}",
           flush=True)
+
+
+def _to_np(out):
+    res = {}
+    if "count" in out:
+        res["count"] = out["count"].cpu().numpy().view(np.uint32).astype(np.int64)
+    for key in ("sum", "min", "max", "avg"):
+        if key in out:
+            res[key] = [t.cpu().numpy() for t in out[key]]
+    return res
+
+
+class _Batch:
+    """The 256-request set, uploaded and tuned as the benchmark does; the
+    oracle's results for a seeded sample of it."""
+
+    def __init__(self):
+        from paper_2310_02926_amd import binding as B
+        specs = synth.batch_specs(256, seed=0, n_hi=1e7)
+        with ThreadPoolExecutor(8) as ex:  # each instance has its own generator
+            self.wss = list(ex.map(synth.instance, specs))
+        dev = torch.device("cuda:0")
+        self.reqs = []
+        for ws in self.wss:
+            coords, attrs = G.to_device(ws)
+            out = B.alloc_outputs(attrs, ws.nx, ws.ny, ws.ops, dev)
+            self.reqs.append(dict(coords=coords, attrs=attrs, n=ws.n, axes=ws.axes, bounds=ws.bounds, nx=ws.nx,
+                                  ny=ws.ny, ops=ws.ops, out=out))
+        torch.cuda.synchronize()
+        B.bin_autotune(self.reqs)
+        ns = np.array([ws.n for ws in self.wss])
+        rng = np.random.default_rng(7)
+        pick = set(rng.choice(len(ns), 38, replace=False).tolist()) | {int(ns.argmax()), int(ns.argmin())}
+        self.sample = sorted(pick)
+        self.refs = {i: G.oracle(self.wss[i]) for i in self.sample}
+
+    def clear_outputs(self):
+        for r in self.reqs:
+            for key, val in r["out"].items():
+                for t in (val if isinstance(val, list) else [val]):
+                    t.fill_(7)
+        torch.cuda.synchronize()
+
+
+def _batch():
+    if "batch" not in _CACHE:
+        _CACHE.clear()
+        _case("generating the 256-request batch, autotuning, binning a sample with the oracle")
+        _CACHE["batch"] = _Batch()
+    return _CACHE["batch"]
+
+
+@pytest.mark.parametrize("mode", ["batched", "graph"])
+def test_full_size_batch(mode):
+    from paper_2310_02926_amd import binding as B
+    w = _batch()
+    total = sum(r["n"] for r in w.reqs)
+    _case(f"full batch of {len(w.reqs)} requests, {total} particles, {mode}")
+    w.clear_outputs()
+    stream = torch.cuda.Stream()
+    if mode == "batched":
+        batch = B.Batch(w.reqs)
+        for _ in range(2):
+            batch.launch(stream)
+    else:
+        graph = B.BinGraph(w.reqs)
+        try:
+            for _ in range(2):
+                graph.launch(stream)
+            stream.synchronize()
+        finally:
+            graph.destroy()
+    stream.synchronize()
+    for i in w.sample:
+        ws = w.wss[i]
+        G.assert_parity(_to_np(w.reqs[i]["out"]), w.refs[i], ws.ops,
+                        what=f"{mode} request {i} (n={ws.n}, {ws.nx}^2, k={ws.k})")
