@@ -353,6 +353,10 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints_
     c.bin_block = 2 * tile_lds <= dev.lds_per_cu ? 512 : 1024;
     set_part_blocks(a, nt, ppt);
     a.quads = (hints.quads ? hints.quads == 2 : use_quads(nk, p->attr_f64, T, (int64_t)nt * ppt)) ? 1 : 0;
+    // Each tile's record total, padding included, is counted in 32 bits;
+    // with up to 3 padding records per sub-chunk, quads only while n plus
+    // that padding stays below 2^32 (without padding the total is <= n).
+    if (a.quads && (uint64_t)a.n + 3ull * (uint64_t)a.nwg * (uint64_t)a.nbpw > 0xFFFFFFFFull) a.quads = 0;
     a.pad_row = a.quads ? part_pad_row(T, (int64_t)nt * ppt) : 0;
     c.scatter_lds = set_off_stage(a, sc, lds_budget - kScatterStatic);
     set_part_items(a, cus);

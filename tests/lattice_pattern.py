@@ -1,0 +1,47 @@
+"""A structured particle set whose binned result has a closed form, for
+checks at sizes the oracle cannot bin in a test (up to 2^32 - 1 particles).
+
+Particle i on an nx by ny mesh over [0, 1]^2 (nx, ny powers of two, so the
+cell centres are exact in binary32) sits at the centre of cell
+(i mod nx, (i div nx) mod ny), so its bin is i mod B with B = nx * ny.
+Attribute j of particle i is ((i div B) + j) mod 3 - 1, one of -1, 0, 1.
+Bin b holds the particles b + B * m for m < c_b, c_b = n div B + (b < n mod B),
+and its attribute j takes the values ((m + j) mod 3) - 1 for those m, so
+count, sum, min, max and average depend only on c_b and j.  The closed form
+is pinned to the oracle on small sizes by a CPU test."""
+import numpy as np
+
+
+def columns(idx, nx, ny, k, xp_float):
+    """Coordinates and attributes of particles idx (an integer array of
+    numpy or torch); xp_float casts an integer array to binary32."""
+    B = nx * ny
+    x = (xp_float(idx % nx) + 0.5) / nx
+    y = (xp_float((idx // nx) % ny) + 0.5) / ny
+    attrs = [xp_float(((idx // B) + j) % 3 - 1) for j in range(k)]
+    return x, y, attrs
+
+
+def expected(n, nx, ny, k):
+    """Per-bin results as the oracle returns them ([ny, nx] arrays)."""
+    B = nx * ny
+    q, r = divmod(n, B)
+    cnt = np.full(B, q, np.int64)
+    cnt[:r] += 1
+    res = {"count": cnt.reshape(ny, nx), "sum": [], "min": [], "max": [], "avg": [], "abs_sum": []}
+    for j in range(k):
+        per = {}
+        for c in {q, q + 1} if r else {q}:
+            vals = [((m + j) % 3) - 1 for m in range(min(c, 3))]
+            full = c // 3  # each full cycle of three values sums to 0 and has |a| sum 2
+            tail = [((m + j) % 3) - 1 for m in range(3 * full, c)]
+            s = float(sum(tail))
+            a = float(2 * full + sum(abs(v) for v in tail))
+            mn = float(min(vals)) if c else np.inf
+            mx = float(max(vals)) if c else -np.inf
+            per[c] = (s, mn, mx, s / c if c else np.nan, a)
+        lo, hi = per[q], per.get(q + 1, per[q])
+        cols = [np.where(cnt == q + 1, hi[f], lo[f]) for f in range(5)]
+        for key, col in zip(("sum", "min", "max", "avg", "abs_sum"), cols):
+            res[key].append(col.reshape(ny, nx))
+    return res

@@ -1,0 +1,85 @@
+"""GPU results at the largest particle counts the boundary accepts (n up to
+2^32 - 1, past every 32-bit signed index), checked bin by bin against the
+closed form of tests/lattice_pattern.py (pinned to the oracle on the CPU).
+Each case runs the automatic plan and asserts which strategy it took: the
+tile partition with the quad gather (the largest n whose padded tile totals
+fit 32 bits), the partition with the record gather (at n = 2^32 - 1, and
+with four attributes), and the whole grid in LDS."""
+import sys
+
+import numpy as np
+import pytest
+
+from tests import gpu_check as G
+from tests import lattice_pattern as L
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(600)]
+torch = pytest.importorskip("torch")
+
+CHUNK = 1 << 27
+
+
+def _case(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _fill(n, nx, ny, k):
+    """The lattice columns built on the device, CHUNK particles at a time."""
+    dev = torch.device("cuda:0")
+    x = torch.empty(n, dtype=torch.float32, device=dev)
+    y = torch.empty(n, dtype=torch.float32, device=dev)
+    attrs = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(k)]
+    for s in range(0, n, CHUNK):
+        e = min(n, s + CHUNK)
+        idx = torch.arange(s, e, dtype=torch.int64, device=dev)
+        cx, cy, ca = L.columns(idx, nx, ny, k, lambda v: v.to(torch.float32))
+        x[s:e] = cx
+        y[s:e] = cy
+        for j in range(k):
+            attrs[j][s:e] = ca[j]
+        del idx, cx, cy, ca
+    torch.cuda.synchronize()
+    return [x, y], attrs
+
+
+@pytest.mark.parametrize("n,side,k,kind,quads", [
+    pytest.param((1 << 32) - (1 << 21) + 1, 2048, 1, "partition", "1", id="partition-quads-n=2^32-2^21+1"),
+    pytest.param(0xFFFFFFFF, 2048, 1, "partition", "0", id="partition-records-n=2^32-1"),
+    pytest.param((1 << 31) + 4097, 1024, 4, "partition", "0", id="partition-records-k4-n=2^31+4097"),
+    pytest.param(0xFFFFFFFF, 64, 1, "lds", None, id="lds-n=2^32-1"),
+])
+def test_largest_particle_counts(n, side, k, kind, quads):
+    from paper_2310_02926_amd import binding as B
+    need = n * (10 + 8 * k) + (8 << 30)  # columns, records (2-byte bin, values) and slack
+    free, _ = torch.cuda.mem_get_info()
+    if free < need:
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of device memory, {free / 2**30:.0f} GiB free")
+    _case(f"largest counts n={n} grid={side}^2 k={k} expected plan={kind}")
+    B.bin_set_plan_override(-1, 0, 0)
+    coords, attrs = _fill(n, side, side, k)
+    out = B.alloc_outputs(attrs, side, side, B.OPS_ALL, torch.device("cuda:0"))
+    bounds = (0.0, 1.0, 0.0, 1.0)
+    req, keep = B.request(coords, attrs, n, (0, 1), bounds, side, side, B.OPS_ALL,
+                          {key: (v.view(-1) if not isinstance(v, list) else [t.view(-1) for t in v])
+                           for key, v in out.items()})
+    plan = B.bin_describe_plan(req)
+    _case(f"plan: {plan}")
+    assert plan.split()[0] == kind
+    if quads is not None:
+        assert f"quads={quads}" in plan
+    stream = torch.cuda.Stream()
+    try:
+        B.bin_particles(coords, attrs, n, (0, 1), bounds, side, side, B.OPS_ALL, out, stream=stream)
+        stream.synchronize()
+        got = {"count": out["count"].cpu().numpy().view(np.uint32).astype(np.int64)}
+        for key in ("sum", "min", "max", "avg"):
+            got[key] = [t.cpu().numpy() for t in out[key]]
+    finally:
+        del coords, attrs, out, req, keep
+        torch.cuda.synchronize()
+        B.bin_release_workspace()
+        torch.cuda.empty_cache()
+    exp = L.expected(n, side, side, k)
+    assert int(got["count"].sum()) == n
+    G.assert_parity(got, exp, B.OPS_ALL, what=f"n={n} {side}^2 k={k}")

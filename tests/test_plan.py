@@ -65,6 +65,17 @@ def test_tiles_not_below_256_bins():
     assert int(plan(1 << 24, 512, 512, cus=64)[1]["tile_bins"]) > 512
 
 
+def test_quads_only_while_padded_tile_totals_fit_32_bits():
+    """A tile's record total, with up to 3 padding records per sub-chunk, is
+    a 32-bit count: at the largest n the record gather is taken."""
+    kind, f = plan(0xFFFFFFFF, 2048, 2048)
+    assert kind == "partition" and f["quads"] == "0"
+    rows = int(f["wg"]) * int(f["blocks"])
+    n = 0xFFFFFFFF - 3 * rows
+    assert plan(n, 2048, 2048)[1]["quads"] == "1"
+    assert plan(n + 1, 2048, 2048)[1]["quads"] == "0"
+
+
 def test_lds_strategy_at_most_1024_threads_per_cu():
     kind, f = plan(1 << 24, 64, 64)
     assert kind == "lds" and f["block"] == "1024" and f["grid"] == "256"
