@@ -11,6 +11,11 @@ count, sum, min, max and average depend only on c_b and j.  The closed form
 is pinned to the oracle on small sizes by a CPU test."""
 import numpy as np
 
+# The largest grids the boundary accepts (nx * ny <= 2^31 - 1), binned on the
+# GPU with the sparse pattern: (n, nx, ny, binary64 coordinates).
+MAX_GRID_CASES = [((1 << 26) + 77, 1 << 15, 1 << 15, False), ((1 << 26) + 77, (1 << 31) - 1, 1, True)]
+MAX_GRID_IDS = ["2^15x2^15-f32", "(2^31-1)x1-f64"]
+
 
 def columns(idx, nx, ny, k, xp_float):
     """Coordinates and attributes of particles idx (an integer array of
@@ -43,5 +48,42 @@ def expected(n, nx, ny, k):
         lo, hi = per[q], per.get(q + 1, per[q])
         cols = [np.where(cnt == q + 1, hi[f], lo[f]) for f in range(5)]
         for key, col in zip(("sum", "min", "max", "avg", "abs_sum"), cols):
+            res[key].append(col.reshape(ny, nx))
+    return res
+
+
+def sparse_cells(idx, n, nx, ny):
+    """Flat cell of particle i in the sparse pattern: (i * nx * ny) div n."""
+    return (idx * (nx * ny)) // n
+
+
+def sparse_columns(idx, n, nx, ny, k, xp_float):
+    """A second pattern, spread evenly over the whole grid: particle i
+    (i < n <= nx * ny) alone at the centre of flat cell (i * nx * ny) div n,
+    so the used bins reach the last row of the largest grids.  Attribute j
+    of particle i is (i + j) mod 3 - 1.  xp_float must hold c mod nx + 0.5
+    and c div nx + 0.5 exactly (binary32 up to 2^23 cells per axis, else
+    binary64)."""
+    c = sparse_cells(idx, n, nx, ny)
+    x = (xp_float(c % nx) + 0.5) / nx
+    y = (xp_float(c // nx) + 0.5) / ny
+    attrs = [xp_float((idx + j) % 3 - 1) for j in range(k)]
+    return x, y, attrs
+
+
+def sparse_expected(n, nx, ny, k):
+    """Per-bin results of sparse_columns as the oracle returns them (small
+    grids only: full [ny, nx] arrays)."""
+    B = nx * ny
+    idx = np.arange(n, dtype=np.int64)
+    bins = sparse_cells(idx, n, nx, ny)
+    cnt = np.zeros(B, np.int64)
+    cnt[bins] = 1
+    res = {"count": cnt.reshape(ny, nx), "sum": [], "min": [], "max": [], "avg": [], "abs_sum": []}
+    for j in range(k):
+        v = ((idx + j) % 3 - 1).astype(np.float64)
+        for key, empty in (("sum", 0.0), ("min", np.inf), ("max", -np.inf), ("avg", np.nan), ("abs_sum", 0.0)):
+            col = np.full(B, empty)
+            col[bins] = np.abs(v) if key == "abs_sum" else v
             res[key].append(col.reshape(ny, nx))
     return res

@@ -83,3 +83,54 @@ def test_largest_particle_counts(n, side, k, kind, quads):
     exp = L.expected(n, side, side, k)
     assert int(got["count"].sum()) == n
     G.assert_parity(got, exp, B.OPS_ALL, what=f"n={n} {side}^2 k={k}")
+
+
+@pytest.mark.parametrize("n,nx,ny,f64", L.MAX_GRID_CASES, ids=L.MAX_GRID_IDS)
+def test_largest_grids(n, nx, ny, f64):
+    """Grids of 2^30 and 2^31 - 1 bins (global atomics), the sparse pattern
+    reaching the last row: every used bin holds its one particle, every
+    other bin the empty-bin values.  Checked on the device (the outputs are
+    tens of GB)."""
+    from paper_2310_02926_amd import binding as B
+    nb = nx * ny
+    need = nb * 28 + n * 24 + (8 << 30)  # outputs, columns and slack
+    free, _ = torch.cuda.mem_get_info()
+    if free < need:
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of device memory, {free / 2**30:.0f} GiB free")
+    _case(f"largest grids n={n} grid={nx}x{ny} f64 coords={f64}")
+    B.bin_set_plan_override(-1, 0, 0)
+    dev = torch.device("cuda:0")
+    ct = torch.float64 if f64 else torch.float32
+    idx = torch.arange(n, dtype=torch.int64, device=dev)
+    x, y, attrs = L.sparse_columns(idx, n, nx, ny, 1, lambda v: v.to(ct))
+    attrs = [a.to(torch.float32) for a in attrs]
+    out = B.alloc_outputs(attrs, nx, ny, B.OPS_ALL, dev)
+    bounds = (0.0, 1.0, 0.0, 1.0)
+    req, keep = B.request([x, y], attrs, n, (0, 1), bounds, nx, ny, B.OPS_ALL,
+                          {key: (v.view(-1) if not isinstance(v, list) else [t.view(-1) for t in v])
+                           for key, v in out.items()})
+    plan = B.bin_describe_plan(req)
+    _case(f"plan: {plan}")
+    assert plan.split()[0] == "global"
+    stream = torch.cuda.Stream()
+    try:
+        B.bin_particles([x, y], attrs, n, (0, 1), bounds, nx, ny, B.OPS_ALL, out, stream=stream)
+        stream.synchronize()
+        cells = L.sparse_cells(idx, n, nx, ny)
+        v = attrs[0]
+        cnt = out["count"].view(-1)
+        assert int(torch.count_nonzero(cnt)) == n
+        assert bool((cnt[cells] == 1).all())
+        s, mn, mx, av = (out[key][0].view(-1) for key in ("sum", "min", "max", "avg"))
+        assert bool((s[cells] == v.to(s.dtype)).all())
+        assert int(torch.count_nonzero(s)) == int(torch.count_nonzero(v))
+        assert bool((mn[cells] == v).all()) and bool((mx[cells] == v).all())
+        assert int((mn == float("inf")).sum()) == nb - n
+        assert int((mx == float("-inf")).sum()) == nb - n
+        assert bool((av[cells] == v.to(av.dtype)).all())
+        assert int(torch.isnan(av).sum()) == nb - n
+    finally:
+        del x, y, attrs, out, req, keep, idx
+        torch.cuda.synchronize()
+        B.bin_release_workspace()
+        torch.cuda.empty_cache()
