@@ -87,3 +87,24 @@ def sparse_expected(n, nx, ny, k):
             col[bins] = np.abs(v) if key == "abs_sum" else v
             res[key].append(col.reshape(ny, nx))
     return res
+
+
+def columns3(idx, nx, ny, nz, k, xp_float):
+    """The lattice on an nx by ny by nz mesh (powers of two): particle i at
+    the centre of cell (i mod nx, (i div nx) mod ny, (i div nx ny) mod nz),
+    flat bin i mod (nx ny nz), attribute j = ((i div nx ny nz) + j) mod 3 - 1:
+    the results are those of the two-axis lattice with nx * ny * nz bins."""
+    B = nx * ny * nz
+    x = (xp_float(idx % nx) + 0.5) / nx
+    y = (xp_float((idx // nx) % ny) + 0.5) / ny
+    z = (xp_float((idx // (nx * ny)) % nz) + 0.5) / nz
+    attrs = [xp_float(((idx // B) + j) % 3 - 1) for j in range(k)]
+    return x, y, z, attrs
+
+
+def expected3(n, nx, ny, nz, k):
+    """Per-bin results of columns3 shaped [nz, ny, nx]."""
+    res = expected(n, nx, ny * nz, k)
+    shape = (nz, ny, nx)
+    return {key: (val.reshape(shape) if not isinstance(val, list) else [v.reshape(shape) for v in val])
+            for key, val in res.items()}

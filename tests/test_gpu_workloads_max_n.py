@@ -134,3 +134,44 @@ def test_largest_grids(n, nx, ny, f64):
         torch.cuda.synchronize()
         B.bin_release_workspace()
         torch.cuda.empty_cache()
+
+
+def test_largest_particle_count_three_axes():
+    """n = 2^32 - 1 on a 64^3 mesh: the fold's composite column and the
+    folded two-axis binning at the largest n, against the closed form."""
+    from paper_2310_02926_amd import binding as B
+    n, d = 0xFFFFFFFF, 64
+    need = n * 26 + (8 << 30)  # four columns, the composite column, records, slack
+    free, _ = torch.cuda.mem_get_info()
+    if free < need:
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of device memory, {free / 2**30:.0f} GiB free")
+    _case(f"largest count, three axes: n={n} mesh={d}^3")
+    B.bin_set_plan_override(-1, 0, 0)
+    dev = torch.device("cuda:0")
+    cols = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(4)]
+    for s in range(0, n, CHUNK):
+        e = min(n, s + CHUNK)
+        idx = torch.arange(s, e, dtype=torch.int64, device=dev)
+        x, y, z, attrs = L.columns3(idx, d, d, d, 1, lambda v: v.to(torch.float32))
+        for c, v in zip(cols, (x, y, z, attrs[0])):
+            c[s:e] = v
+        del idx, x, y, z, attrs
+    torch.cuda.synchronize()
+    dims = (d, d, d)
+    out = B.alloc_outputs_nd(cols[3:], dims, B.OPS_ALL, dev)
+    stream = torch.cuda.Stream()
+    try:
+        B.bin_particles_nd(cols[:3], cols[3:], n, (0, 1, 2), (0.0, 1.0) * 3, dims, B.OPS_ALL, out, stream=stream)
+        stream.synchronize()
+        got = {"count": out["count"].cpu().numpy().view(np.uint32).astype(np.int64)}
+        for key in ("sum", "min", "max", "avg"):
+            got[key] = [t.cpu().numpy() for t in out[key]]
+    finally:
+        del cols, out
+        torch.cuda.synchronize()
+        B.bin_release_workspace()
+        torch.cuda.empty_cache()
+    exp = L.expected3(n, d, d, d, 1)
+    assert got["count"].shape == (d, d, d)
+    assert int(got["count"].sum()) == n
+    G.assert_parity(got, exp, B.OPS_ALL, what=f"three axes n={n} {d}^3")

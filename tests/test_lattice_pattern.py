@@ -49,3 +49,15 @@ def test_sparse_pattern_bins_on_largest_grids(n, nx, ny, f64):
     assert np.array_equal(bins, L.sparse_cells(idx, n, nx, ny))
     assert np.all(np.diff(bins) > 0)  # one particle per used cell
     assert bins[-1] >= nx * ny - nx  # the last row is used
+
+
+@pytest.mark.parametrize("n,nx,ny,nz,k", [(0, 4, 2, 8, 1), (37, 4, 2, 8, 2), (64, 4, 2, 8, 1), (5000, 8, 16, 4, 3)])
+def test_three_axis_closed_form_equals_oracle(n, nx, ny, nz, k):
+    idx = np.arange(n, dtype=np.int64)
+    x, y, z, attrs = L.columns3(idx, nx, ny, nz, k, lambda v: v.astype(np.float32))
+    ref = orc.bin_particles_nd([x, y, z], attrs, (0, 1, 2), (0.0, 1.0) * 3, (nx, ny, nz))
+    exp = L.expected3(n, nx, ny, nz, k)
+    assert np.array_equal(ref["count"], exp["count"])
+    for key in ("sum", "min", "max", "avg", "abs_sum"):
+        for j in range(k):
+            assert np.array_equal(ref[key][j], exp[key][j], equal_nan=True), (key, j)
