@@ -175,3 +175,42 @@ def test_largest_particle_count_three_axes():
     assert got["count"].shape == (d, d, d)
     assert int(got["count"].sum()) == n
     G.assert_parity(got, exp, B.OPS_ALL, what=f"three axes n={n} {d}^3")
+
+
+def test_largest_particle_counts_in_one_batch():
+    """One batched call holding a partition request at n = 2^31 + 4097
+    (1024^2), a whole-grid-in-LDS request at n = 2^32 - 1 (64^2) and a small
+    ragged one with two attributes (256^2): each against its closed form."""
+    from paper_2310_02926_amd import binding as B
+    cases = [((1 << 31) + 4097, 1024, 1), (0xFFFFFFFF, 64, 1), (100_003, 256, 2)]
+    need = sum(n * (12 + 4 * k) for n, _, k in cases) + (8 << 30)  # columns, records, slack
+    free, _ = torch.cuda.mem_get_info()
+    if free < need:
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of device memory, {free / 2**30:.0f} GiB free")
+    _case(f"largest counts in one batch: {cases}")
+    B.bin_set_plan_override(-1, 0, 0)
+    dev = torch.device("cuda:0")
+    reqs = []
+    for n, side, k in cases:
+        coords, attrs = _fill(n, side, side, k)
+        out = B.alloc_outputs(attrs, side, side, B.OPS_ALL, dev)
+        reqs.append(dict(coords=coords, attrs=attrs, n=n, axes=(0, 1), bounds=(0.0, 1.0, 0.0, 1.0), nx=side,
+                         ny=side, ops=B.OPS_ALL, out=out))
+    stream = torch.cuda.Stream()
+    gots = []
+    try:
+        B.bin_particles_batched(reqs, stream=stream)
+        stream.synchronize()
+        for r in reqs:
+            got = {"count": r["out"]["count"].cpu().numpy().view(np.uint32).astype(np.int64)}
+            for key in ("sum", "min", "max", "avg"):
+                got[key] = [t.cpu().numpy() for t in r["out"][key]]
+            gots.append(got)
+    finally:
+        del reqs
+        torch.cuda.synchronize()
+        B.bin_release_workspace()
+        torch.cuda.empty_cache()
+    for (n, side, k), got in zip(cases, gots):
+        assert int(got["count"].sum()) == n
+        G.assert_parity(got, L.expected(n, side, side, k), B.OPS_ALL, what=f"batched n={n} {side}^2 k={k}")
