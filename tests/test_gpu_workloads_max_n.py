@@ -214,3 +214,38 @@ def test_largest_particle_counts_in_one_batch():
     for (n, side, k), got in zip(cases, gots):
         assert int(got["count"].sum()) == n
         G.assert_parity(got, L.expected(n, side, side, k), B.OPS_ALL, what=f"batched n={n} {side}^2 k={k}")
+
+
+def test_largest_particle_count_async():
+    """The asynchronous in situ mode at n = 2^32 - 1 (64^2): the deep copy
+    is taken in the source stream's order, the source columns are then
+    overwritten on that stream, and the grids still hold the lattice's
+    closed form."""
+    from paper_2310_02926_amd import binding as B
+    n, side = 0xFFFFFFFF, 64
+    need = n * 24 + (8 << 30)  # columns and their staged copy, slack
+    free, _ = torch.cuda.mem_get_info()
+    if free < need:
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of device memory, {free / 2**30:.0f} GiB free")
+    _case(f"largest count, asynchronous mode: n={n} grid={side}^2")
+    B.bin_set_plan_override(-1, 0, 0)
+    coords, attrs = _fill(n, side, side, 1)
+    out = B.alloc_outputs(attrs, side, side, B.OPS_ALL, torch.device("cuda:0"))
+    src, bs = torch.cuda.Stream(), torch.cuda.Stream()
+    try:
+        with torch.cuda.stream(src):
+            B.bin_particles_async(coords, attrs, n, (0, 1), (0.0, 1.0, 0.0, 1.0), side, side, B.OPS_ALL, out,
+                                  src_stream=src, bin_stream=bs)
+            coords[0].fill_(2.0)  # after the copy in src's order: every particle outside
+            attrs[0].fill_(5.0)
+        torch.cuda.synchronize()
+        got = {"count": out["count"].cpu().numpy().view(np.uint32).astype(np.int64)}
+        for key in ("sum", "min", "max", "avg"):
+            got[key] = [t.cpu().numpy() for t in out[key]]
+    finally:
+        del coords, attrs, out
+        torch.cuda.synchronize()
+        B.bin_release_workspace()
+        torch.cuda.empty_cache()
+    assert int(got["count"].sum()) == n
+    G.assert_parity(got, L.expected(n, side, side, 1), B.OPS_ALL, what=f"async n={n} {side}^2")
