@@ -43,19 +43,23 @@ def _fill(n, nx, ny, k):
     return [x, y], attrs
 
 
-@pytest.mark.parametrize("n,side,k,kind,quads", [
-    pytest.param((1 << 32) - (1 << 21) + 1, 2048, 1, "partition", "1", id="partition-quads-n=2^32-2^21+1"),
-    pytest.param(0xFFFFFFFF, 2048, 1, "partition", "0", id="partition-records-n=2^32-1"),
-    pytest.param((1 << 31) + 4097, 1024, 4, "partition", "0", id="partition-records-k4-n=2^31+4097"),
-    pytest.param(0xFFFFFFFF, 64, 1, "lds", None, id="lds-n=2^32-1"),
+@pytest.mark.parametrize("n,side,k,kind,quads,auto", [
+    pytest.param((1 << 32) - (1 << 21) + 1, 2048, 1, "partition", "1", False, id="partition-quads-n=2^32-2^21+1"),
+    pytest.param(0xFFFFFFFF, 2048, 1, "partition", "0", False, id="partition-records-n=2^32-1"),
+    pytest.param((1 << 31) + 4097, 1024, 4, "partition", "0", False, id="partition-records-k4-n=2^31+4097"),
+    pytest.param(0xFFFFFFFF, 64, 1, "lds", None, False, id="lds-n=2^32-1"),
+    pytest.param((1 << 32) - (1 << 21) + 1, 2048, 1, "partition", "1", True, id="partition-quads-auto-bounds"),
+    pytest.param(0xFFFFFFFF, 64, 1, "lds", None, True, id="lds-auto-bounds-n=2^32-1"),
 ])
-def test_largest_particle_counts(n, side, k, kind, quads):
+def test_largest_particle_counts(n, side, k, kind, quads, auto):
+    """auto: bounds from the data (every cell centre occurs, so the closed
+    form still holds)."""
     from paper_2310_02926_amd import binding as B
     need = n * (10 + 8 * k) + (8 << 30)  # columns, records (2-byte bin, values) and slack
     free, _ = torch.cuda.mem_get_info()
     if free < need:
         pytest.skip(f"needs {need / 2**30:.0f} GiB of device memory, {free / 2**30:.0f} GiB free")
-    _case(f"largest counts n={n} grid={side}^2 k={k} expected plan={kind}")
+    _case(f"largest counts n={n} grid={side}^2 k={k} auto bounds={auto} expected plan={kind}")
     B.bin_set_plan_override(-1, 0, 0)
     coords, attrs = _fill(n, side, side, k)
     out = B.alloc_outputs(attrs, side, side, B.OPS_ALL, torch.device("cuda:0"))
@@ -70,7 +74,8 @@ def test_largest_particle_counts(n, side, k, kind, quads):
         assert f"quads={quads}" in plan
     stream = torch.cuda.Stream()
     try:
-        B.bin_particles(coords, attrs, n, (0, 1), bounds, side, side, B.OPS_ALL, out, stream=stream)
+        B.bin_particles(coords, attrs, n, (0, 1), None if auto else bounds, side, side, B.OPS_ALL, out,
+                        stream=stream)
         stream.synchronize()
         got = {"count": out["count"].cpu().numpy().view(np.uint32).astype(np.int64)}
         for key in ("sum", "min", "max", "avg"):

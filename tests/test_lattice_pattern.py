@@ -61,3 +61,19 @@ def test_three_axis_closed_form_equals_oracle(n, nx, ny, nz, k):
     for key in ("sum", "min", "max", "avg", "abs_sum"):
         for j in range(k):
             assert np.array_equal(ref[key][j], exp[key][j], equal_nan=True), (key, j)
+
+
+@pytest.mark.parametrize("n,nx,ny,k", [(32, 8, 4, 1), (97, 8, 4, 4), (1000, 16, 16, 1), (3 * 64 + 2, 64, 1, 2),
+                                       (70_001, 64, 32, 3), (5000, 2048, 2, 1)])
+def test_closed_form_with_bounds_from_the_data(n, nx, ny, k):
+    """With n >= nx * ny every cell centre occurs, the bounds from the data
+    run from the first centre to the last, and each particle keeps its cell
+    (the last centre sits on the closed upper edge): the closed form holds."""
+    idx = np.arange(n, dtype=np.int64)
+    x, y, attrs = L.columns(idx, nx, ny, k, lambda v: v.astype(np.float32))
+    ref = orc.bin_particles([x, y], attrs, (0, 1), None, nx, ny)
+    exp = L.expected(n, nx, ny, k)
+    assert np.array_equal(ref["count"], exp["count"])
+    for key in ("sum", "min", "max", "avg", "abs_sum"):
+        for j in range(k):
+            assert np.array_equal(ref[key][j], exp[key][j], equal_nan=True), (key, j)
