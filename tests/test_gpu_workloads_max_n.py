@@ -1,10 +1,15 @@
-"""GPU results at the largest particle counts the boundary accepts (n up to
-2^32 - 1, past every 32-bit signed index), checked bin by bin against the
-closed form of tests/lattice_pattern.py (pinned to the oracle on the CPU).
-Each case runs the automatic plan and asserts which strategy it took: the
-tile partition with the quad gather (the largest n whose padded tile totals
-fit 32 bits), the partition with the record gather (at n = 2^32 - 1, and
-with four attributes), and the whole grid in LDS."""
+"""GPU results at the largest sizes the boundary accepts, checked bin by bin
+against the closed forms of tests/lattice_pattern.py (pinned to the oracle
+on the CPU).
+
+- Particle counts up to 2^32 - 1, past every 32-bit signed index, with the
+  automatic plan and the strategy it takes asserted: the tile partition with
+  the quad gather (the largest n whose padded tile totals fit 32 bits), the
+  partition with the record gather (at n = 2^32 - 1, and with four
+  attributes), the whole grid in LDS; bounds given and from the data.
+- Grids of 2^30 and 2^31 - 1 bins (global atomics).
+- n = 2^32 - 1 on a three-axis mesh, in one batched call, and in the
+  asynchronous mode."""
 import sys
 
 import numpy as np
