@@ -411,7 +411,8 @@ def test_plan_without_gpu_matches_device_plan():
     props = torch.cuda.get_device_properties(0)
     cus = props.multi_processor_count
     lds = props.shared_memory_per_block
-    for (n, side, k) in [(1 << 27, 2048, 1), (1 << 24, 1024, 4), (1 << 24, 128, 1), (1 << 24, 64, 1), (65536, 64, 1)]:
+    for (n, side, k) in [(1 << 27, 2048, 1), (1 << 24, 1024, 4), (1 << 24, 128, 1), (1 << 24, 64, 1), (65536, 64, 1),
+                         (0xFFFFFFFF, 2048, 1), ((1 << 32) - (1 << 21) + 1, 2048, 1)]:
         coords = [torch.empty(8, device="cuda") for _ in range(2)]
         attrs = [torch.empty(8, device="cuda") for _ in range(k)]
         out = B.alloc_outputs(attrs, side, side, 31, "cuda")
