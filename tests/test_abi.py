@@ -199,3 +199,42 @@ def test_nd_rejects_before_any_hip_call():
     assert ei.value.status == B.BIN_ERR_INVALID_ARG
     L = B.lib()
     assert L.bin_particles_nd(None, None, 0, 3, None, None, None, 1, None, None) == B.BIN_ERR_INVALID_ARG
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built library every entry point raises: there is no
+    fallback path."""
+    monkeypatch.setattr(B, "_lib", None)
+    monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "libbinning.so"))
+    with pytest.raises(RuntimeError, match="is missing"):
+        B.lib()
+    with pytest.raises(RuntimeError, match="is missing"):
+        B.bin_version()
+    with pytest.raises(RuntimeError, match="is missing"):
+        B.bin_particles([0x1000, 0x2000], [0x3000], 10, (0, 1), (0.0, 1.0, 0.0, 1.0), 4, 4, B.COUNT,
+                        {"count": 0x4000}, coord_dtype=B.BIN_F32, attr_dtype=B.BIN_F32)
+
+
+def test_product_path_never_reaches_the_oracle():
+    """The package (Python and native sources) imports, loads and calls
+    nothing under oracle/, and importing it leaves the oracle unloaded."""
+    import ast
+    import subprocess
+    import sys
+    pkg = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2310_02926_amd")
+    for name in os.listdir(pkg):
+        if name.endswith(".py"):
+            tree = ast.parse(open(os.path.join(pkg, name)).read())
+            for node in ast.walk(tree):
+                if isinstance(node, ast.Import):
+                    assert not any(a.name.split(".")[0] == "oracle" for a in node.names), name
+                elif isinstance(node, ast.ImportFrom):
+                    assert (node.module or "").split(".")[0] != "oracle", name
+    csrc = os.path.join(pkg, "csrc")
+    for name in os.listdir(csrc):
+        text = open(os.path.join(csrc, name), errors="replace").read()
+        assert "oracle" not in text, name
+    code = ("import sys; import paper_2310_02926_amd.binding, paper_2310_02926_amd.synth; "
+            "print(any(m == 'oracle' or m.startswith('oracle.') for m in sys.modules))")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=os.path.dirname(pkg))
+    assert out.returncode == 0 and out.stdout.strip() == "False", out.stderr
