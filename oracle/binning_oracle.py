@@ -33,8 +33,9 @@ the HIP path) are:
 * R9 bounds taken from the data (``bounds=None``): per axis the minimum and
   maximum over the finite coordinate values; with the closed upper edge the
   extreme particles land in the first and last cell.  A zero-extent axis
-  (all finite values equal) puts them all in its first cell; an axis with
-  no finite value leaves every bin empty.
+  (all finite values equal) puts them all in its first cell, as does an
+  axis whose extent ``hi - lo`` or scale ``nbins / (hi - lo)`` is not finite
+  in binary64; an axis with no finite value leaves every bin empty.
 
 Parity pins: brute force (exact rational index, exactly rounded sums) on
 small inputs; SciPy ``binned_statistic_2d`` / ``binned_statistic`` /
@@ -68,11 +69,18 @@ def axis_index(v, lo: float, hi: float, nbins: int):
     with np.errstate(invalid="ignore"):
         inside = (v >= lo) & (v <= hi)
     # R9: an axis of zero extent (possible only with bounds taken from the
-    # data) puts every inside particle into its first cell.
-    scale = np.float64(nbins) / (hi - lo) if hi > lo else np.float64(0.0)
+    # data) puts every inside particle into its first cell, and so does one
+    # whose extent hi - lo or scale nbins / (hi - lo) is not finite in
+    # binary64 (data spanning more than the largest double, or a subnormal
+    # extent): R2 has no finite scale to multiply by.
+    with np.errstate(over="ignore", divide="ignore"):
+        scale = np.float64(nbins) / (hi - lo) if hi > lo else np.float64(0.0)
+        if not (np.isfinite(hi - lo) and np.isfinite(scale)):
+            scale = np.float64(0.0)
     idx = np.zeros(v.shape, dtype=np.int64)
-    t = (v[inside] - lo) * scale
-    idx[inside] = np.trunc(t).astype(np.int64)
+    if scale > 0:
+        t = (v[inside] - lo) * scale
+        idx[inside] = np.trunc(t).astype(np.int64)
     np.minimum(idx, nbins - 1, out=idx)
     return inside, idx
 
@@ -215,8 +223,8 @@ def _exact_index(v: float, lo: float, hi: float, nbins: int) -> Optional[int]:
     the last bin for ``v == hi``, None outside (R1, R3)."""
     if not (lo <= v <= hi):          # NaN compares false
         return None
-    if lo == hi:                     # zero-extent axis (R9)
-        return 0
+    if lo == hi or not math.isfinite(hi - lo) or not math.isfinite(nbins / (hi - lo)):
+        return 0                     # zero or unrepresentable extent (R9)
     i = math.floor((Fraction(v) - Fraction(lo)) * nbins / (Fraction(hi) - Fraction(lo)))
     return min(i, nbins - 1)
 
@@ -299,19 +307,3 @@ def bin_particles_nd_bruteforce(coords, attrs, axes, bounds, dims) -> Dict[str, 
         for key, arr in (("sum", s), ("min", mn), ("max", mx), ("avg", avg), ("abs_sum", asum)):
             res[key].append(arr)
     return res
-
-
-def sum_tolerance_ok(got, ref_sum, abs_sum, rel: float = 1e-5) -> np.ndarray:
-    """Per-bin check |got - ref| <= rel * sum|a| (R8; plain relative error for
-    non-negative attributes).  Empty bins must hold exactly 0."""
-    got = np.asarray(got, dtype=np.float64)
-    return np.abs(got - ref_sum) <= rel * abs_sum
-
-
-def avg_tolerance_ok(got, ref_avg, abs_sum, count, rel: float = 1e-5) -> np.ndarray:
-    """Per-bin check |got - ref| <= rel * sum|a| / count; NaN exactly where empty."""
-    got = np.asarray(got, dtype=np.float64)
-    empty = count == 0
-    with np.errstate(invalid="ignore", divide="ignore"):
-        ok = np.abs(got - ref_avg) <= rel * abs_sum / np.maximum(count, 1)
-    return np.where(empty, np.isnan(got), ok)

@@ -328,6 +328,19 @@ def pin_auto_bounds(orc):
     # no finite value: nothing inside
     r = orc.bin_particles([np.full(5, np.nan), np.ones(5)], [np.ones(5)], (0, 1), None, 3, 3, ALL)
     assert r["inside"] == 0 and r["count"].sum() == 0
+    # extents with no finite binary64 scale count as zero extent: data
+    # spanning more than the largest double (hi - lo overflows), and a
+    # subnormal extent (nbins / (hi - lo) overflows); every finite particle
+    # is inside, in the first cell of that axis, on both oracle paths.
+    big = np.array([-1.5e308, 1.5e308, 0.0, 1e300, -1e300, np.inf])
+    tiny = np.array([0.0, 5e-324, 1e-323, 5e-324, 0.0, np.nan])
+    yv = np.array([0.1, 0.2, 0.3, 0.4, 0.5, 0.6])
+    for col in (big, tiny):
+        for res in (orc.bin_particles([col, yv], [yv], (0, 1), None, 8, 2, ALL),
+                    orc_bruteforce([col, yv], [yv], (0, 1), None, 8, 2)):
+            assert res["inside"] == 5 and res["count"][:, 0].sum() == 5 and res["count"][:, 1:].sum() == 0
+        inside, idx = orc.axis_index(col, *orc.auto_bounds([col], (0,)), 8)
+        assert inside.sum() == 5 and np.all(idx[inside] == 0)
 
 
 ALL_PINS.append(pin_auto_bounds)

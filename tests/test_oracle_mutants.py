@@ -49,7 +49,10 @@ MUTANTS += [
     ("auto_bounds_keep_nonfinite", "f = v[np.isfinite(v)]", "f = v[~np.isnan(v)]"),
     ("auto_bounds_swapped", 'out += [float(f.min()), float(f.max())] if f.size',
      'out += [float(f.min()), float(f.max()) * (1 + 2**-40)] if f.size'),
-    ("zero_extent_nan", "if hi > lo else np.float64(0.0)", "if hi >= lo else np.float64(0.0)"),
+    ("zero_scale_unguarded", "    if scale > 0:\n        t = (v[inside] - lo) * scale",
+     "    if True:\n        t = (v[inside] - lo) * scale"),
+    ("subnormal_extent_kept", "if not (np.isfinite(hi - lo) and np.isfinite(scale)):",
+     "if not np.isfinite(hi - lo):"),
 ]
 
 
