@@ -12,29 +12,41 @@ namespace bk {
 
 // Bin location (Section 4.2): inside test with a closed upper edge, then
 // trunc((x - lo) * scale) clamped to n-1, all in binary64.  A zero scale
-// (zero-extent axis) maps every inside value to cell 0.
+// (zero-extent axis, or an extent from the data too large or too small for
+// a finite binary64 scale) maps every inside value to cell 0: the product
+// is then 0, or NaN where v - lo overflows, and max(NaN, 0) is 0.
 __device__ __forceinline__ bool locate(double v, const Axis& a, int& idx) {
   if (!(v >= a.lo && v <= a.hi)) return false;  // NaN fails both tests
-  const double f = (v - a.lo) * a.scale;
-  const int i = (int)f;  // v_cvt_i32_f64 truncates; f >= 0 here
+  const double f = __builtin_fmax((v - a.lo) * a.scale, 0.0);
+  const int i = (int)f;  // v_cvt_i32_f64 truncates; 0 <= f <= n (1 + 2^-52) here
   idx = i < a.n ? i : a.n - 1;
   return true;
+}
+
+// Scale of an axis whose bounds come from the data: n / (hi - lo), or 0
+// when the extent is zero or either quantity is not finite in binary64.
+__device__ __forceinline__ double data_scale(int n, double lo, double hi) {
+  if (!(hi > lo)) return 0.0;
+  const double w = hi - lo;
+  const double s = (double)n / w;
+  return (__builtin_isfinite(w) && __builtin_isfinite(s)) ? s : 0.0;
 }
 
 __device__ __forceinline__ double fkey_decode(long long k);
 
 // Axes from bounds computed on the device (four totalOrder keys: xmin,
 // xmax, ymin, ymax), or left as passed when keys is null.  A zero-extent
-// axis gets scale 0 (every inside value in cell 0); an axis that saw no
-// finite value has lo = +Inf > hi = -Inf, so nothing is inside.
+// axis, or one whose extent or scale is not finite, gets scale 0 (every
+// inside value in cell 0); an axis that saw no finite value has
+// lo = +Inf > hi = -Inf, so nothing is inside.
 __device__ __forceinline__ void resolve_axes(const long long* keys, Axis& ax, Axis& ay) {
   if (!keys) return;
   ax.lo = fkey_decode(keys[0]);
   ax.hi = fkey_decode(keys[1]);
   ay.lo = fkey_decode(keys[2]);
   ay.hi = fkey_decode(keys[3]);
-  ax.scale = ax.hi > ax.lo ? (double)ax.n / (ax.hi - ax.lo) : 0.0;
-  ay.scale = ay.hi > ay.lo ? (double)ay.n / (ay.hi - ay.lo) : 0.0;
+  ax.scale = data_scale(ax.n, ax.lo, ax.hi);
+  ay.scale = data_scale(ay.n, ay.lo, ay.hi);
 }
 
 // totalOrder min/max on float bit patterns held directly in a result array.

@@ -11,6 +11,12 @@ from oracle import binning_oracle as orc
 # accumulation paths; the plain FP32 path is checked against a bound that
 # grows with the bin's count instead (see plain_bound).
 REL = 1e-5
+# Besides the sum|a|-normalised bound, the compensated and binary64 paths are
+# held to plain relative error against the FP64 reference on every bin whose
+# sum is not cancelled: |ref| >= sum|a| / COND_MAX (condition number at most
+# COND_MAX).  Where a signed attribute's sum cancels, relative error is not
+# defined by the data and only the normalised bound applies.
+COND_MAX = 1e3
 
 
 def to_device(ws, device="cuda"):
@@ -68,6 +74,12 @@ def assert_parity(got, ref, ops, rel=REL, plain=False, what=""):
             assert not bad.any(), (f"{what}: sum[{j}] off in {bad.sum()} bins; worst excess "
                                    f"{np.max((err - bound)[bad])}")
             assert np.all(g[empty] == 0), f"{what}: empty-bin sum not 0"
+            if not plain:
+                r = ref["sum"][j]
+                well = ~empty & (np.abs(r) * COND_MAX >= ref["abs_sum"][j])
+                rbad = well & ~(err <= rel * np.abs(r))
+                assert not rbad.any(), (f"{what}: sum[{j}] relative error above {rel} in {rbad.sum()} "
+                                        f"well-conditioned bins")
         if ops & B.AVG:
             g = got["avg"][j].astype(np.float64)
             err = np.abs(g - ref["avg"][j])
@@ -75,6 +87,14 @@ def assert_parity(got, ref, ops, rel=REL, plain=False, what=""):
                 ok = err <= bound / np.maximum(cnt, 1) + _avg_cast_slack(got["avg"][j].dtype, ref["avg"][j])
             ok = np.where(empty, np.isnan(g), ok)
             assert ok.all(), f"{what}: avg[{j}] off in {np.sum(~ok)} bins"
+            if not plain:
+                r = ref["avg"][j]
+                with np.errstate(invalid="ignore"):
+                    well = ~empty & (np.abs(r) * cnt * COND_MAX >= ref["abs_sum"][j])
+                    slack = _avg_cast_slack(got["avg"][j].dtype, r)
+                    rbad = well & ~(err <= rel * np.abs(r) + slack)
+                assert not rbad.any(), (f"{what}: avg[{j}] relative error above {rel} in {rbad.sum()} "
+                                        f"well-conditioned bins")
 
 
 def _avg_cast_slack(dtype, ref_avg):

@@ -368,6 +368,19 @@ def test_auto_bounds_degenerate(strategy):
     ws = _ws([np.full(n, np.nan), rng.random(n)], [rng.standard_normal(n)], 8, 8)
     got = _run_auto(ws, strategy)
     assert got["count"].sum() == 0 and np.all(np.isnan(got["avg"][0]))
+    # extents with no finite binary64 scale (R9): binary64 data spanning more
+    # than the largest double, and a subnormal extent; both count as zero
+    # extent, every finite particle in the first column
+    big = rng.uniform(-1.0, 1.0, n) * 1.7e308
+    big[:2] = [-1.7e308, 1.7e308]
+    tiny = rng.integers(0, 4, n).astype(np.float64) * 5e-324
+    tiny[3] = np.inf
+    for col, what in ((big, "overflowing extent"), (tiny, "subnormal extent")):
+        ws = _ws([col, rng.random(n)], [rng.standard_normal(n)], 8, 8)
+        ref = orc.bin_particles(ws.coords, ws.attrs, (0, 1), None, 8, 8)
+        got = _run_auto(ws, strategy)
+        assert got["count"][:, 1:].sum() == 0 and got["count"].sum() == int(np.isfinite(col).sum()), what
+        G.assert_parity(got, ref, 31, rel=1e-12, what=what)
 
 
 @pytest.mark.parametrize("strategy", [pytest.param(1, id="lds"), pytest.param(2, id="part")])
