@@ -75,13 +75,16 @@ void set_part_blocks(bk::PartArgs& a, int scatter_threads, int ppt) {
 }
 
 void set_part_items(bk::PartArgs& a, int cus) {
-  // Items group whole slices greedily; two consecutive items of a tile hold
-  // more than split_len records together, so a tile with R records (padding
-  // included) has at most 2 + 2 R / split_len items.
-  a.max_items = (int32_t)(2 * (int64_t)a.ntiles + 2 * ceil_div((int64_t)part_records(a), (int64_t)a.split_len));
-  // Partial slots only for items of split tiles (ni >= 2 items each):
-  // sum over split tiles of ni <= 2 * sum of (ni - 1) <= 2 * (max_items - ntiles).
-  a.max_slots = (int32_t)std::min<int64_t>(a.max_items, 2 * ((int64_t)a.max_items - a.ntiles));
+  // Slice w of tile t opens item floor(excl(w) / L) of the tile, with excl(w)
+  // the tile's records (padding included) in the slices before w and L the
+  // split length.  The item numbers of a tile run from 0 to at most
+  // m = floor(R_t / L) for a tile of R_t records, so it has at most m + 1
+  // items; a split tile (two or more items) has m >= 1 and so at most 2 m.
+  // Summed over tiles, with R = all record slots: items <= tiles + R / L,
+  // and partial slots (items of split tiles) <= 2 R / L.
+  const int64_t q = (int64_t)part_records(a) / (int64_t)a.split_len;
+  a.max_items = (int32_t)((int64_t)a.ntiles + q);
+  a.max_slots = (int32_t)std::min<int64_t>(a.max_items, 2 * q);
   a.merge_blocks = merge_blocks(a, cus);
 }
 

@@ -2,6 +2,8 @@
 tile size, gather kind, launch shape and the work-item bound, for the
 device sizes of MI355X and of smaller parts."""
 import re
+
+import numpy as np
 from ctypes import c_double, c_int32
 
 import pytest
@@ -89,8 +91,8 @@ def test_lds_strategy_at_most_1024_threads_per_cu():
 
 
 def test_work_item_bound_covers_padding():
-    """max_items = 2 * tiles + 2 * ceil(record slots / split_len), with the
-    record slots including the quad padding of every sub-chunk."""
+    """max_items = tiles + floor(record slots / split_len), with the record
+    slots including the quad padding of every sub-chunk."""
     for n, side, k in [(1 << 27, 2048, 1), (1 << 24, 1024, 4), (3_000_001, 700, 1), (1 << 24, 128, 1)]:
         kind, f = plan(n, side, side, k=k)
         assert kind == "partition"
@@ -100,7 +102,52 @@ def test_work_item_bound_covers_padding():
         if f["quads"] == "1":
             pad = (3 * min(tiles, int(f["sub"])) + 3) // 4 * 4
         slots = n + nrows * pad + 4
-        assert items == 2 * tiles + 2 * -(-slots // split), (n, side, f)
+        assert items == tiles + slots // split, (n, side, f)
+
+
+def _walk_items(counts, split_len):
+    """The work-item rule of the tile binning, written out per tile: slice w
+    opens item floor(excl(w) / split_len) of its tile, where excl(w) is the
+    tile's records in earlier slices; an item starts at every slice whose
+    number differs from the previous slice's.  Returns items per tile."""
+    out = []
+    for row in counts:
+        excl, prev, items = 0, None, 0
+        for c in row:
+            m = excl // split_len
+            if m != prev:
+                items += 1
+                prev = m
+            excl += int(c)
+        out.append(items)
+    return out
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_work_item_and_slot_bounds_hold_for_any_counts(seed):
+    """The planner's bounds - items <= tiles + floor(R / L) and partial
+    slots (items of tiles with two or more items) <= 2 floor(R / L) for R
+    records in all - hold for every count matrix: random, one heavy slice,
+    records just above multiples of L, all records in one tile."""
+    rng = np.random.default_rng(seed)
+    tiles, slices = int(rng.integers(1, 40)), int(rng.integers(1, 60))
+    L = int(rng.integers(1, 50))
+    kind = seed % 4
+    if kind == 0:
+        counts = rng.integers(0, 3 * L, (tiles, slices))
+    elif kind == 1:
+        counts = np.zeros((tiles, slices), dtype=np.int64)
+        counts[:, rng.integers(0, slices)] = rng.integers(0, 20 * L, tiles)
+    elif kind == 2:
+        counts = np.full((tiles, slices), L + 1)
+        counts[:, ::3] = 0
+    else:
+        counts = np.zeros((tiles, slices), dtype=np.int64)
+        counts[rng.integers(0, tiles)] = rng.integers(L - 1, L + 2, slices)
+    R = int(counts.sum())
+    items = _walk_items(counts, L)
+    assert sum(items) <= tiles + R // L
+    assert sum(i for i in items if i > 1) <= 2 * (R // L)
 
 
 def test_unaligned_columns_turn_off_wide_loads():
