@@ -161,6 +161,29 @@ int bin_validate(const bin_columns* coords, const bin_columns* attrs, int64_t n,
                  const int32_t axes[2], const double bounds[4], int32_t nx, int32_t ny,
                  uint32_t ops, const bin_output* out);
 
+/* ---- allocation-free variant ---------------------------------------------- */
+/* For callers that cannot allocate device memory: code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same arguments,
+ * outputs, readings and stream semantics as bin_particles, and the same
+ * kernels; the library's scratch for the call comes from one fixed device
+ * array of BIN_NOALLOC_SCRATCH_BYTES per GPU (part of the library's device
+ * code, held from the first call on that GPU until the process ends), so
+ * the call allocates nothing: no hipMalloc/hipFree, no allocating library
+ * routine, no events.  The caller still owns inputs and outputs.
+ * Limit: a request whose plan needs more scratch than the array holds is
+ * refused with BIN_ERR_INVALID_ARG before anything is enqueued (roughly, a
+ * partition-strategy request takes 6 bytes per particle plus 4 per extra
+ * attribute, a whole-grid LDS request one partial grid per workgroup; a
+ * request with no scratch - one workgroup - always fits).
+ * Concurrency: every call on one GPU uses that GPU's one array, and the
+ * array keeps the last call's contents (the kernels set up what they read).
+ * Calls whose work overlaps on one GPU - on different streams or from
+ * several threads - race on the array; order them, e.g. one stream per GPU. */
+#define BIN_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int bin_particles_noalloc(const bin_columns* coords, const bin_columns* attrs, int64_t n,
+                          const int32_t axes[2], const double bounds[4], int32_t nx, int32_t ny,
+                          uint32_t ops, const bin_output* out, void* stream);
+
 /* ---- meshes of one, two or three axes ----------------------------------- */
 /* The mesh axes are any chosen subset of the particle variables (paper,
  * Section 4.2); this entry point takes one, two or three of them.

@@ -29,7 +29,7 @@ MAX_ATTRS = 16
 
 #: Every function declared in include/binning.h.
 EXPORTS = (
-    "bin_particles", "bin_validate", "bin_particles_nd", "bin_validate_nd", "bin_particles_async", "bin_particles_batched", "bin_particles_multi", "bin_graph_create", "bin_graph_launch",
+    "bin_particles", "bin_particles_noalloc", "bin_validate", "bin_particles_nd", "bin_validate_nd", "bin_particles_async", "bin_particles_batched", "bin_particles_multi", "bin_graph_create", "bin_graph_launch",
     "bin_graph_destroy", "bin_autotune", "bin_status_string", "bin_last_error_message",
     "bin_stream_status", "bin_release_workspace", "bin_version", "bin_timing_enable", "bin_timing_read",
     "bin_timing_report",
@@ -101,6 +101,9 @@ def lib() -> ctypes.CDLL:
     sig = {
         "bin_particles": (c_int, [POINTER(Columns), POINTER(Columns), c_int64, POINTER(c_int32),
                                   POINTER(c_double), c_int32, c_int32, c_uint32, POINTER(Output), c_void_p]),
+        "bin_particles_noalloc": (c_int, [POINTER(Columns), POINTER(Columns), c_int64, POINTER(c_int32),
+                                          POINTER(c_double), c_int32, c_int32, c_uint32, POINTER(Output),
+                                          c_void_p]),
         "bin_validate": (c_int, [POINTER(Columns), POINTER(Columns), c_int64, POINTER(c_int32),
                                  POINTER(c_double), c_int32, c_int32, c_uint32, POINTER(Output)]),
         "bin_particles_nd": (c_int, [POINTER(Columns), POINTER(Columns), c_int64, c_int32, POINTER(c_int32),
@@ -231,6 +234,20 @@ def bin_particles(coords, attrs, n: int, axes, bounds, nx: int, ny: int, ops: in
     bd = (c_double * 4)(*bounds) if bounds is not None else None
     st = lib().bin_particles(ctypes.byref(c), ctypes.byref(a) if a is not None else None, n, ax, bd,
                              nx, ny, ops, ctypes.byref(o), _stream_handle(stream))
+    check(st)
+
+
+def bin_particles_noalloc(coords, attrs, n: int, axes, bounds, nx: int, ny: int, ops: int, out: Dict,
+                          stream=None, coord_dtype=None, attr_dtype=None) -> None:
+    """bin_particles with the library's scratch in its fixed per-GPU array
+    (no device allocation); arguments as bin_particles."""
+    c, ck = columns(coords, coord_dtype)
+    a, ak = columns(attrs, attr_dtype) if attrs is not None else (None, None)
+    o, ok = output(out.get("count"), out.get("sum"), out.get("min"), out.get("max"), out.get("avg"))
+    ax = (c_int32 * 2)(*axes)
+    bd = (c_double * 4)(*bounds) if bounds is not None else None
+    st = lib().bin_particles_noalloc(ctypes.byref(c), ctypes.byref(a) if a is not None else None, n, ax, bd,
+                                     nx, ny, ops, ctypes.byref(o), _stream_handle(stream))
     check(st)
 
 

@@ -5,7 +5,7 @@
 
 using namespace binimpl;
 
-namespace {
+namespace binimpl {
 
 bin_request make_request(const bin_columns* coords, const bin_columns* attrs, int64_t n,
                          const int32_t axes[2], const double bounds[4], int32_t nx, int32_t ny,
@@ -25,6 +25,10 @@ bin_request make_request(const bin_columns* coords, const bin_columns* attrs, in
   return r;
 }
 
+}  // namespace binimpl
+
+namespace {
+
 // A stream that already holds a fault makes every later call on it fail.
 int precheck_stream(hipStream_t s) {
   hipError_t e = hipStreamQuery(s);
@@ -39,8 +43,22 @@ static thread_local PlanHints t_hints;
 const PlanHints& thread_hints() { return t_hints; }
 PlanHints& thread_hints_mut() { return t_hints; }
 
-// Single request on a stream (also used by the autotuner).
-int run_request(const bin_request& r, hipStream_t s, const PlanHints& hints) {
+// Scratch of 'bytes' for a request on stream s: from the caller's fixed
+// block (no allocation; a request that needs more is refused), else from
+// the library's pool for (device, stream).
+static int take_scratch(int device, hipStream_t s, size_t bytes, const FixedScratch* fixed, void** out) {
+  if (!fixed) return scratch_get(device, s, bytes, out);
+  if (bytes > fixed->cap)
+    return fail(BIN_ERR_INVALID_ARG,
+                "the request needs %zu bytes of scratch on this device, more than the %zu bytes the "
+                "allocation-free entry point holds; use bin_particles",
+                bytes, fixed->cap);
+  *out = bytes ? fixed->ptr : nullptr;
+  return BIN_OK;
+}
+
+int run_request_in(const bin_request& r, hipStream_t s, const PlanHints& hints, const FixedScratch* fixed,
+                   bk::KTimer* tm) {
   DeviceInfo dev;
   int st = device_info(&dev);
   if (st) return st;
@@ -51,19 +69,24 @@ int run_request(const bin_request& r, hipStream_t s, const PlanHints& hints) {
   if (st) return st;
   void* scratch = nullptr;
   if (p.scratch_bytes) {
-    st = scratch_get(dev.device, s, p.scratch_bytes, &scratch);
+    st = take_scratch(dev.device, s, p.scratch_bytes, fixed, &scratch);
     if (st) return st;
     st = prepare(r, dev, hints, scratch, &p);
     if (st) return st;
   }
-  return enqueue(p, s, timing_timer());
+  return enqueue(p, s, tm);
+}
+
+// Single request on a stream (also used by the autotuner).
+int run_request(const bin_request& r, hipStream_t s, const PlanHints& hints) {
+  return run_request_in(r, s, hints, nullptr, timing_timer());
 }
 
 // Bounds from the data (bounds == NULL): a min/max pass over the two axis
 // columns writes four keys at the start of the scratch block; the binning
 // kernels read them instead of host bounds.  The plan itself does not
 // depend on the bounds, so it is made with a placeholder.
-int run_auto_bounds(const bin_request& r0, hipStream_t s) {
+int run_auto_bounds_in(const bin_request& r0, hipStream_t s, const FixedScratch* fixed, bk::KTimer* tm) {
   bin_request r = r0;
   r.bounds[0] = 0.0;
   r.bounds[1] = 1.0;
@@ -79,7 +102,7 @@ int run_auto_bounds(const bin_request& r0, hipStream_t s) {
   st = prepare(r, dev, hints, nullptr, &p);
   if (st) return st;
   void* scratch = nullptr;
-  st = scratch_get(dev.device, s, p.scratch_bytes + 256, &scratch);
+  st = take_scratch(dev.device, s, p.scratch_bytes + 256, fixed, &scratch);
   if (st) return st;
   st = prepare(r, dev, hints, static_cast<unsigned char*>(scratch) + 256, &p);
   if (st) return st;
@@ -87,12 +110,13 @@ int run_auto_bounds(const bin_request& r0, hipStream_t s) {
   p.bin.dyn = keys;
   p.lds.dyn = keys;
   p.part.dyn = keys;
-  bk::KTimer* tm = timing_timer();
   hipError_t e = bk::launch_bounds(r.coords.cols[r.axes[0]], r.coords.cols[r.axes[1]], p.coord_f64, r.n, keys,
                                    dev.cus, s, tm);
   if (e != hipSuccess) return hip_fail(e, "launch bounds kernels");
   return enqueue(p, s, tm);
 }
+
+int run_auto_bounds(const bin_request& r, hipStream_t s) { return run_auto_bounds_in(r, s, nullptr, timing_timer()); }
 
 // Three axes: fold axes 1 and 2 into a composite column in scratch (one
 // pass), then bin (axis 0, composite) on a dims[0] x dims[1] * dims[2] mesh

@@ -119,8 +119,21 @@ int enqueue(const Prepared& p, hipStream_t s, bk::KTimer* tm);
 std::string describe(const Prepared& p);
 
 // Whole requests.
+bin_request make_request(const bin_columns* coords, const bin_columns* attrs, int64_t n, const int32_t axes[2],
+                         const double bounds[4], int32_t nx, int32_t ny, uint32_t ops, const bin_output* out);
 int run_request(const bin_request& r, hipStream_t s, const PlanHints& hints);
 int run_auto_bounds(const bin_request& r, hipStream_t s);
+// The same with the scratch taken from a fixed device block of cap bytes
+// (nothing is allocated; a request needing more fails with
+// BIN_ERR_INVALID_ARG), or from the pool when fixed is null; tm times the
+// launches (null: untimed).
+struct FixedScratch {
+  void* ptr;
+  size_t cap;
+};
+int run_request_in(const bin_request& r, hipStream_t s, const PlanHints& hints, const FixedScratch* fixed,
+                   bk::KTimer* tm);
+int run_auto_bounds_in(const bin_request& r, hipStream_t s, const FixedScratch* fixed, bk::KTimer* tm);
 int run_batch(const bin_request* reqs, int nreq, hipStream_t s, const PlanHints& hints);
 // Device scratch a batch needs (0 and *status set on a bad batch).
 size_t batch_scratch_bytes(const bin_request* reqs, int nreq, int* status);

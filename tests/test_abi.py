@@ -101,6 +101,11 @@ def test_bin_particles_rejects_before_any_hip_call():
     with pytest.raises(B.BinError) as ei:
         B.bin_particles(**good(bounds=(0.0, 0.0, 0.0, 1.0)), stream=0)
     assert ei.value.status == B.BIN_ERR_INVALID_ARG
+    # the allocation-free variant runs the same checks first
+    for over in (dict(nx=0), dict(bounds=(0.0, 0.0, 0.0, 1.0)), dict(ops=0)):
+        with pytest.raises(B.BinError) as ei:
+            B.bin_particles_noalloc(**good(**over), stream=0)
+        assert ei.value.status == B.BIN_ERR_INVALID_ARG
 
 
 def test_plain_sum_outputs_may_be_4_byte_aligned():
