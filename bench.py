@@ -92,21 +92,38 @@ def algorithmic_bytes(ws):
     return ins, outs
 
 
-def cpu_baseline(ws, target_s: float = 12.0):
-    """The oracle as it stands, on a prefix sample of the same particles:
-    grow the sample until one run takes about target_s seconds (or the whole
-    workload is used)."""
+def host_cpu():
+    """CPU model and logical CPU count of the host the benchmark runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
+
+
+def _oracle_call(ws, lo, hi):
     from oracle import binning_oracle as orc
+    if "nd" in ws.meta:
+        axes, bounds, dims = ws.meta["nd"]
+        return orc.bin_particles_nd([c[lo:hi] for c in ws.coords], [a[lo:hi] for a in ws.attrs], axes, bounds, dims)
+    return orc.bin_particles([c[lo:hi] for c in ws.coords], [a[lo:hi] for a in ws.attrs], ws.axes, ws.bounds,
+                             ws.nx, ws.ny)
+
+
+def cpu_baseline_1core(ws, target_s: float = 12.0):
+    """The oracle as it stands, one NumPy thread, on a prefix sample of the
+    same particles: grow the sample until one run takes about target_s
+    seconds (or the whole workload is used)."""
     n = ws.n
     m = min(n, 1 << 20)
     while True:
         t0 = time.perf_counter()
-        if "nd" in ws.meta:
-            axes, bounds, dims = ws.meta["nd"]
-            orc.bin_particles_nd([c[:m] for c in ws.coords], [a[:m] for a in ws.attrs], axes, bounds, dims)
-        else:
-            orc.bin_particles([c[:m] for c in ws.coords], [a[:m] for a in ws.attrs], ws.axes, ws.bounds, ws.nx,
-                              ws.ny)
+        _oracle_call(ws, 0, m)
         dt = time.perf_counter() - t0
         if dt >= 0.5 * target_s or m >= n:
             break
@@ -114,6 +131,60 @@ def cpu_baseline(ws, target_s: float = 12.0):
     return {"value": round(m / dt / 1e9, 6), "unit": "Gparticles/s", "cores": 1, "kind": "oracle",
             "sample": f"first {m} of {n} particles of the same workload (same grid, ops), one NumPy thread, "
                       f"{dt:.1f} s"}
+
+
+_NCORE = {}
+
+
+def _ncore_worker(w):
+    """Oracle on slice w of the sample; writes count, sum, |a| sum, min and
+    max into this worker's rows of the shared result arrays."""
+    ws, m, W, sh = _NCORE["ws"], _NCORE["m"], _NCORE["W"], _NCORE["sh"]
+    lo, hi = w * m // W, (w + 1) * m // W
+    r = _oracle_call(ws, lo, hi)
+    sh["count"][w] = r["count"].ravel()
+    for j in range(len(ws.attrs)):
+        for key in ("sum", "abs_sum", "min", "max"):
+            sh[key][w, j] = r[key][j].ravel()
+    return r["inside"]
+
+
+def cpu_baseline_ncore(ws, m: int, workers: int):
+    """The same oracle on N processes: the first m particles split into N
+    slices, each binned by the oracle in its own process (forked, results
+    written to shared memory), the partial grids combined by the oracle's
+    merge law (counts and sums add, min of mins, max of maxes)."""
+    import multiprocessing as mp
+    from multiprocessing import shared_memory
+    from oracle import binning_oracle as orc
+    nb = int(np.prod(ws.meta["nd"][2])) if "nd" in ws.meta else ws.nx * ws.ny
+    k = len(ws.attrs)
+    W = workers
+    blocks, sh = [], {}
+    for key, shape in (("count", (W, nb)), ("sum", (W, k, nb)), ("abs_sum", (W, k, nb)), ("min", (W, k, nb)),
+                       ("max", (W, k, nb))):
+        dt = np.int64 if key == "count" else np.float64
+        shm = shared_memory.SharedMemory(create=True, size=max(8, int(np.prod(shape)) * 8))
+        blocks.append(shm)
+        sh[key] = np.ndarray(shape, dtype=dt, buffer=shm.buf)
+    _NCORE.update(ws=ws, m=m, W=W, sh=sh)
+    try:
+        t0 = time.perf_counter()
+        with mp.get_context("fork").Pool(W) as pool:
+            inside = pool.map(_ncore_worker, range(W), chunksize=1)
+        parts = [{"count": sh["count"][w], "inside": inside[w],
+                  **{key: [sh[key][w, j] for j in range(k)] for key in ("sum", "abs_sum", "min", "max")}}
+                 for w in range(W)]
+        orc.merge(parts)
+        dt = time.perf_counter() - t0
+    finally:
+        _NCORE.clear()
+        for shm in blocks:
+            shm.close()
+            shm.unlink()
+    return {"value": round(m / dt / 1e9, 6), "unit": "Gparticles/s", "cores": W, "kind": "oracle",
+            "sample": f"first {m} of {ws.n} particles of the same workload in {W} slices, one process per "
+                      f"slice, partial grids combined by the merge law, {dt:.1f} s"}
 
 
 def kernel_algorithmic_bytes(name: str, ws) -> int:
@@ -296,11 +367,12 @@ def run_served(args):
     stream = torch.cuda.Stream()
     B.bin_autotune(pool)
     batch = B.Batch(pool)
-    # up to well past what one-at-a-time launches sustain (~9000 req/s here)
-    rates = [100, 1000, 5000, 10000, 20000, 40000]
+    # the configured sweep (100-5000 req/s), then past what one-at-a-time
+    # launches sustain
+    rates = [100, 200, 500, 1000, 2000, 5000, 10000, 20000, 40000]
     rows = []
     for rate in rates:
-        count = int(min(3000, max(200, rate // 4)))
+        count = int(min(5000, max(1000, 2 * rate)))
         arr = synth.poisson_arrivals(rate, count, seed=rate)
         pick = np.random.default_rng(rate).integers(0, len(pool), count)
         n_total = int(sum(pool[i]["n"] for i in pick))
@@ -462,15 +534,116 @@ def run_insitu(args):
     print(json.dumps(rec), flush=True)
 
 
+def time_region(call, stream, steps):
+    """Milliseconds of `steps` back-to-back calls: one event pair on the
+    launch stream around all of them, the device synchronised on both sides."""
+    import torch
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        call()
+    e1.record(stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def time_each(call, stream, steps):
+    """Milliseconds of each of `steps` calls (an event pair around each)."""
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record(stream)
+        call()
+        b.record(stream)
+    stream.synchronize()
+    return [a.elapsed_time(b) for a, b in ev]
+
+
+def stream_copy_GBs(dev, stream, nbytes=1 << 30, reps=10):
+    """Measured device-to-device copy bandwidth (bytes read + written per
+    second) of a plain 1 GiB copy: the practical streaming ceiling."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    with torch.cuda.stream(stream):
+        dst.copy_(src)
+        ms = time_region(lambda: dst.copy_(src), stream, reps)
+    del src, dst
+    return 2 * nbytes * reps / (ms / 1e3) / 1e9
+
+
+def _bits(a):
+    return a.view(np.int64 if a.dtype == np.float64 else np.int32)
+
+
+def precision_study(ws, coords, attrs, stream, steps):
+    """Each precision mode on the whole workload against the binary64 oracle:
+    count/min/max mismatches (bins), and per op the largest and the 99th
+    percentile error over non-empty bins - |sum - ref| / sum|a| and
+    |avg - ref| / (sum|a| / count) - plus plain relative error |x - ref| / |ref|
+    where the sum does not cancel (|ref| >= sum|a| / 1000); and each mode's
+    time per call."""
+    import torch
+    from oracle import binning_oracle as orc
+    from paper_2310_02926_amd import binding as B
+    t0 = time.perf_counter()
+    ref = orc.bin_particles(ws.coords, ws.attrs, ws.axes, ws.bounds, ws.nx, ws.ny)
+    log(f"precision study: oracle on all {ws.n} particles in {time.perf_counter() - t0:.1f}s")
+    cnt = ref["count"].ravel()
+    full = cnt > 0
+    out = {}
+    for name, flag in (("default", 0), ("comp", B.PREC_COMP), ("plain", B.PREC_PLAIN), ("f64", B.PREC_F64)):
+        ops = B.OPS_ALL | flag
+        o = B.alloc_outputs(attrs, ws.nx, ws.ny, ops, coords[0].device)
+
+        def call():
+            B.bin_particles(coords, attrs, ws.n, ws.axes, ws.bounds, ws.nx, ws.ny, ops, o, stream=stream)
+        for _ in range(3):
+            call()
+        ms = time_region(call, stream, steps) / steps
+        g = {"count": o["count"].cpu().numpy().view(np.uint32).astype(np.int64).ravel()}
+        row = {"ms_per_step": round(ms, 5), "Gparticles_s": round(ws.n / (ms / 1e3) / 1e9, 3),
+               "count_mismatches": int(np.sum(g["count"] != cnt))}
+        for j in range(len(ws.attrs)):
+            asum = ref["abs_sum"][j].ravel()
+            for key in ("min", "max"):
+                got = o[key][j].cpu().numpy().ravel()
+                row[f"{key}_mismatches"] = row.get(f"{key}_mismatches", 0) + int(
+                    np.sum(_bits(got) != _bits(ref[key][j].ravel().astype(got.dtype))))
+            for key in ("sum", "avg"):
+                got = o[key][j].cpu().numpy().ravel().astype(np.float64)
+                r = ref[key][j].ravel()
+                err = np.abs(got[full] - r[full])
+                scale = asum[full] if key == "sum" else asum[full] / cnt[full]
+                norm = err / scale
+                well = np.abs(r[full]) * 1e3 >= scale
+                rel = err[well] / np.abs(r[full][well])
+                row[f"{key}_err_norm_max"] = float(norm.max()) if norm.size else 0.0
+                row[f"{key}_err_norm_p99"] = float(np.percentile(norm, 99)) if norm.size else 0.0
+                row[f"{key}_err_rel_max"] = float(rel.max()) if rel.size else 0.0
+                row[f"{key}_err_rel_p99"] = float(np.percentile(rel, 99)) if rel.size else 0.0
+        out[name] = row
+        log(f"precision {name}: {row}")
+        del o
+        torch.cuda.synchronize()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="hotspot", choices=["hotspot", "gmm", "uniform", "nd3", "batched", "served", "insitu"])
     ap.add_argument("--prec", default="default", choices=["default", "comp", "plain", "f64"])
     ap.add_argument("--scale", type=int, default=0, help="shrink n by 2^scale (quick runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-studies", action="store_true",
+                    help="skip the precision study and the bounds-from-data leg of the headline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of known size (for HBM counter scaling)")
     args = ap.parse_args()
@@ -528,19 +701,13 @@ def main():
     stream.synchronize()
     log(f"warmup {args.warmup} done")
 
-    # Timed region 1: whole calls, bracketed by events on the launch stream.
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(args.steps):
-        call()
-    ev1.record(stream)
-    stream.synchronize()
-    torch.cuda.synchronize()
-    total_ms = ev0.elapsed_time(ev1)
-    ms_step = total_ms / args.steps
-    # Timed region 2: the same calls with the library's per-kernel event pairs.
+    # Timed region 1: exactly `steps` whole calls, bracketed by events on the
+    # launch stream with the device synchronised on both sides.
+    ms_step = time_region(call, stream, args.steps) / args.steps
+    # Region 2: the same calls one by one (an event pair around each), for
+    # the distribution of the time per call.
+    each = np.asarray(time_each(call, stream, args.steps))
+    # Region 3: the same calls with the library's per-kernel event pairs.
     B.bin_timing_enable(True)
     for _ in range(args.steps):
         call()
@@ -549,8 +716,10 @@ def main():
     rep = B.bin_timing_report()
     dominant = max(rep, key=lambda k: rep[k][1])
     launches, kern_ms = rep[dominant]
-    log(f"timed {args.steps} steps: {ms_step:.4f} ms/step; kernels (avg ms): "
+    log(f"timed {args.steps} steps: {ms_step:.4f} ms/step (median {np.median(each):.4f}); kernels (avg ms): "
         + ", ".join(f"{k}={v[1] / max(v[0], 1):.4f}" for k, v in sorted(rep.items(), key=lambda kv: -kv[1][1])))
+    copy_gbs = stream_copy_GBs(dev, stream)
+    log(f"stream copy {copy_gbs:.0f} GB/s")
 
     ins, outs = algorithmic_bytes(ws)
     kern_avg_s = kern_ms / max(launches, 1) / 1e3
@@ -558,6 +727,7 @@ def main():
     achieved = kbytes / kern_avg_s / 1e9
     khash = kernel_source_hash()
     value = ws.n / (ms_step / 1e3) / 1e9
+    whole_gbs = (ins + outs) / (ms_step / 1e3) / 1e9
     # HBM bytes per launch of the dominant kernel from the committed counter
     # runs (FETCH_SIZE + WRITE_SIZE, copy-calibrated), only while the kernel
     # sources are the ones those counters were taken on
@@ -595,17 +765,55 @@ def main():
             "algorithmic_bytes_per_launch": kbytes,
             "kernel_ms_avg": round(kern_avg_s * 1e3, 5),
         },
+        "per_call_ms": {"median": round(float(np.median(each)), 5), "p10": round(float(np.percentile(each, 10)), 5),
+                        "p90": round(float(np.percentile(each, 90)), 5), "calls": int(each.size)},
         "kernels_ms_avg": {k: round(v[1] / max(v[0], 1), 5) for k, v in rep.items()},
         "whole_call": {
             "algorithmic_bytes": ins + outs,
-            "achieved_GBs": round((ins + outs) / (ms_step / 1e3) / 1e9, 1),
-            "frac_of_hbm_peak": round((ins + outs) / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "achieved_GBs": round(whole_gbs, 1),
+            "frac_of_hbm_peak": round(whole_gbs / HBM_PEAK_GBS, 4),
+            "stream_copy_GBs": round(copy_gbs, 1),
+            "frac_of_stream_copy": round(whole_gbs / copy_gbs, 4),
         },
         "kernel_source_hash": khash,
+        "host_cpu": host_cpu(),
     }
+    if args.workload == "hotspot" and args.prec == "default" and not args.no_studies and "nd" not in ws.meta:
+        # Bounds from the data: the same call with bounds = NULL (a min/max
+        # pass over the two coordinate columns first).
+        oa = B.alloc_outputs(attrs, ws.nx, ws.ny, ops, dev)
+
+        def call_auto():
+            B.bin_particles(coords, attrs, ws.n, ws.axes, None, ws.nx, ws.ny, ops, oa, stream=stream)
+        for _ in range(3):
+            call_auto()
+        ms_auto = time_region(call_auto, stream, args.steps) / args.steps
+        B.bin_timing_enable(True)
+        for _ in range(args.steps):
+            call_auto()
+        stream.synchronize()
+        B.bin_timing_enable(False)
+        ra = B.bin_timing_report()
+        bk = ra.get("bounds_reduce_kernel", (1, 0.0))
+        b_ms = bk[1] / max(bk[0], 1)
+        b_bytes = sum(c.itemsize * c.size for c in ws.coords[:2])
+        rec["bounds_from_data"] = {
+            "ms_per_step": round(ms_auto, 5), "Gparticles_s": round(ws.n / (ms_auto / 1e3) / 1e9, 3),
+            "bounds_reduce_kernel_ms": round(b_ms, 5),
+            "bounds_pass_GBs": round(b_bytes / (b_ms / 1e3) / 1e9, 1) if b_ms > 0 else None,
+            "bounds_pass_frac_of_hbm_peak": round(b_bytes / (b_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if b_ms > 0 else None,
+            "floor_bytes_per_particle": 2 * ws.coords[0].itemsize}
+        log(f"bounds from the data: {rec['bounds_from_data']}")
+        del oa
+        rec["precision_study"] = precision_study(ws, coords, attrs, stream, max(10, args.steps // 2))
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a sample")
-        rec["cpu_baseline"] = cpu_baseline(ws)
+        log("timing the CPU oracle on a sample (one process)")
+        one = cpu_baseline_1core(ws)
+        m = int(one["sample"].split()[1])
+        workers = max(1, min(16, os.cpu_count() or 1))
+        log(f"timing the CPU oracle on {workers} processes")
+        rec["cpu_baseline"] = cpu_baseline_ncore(ws, m, workers)
+        rec["cpu_baseline_1core"] = one
     else:
         rec["cpu_baseline"] = None
     print(json.dumps(rec), flush=True)

@@ -21,45 +21,92 @@ __global__ void bounds_init_kernel(long long* keys) {
 }
 
 template <typename CT>
-__global__ __launch_bounds__(256) void bounds_reduce_kernel(const void* x, const void* y, int64_t n, long long* keys) {
-  __shared__ double red[4][256];
-  double xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const double vx = (double)ld<CT>(x, i);
-    const double vy = (double)ld<CT>(y, i);
-    if (__builtin_isfinite(vx)) {
-      xmn = vx < xmn ? vx : xmn;
-      xmx = vx > xmx ? vx : xmx;
-    }
-    if (__builtin_isfinite(vy)) {
-      ymn = vy < ymn ? vy : ymn;
-      ymx = vy > ymx ? vy : ymx;
-    }
+__device__ __forceinline__ void minmax_finite(CT v, CT& mn, CT& mx) {
+  if (__builtin_isfinite(v)) {
+    mn = v < mn ? v : mn;
+    mx = v > mx ? v : mx;
   }
-  red[0][threadIdx.x] = xmn;
-  red[1][threadIdx.x] = xmx;
-  red[2][threadIdx.x] = ymn;
-  red[3][threadIdx.x] = ymx;
+}
+
+// Grid-stride min/max of the finite values of both columns, in the column
+// type (exact).  With both columns 16-byte aligned, groups of 4 values are
+// read with 16-byte loads, U groups per column in flight per thread; the
+// rest (and unaligned columns) element by element.  Each block reduces
+// across its waves and folds its result into the keys with 4 atomics.
+template <typename CT>
+__global__ __launch_bounds__(256) void bounds_reduce_kernel(const void* x, const void* y, int64_t n, int vec,
+                                                            long long* keys) {
+  __shared__ CT red[4][4];
+  CT xmn = (CT)INFINITY, xmx = (CT)-INFINITY, ymn = (CT)INFINITY, ymx = (CT)-INFINITY;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  int64_t done = 0;
+  if (vec) {
+    constexpr int U = 2;
+    const int64_t nq = n / 4;
+    int64_t q = tid;
+    for (; q + (U - 1) * nth < nq; q += U * nth) {
+      CT vx[U][4], vy[U][4];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        ld4v<CT>(x, 4 * (q + u * nth), vx[u]);
+        ld4v<CT>(y, 4 * (q + u * nth), vy[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          minmax_finite(vx[u][e], xmn, xmx);
+          minmax_finite(vy[u][e], ymn, ymx);
+        }
+    }
+    for (; q < nq; q += nth) {
+      CT vx[4], vy[4];
+      ld4v<CT>(x, 4 * q, vx);
+      ld4v<CT>(y, 4 * q, vy);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        minmax_finite(vx[e], xmn, xmx);
+        minmax_finite(vy[e], ymn, ymx);
+      }
+    }
+    done = 4 * nq;
+  }
+  for (int64_t i = done + tid; i < n; i += nth) {
+    minmax_finite(ld<CT>(x, i), xmn, xmx);
+    minmax_finite(ld<CT>(y, i), ymn, ymx);
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const CT a = __shfl_xor(xmn, o), b = __shfl_xor(xmx, o), c = __shfl_xor(ymn, o), d = __shfl_xor(ymx, o);
+    xmn = a < xmn ? a : xmn;
+    xmx = b > xmx ? b : xmx;
+    ymn = c < ymn ? c : ymn;
+    ymx = d > ymx ? d : ymx;
+  }
+  const int wid = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][wid] = xmn;
+    red[1][wid] = xmx;
+    red[2][wid] = ymn;
+    red[3][wid] = ymx;
+  }
   __syncthreads();
-  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) {
-      const int t = threadIdx.x;
-      red[0][t] = red[0][t + off] < red[0][t] ? red[0][t + off] : red[0][t];
-      red[1][t] = red[1][t + off] > red[1][t] ? red[1][t + off] : red[1][t];
-      red[2][t] = red[2][t + off] < red[2][t] ? red[2][t + off] : red[2][t];
-      red[3][t] = red[3][t + off] > red[3][t] ? red[3][t + off] : red[3][t];
-    }
-    __syncthreads();
-  }
   // -0 and +0 compare equal above; totalOrder keys pick -0 for the minimum
   // and +0 for the maximum only when that value was seen, which cannot move
   // any particle across a bin edge (both are the same coordinate).
   if (threadIdx.x == 0) {
-    atomicMin(keys + 0, fkey(red[0][0]));
-    atomicMax(keys + 1, fkey(red[1][0]));
-    atomicMin(keys + 2, fkey(red[2][0]));
-    atomicMax(keys + 3, fkey(red[3][0]));
+    const int nw = (int)(blockDim.x >> 6);
+    for (int w = 1; w < nw; ++w) {
+      xmn = red[0][w] < xmn ? red[0][w] : xmn;
+      xmx = red[1][w] > xmx ? red[1][w] : xmx;
+      ymn = red[2][w] < ymn ? red[2][w] : ymn;
+      ymx = red[3][w] > ymx ? red[3][w] : ymx;
+    }
+    atomicMin(keys + 0, fkey((double)xmn));
+    atomicMax(keys + 1, fkey((double)xmx));
+    atomicMin(keys + 2, fkey((double)ymn));
+    atomicMax(keys + 3, fkey((double)ymx));
   }
 }
 
@@ -70,13 +117,15 @@ hipError_t launch_bounds(const void* x, const void* y, bool coord_f64, int64_t n
   if (tm) tm->end("bounds_init_kernel", s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t want = (n + 4095) / 4096;
-  const int grid = (int)(want < 1 ? 1 : (want > (int64_t)cus * 4 ? (int64_t)cus * 4 : want));
+  // One block per 8192 values, at most 8 per CU.
+  const int64_t want = (n + 8191) / 8192;
+  const int grid = (int)(want < 1 ? 1 : (want > (int64_t)cus * 8 ? (int64_t)cus * 8 : want));
+  const int vec = (reinterpret_cast<uintptr_t>(x) % 16 == 0 && reinterpret_cast<uintptr_t>(y) % 16 == 0) ? 1 : 0;
   if (tm) tm->begin(s);
   if (coord_f64)
-    hipLaunchKernelGGL((bounds_reduce_kernel<double>), dim3(grid), dim3(256), 0, s, x, y, n, keys);
+    hipLaunchKernelGGL((bounds_reduce_kernel<double>), dim3(grid), dim3(256), 0, s, x, y, n, vec, keys);
   else
-    hipLaunchKernelGGL((bounds_reduce_kernel<float>), dim3(grid), dim3(256), 0, s, x, y, n, keys);
+    hipLaunchKernelGGL((bounds_reduce_kernel<float>), dim3(grid), dim3(256), 0, s, x, y, n, vec, keys);
   if (tm) tm->end("bounds_reduce_kernel", s);
   return hipGetLastError();
 }
