@@ -275,9 +275,19 @@ int bin_graph_destroy(bin_graph* graph);
 
 /* ---- autotuning ------------------------------------------------------------ */
 /* Time the candidate kernel configurations for requests shaped like
- * reqs[0..count) and remember the fastest per shape class (in memory, and in
- * the JSON file named by the environment variable BIN_TUNE_CACHE if set).
- * Runs kernels on a private stream and synchronises it; it overwrites the
+ * reqs[0..count) and remember the fastest per (device, shape class).  The
+ * candidates include the strategy itself where both apply (whole grid in
+ * LDS, tile partition), the tile size, the scatter shape and the gather
+ * form.  The table is kept in memory
+ * and, if the environment variable BIN_TUNE_CACHE names a file, read from
+ * and written back to it as JSON:
+ *   {"version": 1, "entries": {"gfx950:256|n20_b16_k1_c0_a0_o31":
+ *     {"strategy": 2, "block": 0, "grid": 0, "part_wg": 512,
+ *      "scatter_ppt": 16, "scatter_threads": 1024, "tile_shift": 13,
+ *      "split_len": 0, "quads": 2}, ...}}
+ * (key: device architecture and compute units, then log2 of n and of the
+ * bin count, attributes, coordinate and attribute dtypes, ops).  Runs
+ * kernels on a private stream and synchronises it; it overwrites the
  * requests' output buffers.  Without tuning data the built-in rules apply. */
 int bin_autotune(const bin_request* reqs, int32_t count);
 
@@ -350,10 +360,16 @@ int bin_describe_plan_on(const bin_request* req, int32_t cus, int64_t lds_per_bl
 
 /* ---- serving --------------------------------------------------------------- */
 /* A request server with continuous batching: binsrv_submit may be called
- * from any thread while earlier requests run; a dispatcher thread admits
- * waiting requests as soon as a stream slot and enough device memory (the
- * budget) are free, runs each admitted group as one batched launch, and keeps
- * each result grid resident on the device until binsrv_release. */
+ * from any thread while earlier requests run.  Waiting requests are admitted
+ * in arrival order as soon as a stream slot and enough device memory (the
+ * budget: result grids plus the library scratch of the batch as it will run)
+ * are free - by binsrv_submit itself when a slot is free, else when a batch
+ * finishes or grids are released - and each admitted group runs as one
+ * batched launch on its slot's stream (a lone request runs the
+ * single-request kernels).  Each slot has a waiter thread blocked on the
+ * slot's completion event, which stamps the requests done.  Result grids
+ * stay resident on the device until binsrv_release.  Device memory is
+ * allocated outside the server's lock. */
 typedef struct binsrv binsrv;
 typedef struct binsrv_config {
   uint64_t budget_bytes;   /* device memory for result grids and scratch    */
@@ -365,7 +381,11 @@ typedef struct binsrv_config {
 
 /* A server request: like bin_request but without outputs; the server
  * allocates the result grids (all five op kinds as requested, with the
- * default precision rules) from its budget. */
+ * default precision rules) from its budget.  producer_stream: the stream
+ * (hipStream_t as void*) whose work writes the input columns, or NULL when
+ * they are complete on the device before binsrv_submit.  The server records
+ * an event on it at submit time and its kernels read the columns only after
+ * that event, so a simulation may enqueue its writes and submit at once. */
 typedef struct binsrv_request {
   bin_columns coords;
   bin_columns attrs;
@@ -374,6 +394,7 @@ typedef struct binsrv_request {
   double bounds[4];
   int32_t nx, ny;
   uint32_t ops;
+  void* producer_stream;
 } binsrv_request;
 
 /* Where a finished request's resident grids are (device pointers owned by
@@ -397,16 +418,24 @@ typedef struct binsrv_stats {
 } binsrv_stats;
 
 int binsrv_create(const binsrv_config* cfg, binsrv** srv);
-/* Queue a request.  Inputs are borrowed until the request completes.
- * Returns BIN_ERR_ADMISSION if it can never fit the budget. */
+/* Queue a request (and launch it at once when a slot and memory are free).
+ * Inputs are borrowed until the request completes; they must be complete on
+ * the device before submit, or written on req->producer_stream.  Returns
+ * BIN_ERR_ADMISSION if it can never fit the budget.  A request whose result
+ * grids cannot be allocated fails alone (BIN_ERR_OOM from binsrv_wait). */
 int binsrv_submit(binsrv* srv, const binsrv_request* req, uint64_t* ticket);
 /* Wait up to timeout_ns (negative = forever) for a ticket's completion;
- * fills *result.  BIN_ERR_TIMEOUT if it is not done in time. */
+ * fills *result and returns the request's status.  BIN_ERR_TIMEOUT if it is
+ * not done in time.  Safe to call while another thread destroys the server:
+ * the call then either fails with BIN_ERR_INVALID_ARG or completes before
+ * the server is freed. */
 int binsrv_wait(binsrv* srv, uint64_t ticket, int64_t timeout_ns, bin_result* result);
 /* Return a finished request's grids to the server's pool. */
 int binsrv_release(binsrv* srv, uint64_t ticket);
 int binsrv_get_stats(binsrv* srv, binsrv_stats* stats);
-/* Drain in-flight work, free every grid and stop the dispatcher. */
+/* Drain waiting and in-flight work, free every grid and stop the slot
+ * waiters.  Calls made concurrently on the same server either fail with
+ * BIN_ERR_INVALID_ARG or finish before it is freed. */
 int binsrv_destroy(binsrv* srv);
 
 #ifdef __cplusplus

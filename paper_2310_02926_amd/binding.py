@@ -60,7 +60,8 @@ class ServerConfig(ctypes.Structure):
 
 class ServerRequest(ctypes.Structure):
     _fields_ = [("coords", Columns), ("attrs", Columns), ("n", c_int64), ("axes", c_int32 * 2),
-                ("bounds", c_double * 4), ("nx", c_int32), ("ny", c_int32), ("ops", c_uint32)]
+                ("bounds", c_double * 4), ("nx", c_int32), ("ny", c_int32), ("ops", c_uint32),
+                ("producer_stream", c_void_p)]
 
 
 class GridSpec(ctypes.Structure):
@@ -469,10 +470,13 @@ class Server:
         check(lib().binsrv_create(ctypes.byref(cfg), ctypes.byref(self._h)))
         self._keep = {}
 
-    def submit(self, coords, attrs, n, axes, bounds, nx, ny, ops) -> int:
+    def submit(self, coords, attrs, n, axes, bounds, nx, ny, ops, producer_stream=None) -> int:
+        """Queue a request; ``producer_stream`` (a torch stream or handle)
+        is the stream whose queued work writes the columns, if any."""
         c, ck = columns(coords)
         a, ak = columns(attrs) if attrs else (Columns(None, 0, BIN_F32), None)
-        req = ServerRequest(c, a, n, (c_int32 * 2)(*axes), (c_double * 4)(*bounds), nx, ny, ops)
+        ps = None if producer_stream is None else _stream_handle(producer_stream)
+        req = ServerRequest(c, a, n, (c_int32 * 2)(*axes), (c_double * 4)(*bounds), nx, ny, ops, ps)
         t = c_uint64()
         check(lib().binsrv_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
         self._keep[t.value] = (coords, attrs, ck, ak, (nx, ny, ops, len(attrs or [])))

@@ -204,6 +204,12 @@ int device_info(DeviceInfo* info) {
   d.cus = p.multiProcessorCount;
   d.lds_per_block = p.sharedMemPerBlock;
   d.lds_per_cu = p.maxSharedMemoryPerMultiProcessor ? p.maxSharedMemoryPerMultiProcessor : p.sharedMemPerBlock;
+  {
+    std::string arch = p.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);  // drop feature flags
+    snprintf(d.arch, sizeof d.arch, "%s:%d", arch.c_str(), d.cus);
+  }
   // Dynamic LDS beyond the default needs an explicit opt-in per kernel.
   e = bk::set_lds_limit(d.lds_per_block);
   if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(max dynamic LDS)");

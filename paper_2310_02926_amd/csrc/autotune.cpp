@@ -1,12 +1,20 @@
-// Autotuner: times candidate launch configurations for representative
-// requests and remembers the fastest per shape class.  The planner looks the
-// class up whenever the caller set no explicit override.
+// Autotuner: times candidate launch configurations - including the
+// strategy itself (whole grid in LDS or tile partition) where both apply -
+// for representative requests and remembers the
+// fastest per (device, shape class).  The planner looks the class up
+// whenever the caller set no explicit override.
 //
 // Shape class: log2 buckets of n and of the bin count, attribute count,
-// coordinate and attribute types, precision and op mask.  The table lives in
-// memory and, when the environment variable BIN_TUNE_CACHE names a file, is
-// loaded from and saved to that file (one "key value..." line per class).
+// coordinate and attribute types and the op mask (precision flags included).
+// The table lives in memory and, when the environment variable
+// BIN_TUNE_CACHE names a file, is loaded from and saved to that file as JSON:
+//   {"version": 1, "entries": {"<device>|<class>": {"strategy": s, "block": b,
+//    "grid": g, "part_wg": w, "scatter_ppt": p, "scatter_threads": t,
+//    "tile_shift": h, "split_len": l, "quads": q}, ...}}
+// where <device> is the device's architecture name and compute-unit count,
+// so one file can hold the tunings of several kinds of GPU.
 #include <algorithm>
+#include <cctype>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -37,15 +45,105 @@ int log2_bucket(int64_t v) {
   return b;
 }
 
-std::string class_key(const bin_request& r) {
+std::string class_key(const bin_request& r, const DeviceInfo& dev) {
   const int k = r.attrs.cols ? r.attrs.ncols : 0;
-  char buf[128];
-  snprintf(buf, sizeof buf, "n%d_b%d_k%d_c%d_a%d_o%u", log2_bucket(r.n), log2_bucket((int64_t)r.nx * r.ny), k,
-           r.coords.dtype, k ? r.attrs.dtype : 0, r.ops);
+  char buf[192];
+  snprintf(buf, sizeof buf, "%s|n%d_b%d_k%d_c%d_a%d_o%u", dev.arch[0] ? dev.arch : "unknown", log2_bucket(r.n),
+           log2_bucket((int64_t)r.nx * r.ny), k, r.coords.dtype, k ? r.attrs.dtype : 0, r.ops);
   return buf;
 }
 
 const char* cache_path() { return getenv("BIN_TUNE_CACHE"); }
+
+// The fields of a tuning entry, in file order.
+struct Field {
+  const char* name;
+  int64_t PlanHints::*i64;
+  int PlanHints::*i32;
+};
+const Field kFields[] = {{"strategy", nullptr, &PlanHints::force_strategy},
+                         {"block", nullptr, &PlanHints::block},
+                         {"grid", nullptr, &PlanHints::grid},
+                         {"part_wg", nullptr, &PlanHints::part_wg},
+                         {"scatter_ppt", nullptr, &PlanHints::scatter_ppt},
+                         {"scatter_threads", nullptr, &PlanHints::scatter_threads},
+                         {"tile_shift", nullptr, &PlanHints::tile_shift},
+                         {"split_len", &PlanHints::split_len, nullptr},
+                         {"quads", nullptr, &PlanHints::quads}};
+
+// A small reader for the cache's own JSON layout: string keys, objects and
+// integers only.  Anything else makes the file count as empty.
+struct JsonIn {
+  const std::string& t;
+  size_t i = 0;
+  void ws() {
+    while (i < t.size() && std::isspace((unsigned char)t[i])) ++i;
+  }
+  bool eat(char c) {
+    ws();
+    if (i < t.size() && t[i] == c) {
+      ++i;
+      return true;
+    }
+    return false;
+  }
+  bool str(std::string& out) {
+    if (!eat('"')) return false;
+    out.clear();
+    while (i < t.size() && t[i] != '"') {
+      if (t[i] == '\\') return false;  // the writer never escapes
+      out += t[i++];
+    }
+    return i++ < t.size();
+  }
+  bool num(long long& v) {
+    ws();
+    const char* b = t.c_str() + i;
+    char* e = nullptr;
+    v = std::strtoll(b, &e, 10);
+    if (e == b) return false;
+    i += (size_t)(e - b);
+    return true;
+  }
+  bool entry(PlanHints& h) {
+    if (!eat('{')) return false;
+    if (eat('}')) return true;
+    do {
+      std::string name;
+      long long v = 0;
+      if (!str(name) || !eat(':') || !num(v)) return false;
+      for (const Field& f : kFields)
+        if (name == f.name) {
+          if (f.i64) h.*(f.i64) = v;
+          else h.*(f.i32) = (int)v;
+        }
+    } while (eat(','));
+    return eat('}');
+  }
+  bool file(std::map<std::string, PlanHints>& out) {
+    if (!eat('{')) return false;
+    do {
+      std::string name;
+      if (!str(name) || !eat(':')) return false;
+      if (name == "entries") {
+        if (!eat('{')) return false;
+        if (!eat('}')) {
+          do {
+            std::string key;
+            PlanHints h;
+            if (!str(key) || !eat(':') || !entry(h)) return false;
+            out[key] = h;
+          } while (eat(','));
+          if (!eat('}')) return false;
+        }
+      } else {
+        long long v;
+        if (!num(v)) return false;
+      }
+    } while (eat(','));
+    return eat('}');
+  }
+};
 
 void load_locked() {
   if (g_tune_loaded) return;
@@ -53,29 +151,33 @@ void load_locked() {
   const char* p = cache_path();
   if (!p) return;
   std::ifstream f(p);
-  std::string line;
-  while (std::getline(f, line)) {
-    std::istringstream is(line);
-    std::string key;
-    PlanHints h;
-    long long split = 0;
-    if (is >> key >> h.force_strategy >> h.block >> h.grid >> h.part_wg >> h.scatter_ppt >> h.scatter_threads >>
-        h.tile_shift >> split) {
-      h.split_len = split;
-      g_tune[key] = h;
-    }
-  }
+  if (!f) return;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string text = ss.str();
+  std::map<std::string, PlanHints> m;
+  JsonIn in{text};
+  if (in.file(m))
+    for (auto& kv : m) g_tune[kv.first] = kv.second;
 }
 
 void save_locked() {
   const char* p = cache_path();
   if (!p) return;
   std::ofstream f(p, std::ios::trunc);
+  f << "{\"version\": 1, \"entries\": {";
+  bool first = true;
   for (auto& kv : g_tune) {
+    f << (first ? "\n  " : ",\n  ") << '"' << kv.first << "\": {";
+    first = false;
     const PlanHints& h = kv.second;
-    f << kv.first << ' ' << h.force_strategy << ' ' << h.block << ' ' << h.grid << ' ' << h.part_wg << ' '
-      << h.scatter_ppt << ' ' << h.scatter_threads << ' ' << h.tile_shift << ' ' << (long long)h.split_len << '\n';
+    for (size_t j = 0; j < sizeof kFields / sizeof kFields[0]; ++j) {
+      const Field& fd = kFields[j];
+      f << (j ? ", " : "") << '"' << fd.name << "\": " << (fd.i64 ? (long long)(h.*(fd.i64)) : (long long)(h.*(fd.i32)));
+    }
+    f << '}';
   }
+  f << "\n}}\n";
 }
 
 bool is_default(const PlanHints& h) {
@@ -87,11 +189,12 @@ bool is_default(const PlanHints& h) {
 
 // Hints for a request: the caller's explicit override if any, else the
 // tuned entry of its shape class, else defaults.
-PlanHints effective_hints(const bin_request& r, const PlanHints& explicit_hints) {
+PlanHints effective_hints(const bin_request& r, const DeviceInfo& dev, const PlanHints& explicit_hints) {
   if (!is_default(explicit_hints)) return explicit_hints;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   load_locked();
-  auto it = g_tune.find(class_key(r));
+  if (g_tune.empty()) return explicit_hints;
+  auto it = g_tune.find(class_key(r, dev));
   return it == g_tune.end() ? explicit_hints : it->second;
 }
 
@@ -140,9 +243,14 @@ int autotune(const bin_request* reqs, int count) {
     Prepared p;
     st = prepare(r, dev, PlanHints{}, nullptr, &p);
     if (st) break;
+    // The strategy is a candidate like any other setting: a grid that fits
+    // LDS whole is also timed as a tile partition (the reverse is not
+    // possible).  The global-atomic strategy is left to the planner's rule
+    // (grids beyond the tile limit): batches and graphs take the other two.
     std::vector<PlanHints> cands;
     PlanHints base;
     cands.push_back(base);
+    const int64_t nb = (int64_t)r.nx * r.ny;
     if (p.cfg.strategy == bk::STRAT_LDS) {
       for (int block : {256, 512, 1024})
         for (int g : {0, cus / 2, cus, 2 * cus, 4 * cus}) {
@@ -152,22 +260,30 @@ int autotune(const bin_request* reqs, int count) {
           h.grid = g;
           cands.push_back(h);
         }
-    } else if (p.cfg.strategy == bk::STRAT_PART) {
-      const int smax = p.part.lay.tile_shift;
-      for (int sh : {smax, smax - 1})
-        for (int nt : {512, 1024})
-          for (int ppt : {4, 8, 16})
-            for (int wg : {cus, 2 * cus, 4 * cus}) {
-              if (sh < 6) continue;
+    }
+    // tile sizes up to the largest that fits LDS (the plan's own choice for
+    // a partition request, else the smallest power of two holding the grid)
+    int smax = 6;
+    if (p.cfg.strategy == bk::STRAT_PART) smax = p.part.lay.tile_shift;
+    else
+      while (smax < 15 && ((int64_t)1 << smax) < nb) ++smax;
+    for (int sh : {smax, smax - 1, smax - 2})
+      for (int nt : {512, 1024})
+        for (int ppt : {4, 8, 16})
+          for (int wg : {cus, 2 * cus, 4 * cus})
+            for (int q : {0, 1, 2}) {
+              if (sh < 6 || (int64_t)1 << sh > 2 * nb) continue;
+              if (q && (ppt != 16 || nt != 1024 || wg != 2 * cus)) continue;  // quads: one shape
               PlanHints h;
               h.force_strategy = bk::STRAT_PART;
               h.tile_shift = sh;
               h.scatter_threads = nt;
               h.scatter_ppt = ppt;
               h.part_wg = wg;
+              h.quads = q;
               cands.push_back(h);
             }
-    }
+
     float best = 1e30f;
     PlanHints best_h = base;
     for (const PlanHints& h : cands) {
@@ -186,7 +302,7 @@ int autotune(const bin_request* reqs, int count) {
     if (st == BIN_OK) {
       std::lock_guard<std::mutex> lk(g_tune_mu);
       load_locked();
-      g_tune[class_key(r)] = best_h;
+      g_tune[class_key(r, dev)] = best_h;
     }
   }
   (void)hipStreamSynchronize(s);

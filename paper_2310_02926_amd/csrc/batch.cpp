@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <tuple>
 #include <unordered_map>
@@ -29,12 +30,24 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 struct PartGroup {
   bool cf64 = false, af64 = false;
   int prec = 0;
+  int nt = 1024, ppt = 8;  // scatter shape shared by the group
+  bool quads = false;      // runs padded to quads, gathered a quad per lane
   std::vector<int> idx;              // request indices
   std::vector<bk::PartArgs> args;    // patched records
   bk::PartCfg cfg{};
   bk::PartBatch b{};
   size_t desc_off = 0, map_wg_off = 0, map_walk_off = 0, map_item_off = 0, map_tile_off = 0;
   std::vector<uint32_t> map_wg, map_walk, map_item, map_tile;
+  // Persistent launch (1024-thread scatter shapes): the work list, its
+  // control words, and the LDS group it also runs (index, or -1).
+  bool persist = false;
+  int lds_group = -1;
+  std::vector<uint32_t> items;
+  size_t items_off = 0;
+  uint32_t* ctl = nullptr;
+  uint32_t ctl_words = 0;
+  size_t persist_lds = 0;
+  bk::PersistBatch pb{};
 };
 
 struct LdsGroup {
@@ -47,6 +60,7 @@ struct LdsGroup {
   bk::LdsBatch b{};
   size_t desc_off = 0, map_slot_off = 0, map_merge_off = 0;
   std::vector<uint32_t> map_slot, map_merge;
+  bool in_persist = false;  // run by a partition group's persistent launch
 };
 
 }  // namespace
@@ -65,12 +79,16 @@ namespace {
 
 // Pass 1 (base == nullptr) sizes everything; pass 2 lays out pointers.
 int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const PlanHints& hints,
-               unsigned char* base, BatchPlan* bp) {
+               unsigned char* base, BatchPlan* bp, bool allow_persist = true) {
   bp->preps.assign(nreq, Prepared{});
   bp->part.clear();
   bp->lds.clear();
   bp->global_reqs.clear();
-  std::map<std::tuple<int, int, int, int>, int> gmap;
+  // Groups: strategy and types, and for tile partitions the scatter shape
+  // and gather form each request's own plan chose (one launch serves one
+  // shape; requests of different shapes go to different groups rather than
+  // all taking the smallest shape).
+  std::map<std::tuple<int, int, int, int, int, int, int>, int> gmap;
   for (int i = 0; i < nreq; ++i) {
     Prepared& p = bp->preps[i];
     int st = prepare(reqs[i], dev, hints, nullptr, &p);
@@ -80,7 +98,21 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
       bp->global_reqs.push_back(i);
       continue;
     }
-    auto key = std::make_tuple(strat, (int)p.coord_f64, (int)p.attr_f64, p.prec);
+    int nt = 0, ppt = 0, quads = 0;
+    if (strat == bk::STRAT_PART) {
+      nt = p.pcfg.scatter_threads;
+      ppt = p.pcfg.ppt;
+      // The table-driven scatter needs a few more registers than the single
+      // one: at most 8 particles per thread at 1024 threads.
+      if (nt >= 1024) ppt = std::min(ppt, 8);
+      bk::PartArgs a = p.part;
+      set_part_blocks(a, nt, ppt);
+      quads = (p.part.quads && use_quads(a.k, p.attr_f64, a.ntiles, (int64_t)nt * ppt) &&
+               (uint64_t)a.n + 3ull * (uint64_t)a.nwg * (uint64_t)a.nbpw <= 0xFFFFFFFFull)
+                  ? 1
+                  : 0;
+    }
+    auto key = std::make_tuple(strat, (int)p.coord_f64, (int)p.attr_f64, p.prec, nt, ppt, quads);
     auto it = gmap.find(key);
     if (it == gmap.end()) {
       if (strat == bk::STRAT_PART) {
@@ -88,6 +120,9 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
         g.cf64 = p.coord_f64;
         g.af64 = p.attr_f64;
         g.prec = p.prec;
+        g.nt = nt;
+        g.ppt = ppt;
+        g.quads = quads != 0;
         bp->part.push_back(g);
         it = gmap.emplace(key, (int)bp->part.size() - 1).first;
       } else {
@@ -114,35 +149,31 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
     const int R = (int)g.idx.size();
     if (R > 65535) return fail(BIN_ERR_UNSUPPORTED, "a batch group holds at most 65535 requests");
     g.args.resize(R);
-    // One scatter shape for the whole group: the smallest PPT any request
-    // needs, staged values sized for the largest request.
-    int ppt = 32, nt = 1024;
+    // The group's scatter shape; staged values sized for the largest request.
+    const int ppt = g.ppt, nt = g.nt;
     size_t bin_lds = 16;
     int bin_block = 256;
     size_t asz = g.af64 ? 8 : 4;
     for (int r = 0; r < R; ++r) {
       const Prepared& p = bp->preps[g.idx[r]];
-      ppt = std::min(ppt, p.pcfg.ppt);
-      nt = std::min(nt, p.pcfg.scatter_threads);
       bin_lds = std::max(bin_lds, p.pcfg.bin_lds);
       bin_block = std::max(bin_block, p.pcfg.bin_block);
     }
-    // The table-driven scatter needs a few more registers than the single
-    // one: 8 particles per thread at 1024 threads.
-    if (nt >= 1024) ppt = std::min(ppt, 8);
     const size_t S = (size_t)nt * ppt;
-    // Per request: tile counters, record stage and values, then its staged
-    // rows of the run table; the launch takes the largest.
+    // Per request: tile counters, record stage (with quad padding) and
+    // values, then its staged rows of the run table; the launch takes the
+    // largest.
     size_t scatter_lds = 16;
     for (int r = 0; r < R; ++r) {
       bk::PartArgs a = bp->preps[g.idx[r]].part;
       set_part_blocks(a, nt, ppt);
-      const size_t SP = S;  // batches gather record by record: no padding
+      const size_t SP = S + (g.quads ? part_pad_row(a.ntiles, (int64_t)S) : 0);
       const size_t sv = al16(16 * (size_t)a.ntiles + 2 * SP);
       scatter_lds = std::max(scatter_lds, set_off_stage(a, sv + (a.k ? SP * asz : 0), dev.lds_per_block - 256));
     }
     g.cfg.ppt = ppt;
     g.cfg.scatter_threads = nt;
+    g.cfg.quads = g.quads ? 1 : 0;
     g.cfg.scatter_lds = scatter_lds;
     g.cfg.bin_lds = bin_lds;
     g.cfg.bin_block = bin_block;
@@ -154,9 +185,9 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
     for (int r = 0; r < R; ++r) {
       bk::PartArgs a = bp->preps[g.idx[r]].part;
       set_part_blocks(a, nt, ppt);
-      a.quads = 0;
-      a.pad_row = 0;
-      const size_t SP = S;
+      a.quads = g.quads ? 1 : 0;
+      a.pad_row = g.quads ? part_pad_row(a.ntiles, (int64_t)S) : 0;
+      const size_t SP = S + a.pad_row;
       const size_t nrec = part_records(a);
       a.stage_val_off = (int32_t)al16(16 * (size_t)a.ntiles + 2 * SP);
       set_off_stage(a, a.stage_val_off + (a.k ? SP * asz : 0), dev.lds_per_block - 256);
@@ -217,6 +248,62 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
     g.b.n_slot_blocks = (int32_t)g.map_slot.size();
     g.b.n_merge_blocks = (int32_t)g.map_merge.size();
   }
+  // --- persistent launches: a partition group whose scatter runs 1024
+  // threads takes every stage of its requests in one launch, together with
+  // the LDS requests of the same types.  Work list in dependency order,
+  // larger requests first within each stage.
+  for (auto& g : bp->part) {
+    g.persist = allow_persist && g.nt == 1024 && (g.ppt == 4 || g.ppt == 8);
+    if (!g.persist) continue;
+    g.lds_group = -1;
+    for (size_t li = 0; li < bp->lds.size(); ++li) {
+      LdsGroup& lg = bp->lds[li];
+      if (!lg.in_persist && lg.cf64 == g.cf64 && lg.af64 == g.af64 && lg.prec == g.prec && lg.block <= 1024) {
+        lg.in_persist = true;
+        g.lds_group = (int)li;
+        break;
+      }
+    }
+    const LdsGroup* lg = g.lds_group >= 0 ? &bp->lds[g.lds_group] : nullptr;
+    const int R = (int)g.args.size();
+    const int RL = lg ? (int)lg->args.size() : 0;
+    auto item = [&](int kind, int r, uint32_t i) {
+      g.items.push_back(((uint32_t)kind << 24) | (uint32_t)r);
+      g.items.push_back(i);
+    };
+    // requests by size, largest first (partition: r, LDS: R + r)
+    std::vector<int> order;
+    for (int r = 0; r < R + RL; ++r) order.push_back(r);
+    auto n_of = [&](int r) { return r < R ? g.args[r].n : lg->args[r - R].n; };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return n_of(x) > n_of(y); });
+    g.items.clear();
+    for (int r : order) {
+      if (r < R)
+        for (int w = 0; w < g.args[r].nwg; ++w) item(bk::PK_SCATTER, r, (uint32_t)w);
+      else
+        for (int c = 0; c < lg->args[r - R].nslots; ++c) item(bk::PK_LDS, r - R, (uint32_t)c);
+    }
+    for (int r : order)
+      if (r < R)
+        for (int b = 0; b < (g.args[r].ntiles + 15) / 16; ++b) item(bk::PK_WALK, r, (uint32_t)b);
+    for (int r : order)
+      if (r < R) item(bk::PK_PLACE, r, 0u);
+    for (int r : order)
+      if (r < R)
+        for (int i = 0; i < g.args[r].max_items; ++i) item(bk::PK_BIN, r, (uint32_t)i);
+    for (int r : order)
+      if (r < R)
+        for (int b = 0; b < g.args[r].merge_blocks; ++b) item(bk::PK_MERGE, r, (uint32_t)b);
+    g.ctl_words = 2 + 4 * (uint32_t)R + (uint32_t)RL;
+    g.ctl = reinterpret_cast<uint32_t*>(take(4 * (size_t)g.ctl_words));
+    // LDS: the largest stage of any item (the merge and placement
+    // workspaces included).
+    size_t lds = std::max({g.cfg.scatter_lds, g.cfg.bin_lds, (size_t)(4 * (16 + 4096)), (size_t)(16 * 64 * 28)});
+    if (lg) lds = std::max(lds, lg->lds_bytes);
+    g.persist_lds = lds;
+    if (lds + 256 > dev.lds_per_block) g.persist = false;
+    if (!g.persist && lg) bp->lds[g.lds_group].in_persist = false;
+  }
   // --- tables: descriptors and maps, one upload
   size_t t = 0;
   auto tab = [&](size_t bytes) {
@@ -230,6 +317,7 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
     g.map_walk_off = tab(4 * g.map_walk.size());
     g.map_item_off = tab(4 * g.map_item.size());
     g.map_tile_off = tab(4 * g.map_tile.size());
+    if (g.persist) g.items_off = tab(4 * g.items.size());
   }
   for (auto& g : bp->lds) {
     g.desc_off = tab(sizeof(bk::LdsArgs) * g.args.size());
@@ -263,16 +351,35 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
     g.b.map_slot = reinterpret_cast<const uint32_t*>(tdev + g.map_slot_off);
     g.b.map_merge = reinterpret_cast<const uint32_t*>(tdev + g.map_merge_off);
   }
+  for (auto& g : bp->part) {
+    if (!g.persist) continue;
+    std::memcpy(h + g.items_off, g.items.data(), 4 * g.items.size());
+    bk::PersistBatch& pb = g.pb;
+    pb.part = g.b.descs;
+    pb.lds = g.lds_group >= 0 ? bp->lds[g.lds_group].b.descs : nullptr;
+    pb.items = reinterpret_cast<const uint32_t*>(tdev + g.items_off);
+    pb.ctl = g.ctl;
+    pb.nitems = (uint32_t)(g.items.size() / 2);
+    pb.npart = (int32_t)g.args.size();
+    pb.nlds = g.lds_group >= 0 ? (int32_t)bp->lds[g.lds_group].args.size() : 0;
+    pb.wait_ticks = 200000000;  // 2 s of the 100 MHz clock: far beyond any batch
+  }
   return BIN_OK;
 }
 
 // Kernel launches of a laid-out batch (tables already on the device).
-int launch_batch(const BatchPlan& bp, hipStream_t s, bk::KTimer* tm) {
+int launch_batch(const BatchPlan& bp, hipStream_t s, bk::KTimer* tm, int cus) {
   for (const auto& g : bp.part) {
-    hipError_t e = bk::launch_partition_batch(g.b, g.cf64, g.af64, g.prec, g.cfg, s, tm);
+    hipError_t e;
+    if (g.persist)
+      e = bk::launch_persist(g.pb, g.ctl_words, g.cf64, g.af64, g.prec, g.ppt, g.quads,
+                             std::max(1, std::min(cus, (int)g.pb.nitems)), g.persist_lds, s, tm);
+    else
+      e = bk::launch_partition_batch(g.b, g.cf64, g.af64, g.prec, g.cfg, s, tm);
     if (e != hipSuccess) return hip_fail(e, "launch batched partition kernels");
   }
   for (const auto& g : bp.lds) {
+    if (g.in_persist) continue;
     hipError_t e = bk::launch_lds_batch(g.b, g.cf64, g.af64, g.prec, g.lds_bytes, g.block, s, tm);
     if (e != hipSuccess) return hip_fail(e, "launch batched LDS kernels");
   }
@@ -293,29 +400,59 @@ int validate_requests(const bin_request* reqs, int nreq) {
   return BIN_OK;
 }
 
-// Pinned staging for table uploads, one buffer per stream; an event marks
-// when the previous upload from it has finished.
-struct Stage {
+// Pinned staging for table uploads: per stream a small ring of buffers,
+// each with an event that marks when its last upload has been consumed.  A
+// call takes a buffer whose upload is done (adding one while the ring has
+// fewer than kStageRing), so it does not wait for the stream; only with
+// every buffer of a full ring still in flight does it wait for the oldest.
+// The global lock only finds the stream's ring; each ring has its own lock,
+// so calls on different streams do not wait for each other.
+constexpr size_t kStageRing = 4;
+struct StageBuf {
   void* host = nullptr;
   size_t bytes = 0;
   hipEvent_t done = nullptr;
 };
+struct StreamStage {
+  std::mutex mu;
+  std::vector<StageBuf> ring;
+  size_t next = 0;  // the oldest upload when the ring is full
+};
 std::mutex g_stage_mu;
-std::unordered_map<void*, Stage> g_stages;
+std::unordered_map<void*, std::unique_ptr<StreamStage>> g_stages;
 
 int upload_tables(const BatchPlan& bp, unsigned char* scratch, hipStream_t s) {
   if (bp.tables_bytes == 0) return BIN_OK;
-  std::lock_guard<std::mutex> lk(g_stage_mu);
-  Stage& st = g_stages[(void*)s];
-  hipError_t e;
-  if (st.done) {
-    e = hipEventSynchronize(st.done);  // the buffer may still feed the last upload
-    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize(staging)");
-  } else {
-    e = hipEventCreateWithFlags(&st.done, hipEventDisableTiming);
-    if (e != hipSuccess) return hip_fail(e, "hipEventCreate(staging)");
+  StreamStage* ss;
+  {
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    auto& p = g_stages[(void*)s];
+    if (!p) p = std::make_unique<StreamStage>();
+    ss = p.get();
   }
-  if (st.bytes < bp.tables_bytes) {
+  std::lock_guard<std::mutex> lk(ss->mu);
+  hipError_t e;
+  size_t pick = ss->ring.size();
+  for (size_t i = 0; i < ss->ring.size(); ++i)
+    if (hipEventQuery(ss->ring[i].done) == hipSuccess) {
+      pick = i;
+      if (ss->ring[i].bytes >= bp.tables_bytes) break;
+    }
+  if (pick == ss->ring.size()) {
+    if (ss->ring.size() < kStageRing) {
+      StageBuf b;
+      e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming);
+      if (e != hipSuccess) return hip_fail(e, "hipEventCreate(staging)");
+      ss->ring.push_back(b);
+    } else {
+      pick = ss->next;
+      ss->next = (ss->next + 1) % kStageRing;
+      e = hipEventSynchronize(ss->ring[pick].done);  // every buffer still feeds an upload
+      if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize(staging)");
+    }
+  }
+  StageBuf& st = ss->ring[pick];
+  if (st.bytes < bp.tables_bytes) {  // its last upload is done: safe to replace
     if (st.host) (void)hipHostFree(st.host);
     st.host = nullptr;
     st.bytes = 0;
@@ -333,7 +470,138 @@ int upload_tables(const BatchPlan& bp, unsigned char* scratch, hipStream_t s) {
 
 }  // namespace
 
-int run_batch(const bin_request* reqs, int nreq, hipStream_t s, const PlanHints& hints) {
+// Several grids over one table in one pass over the table: every grid is a
+// tile-partition request with the same slices and sub-chunks of 2048
+// particles (512 threads x 4); one fused scatter stages the union of the
+// columns per sub-chunk in LDS and writes every grid's records, then the
+// rest of the batch's stages run as usual.  Returns false (nothing done)
+// when the requests do not qualify: f32 columns, 2..kMultiGrids grids, all
+// on the partition strategy, at most kMultiCols distinct columns, and the
+// LDS stage fits.
+bool run_multi_fused(const bin_request* reqs, int nreq, hipStream_t s, int* status) {
+  *status = BIN_OK;
+  if (nreq < 2 || nreq > bk::kMultiGrids) return false;
+  const bin_request& r0 = reqs[0];
+  const int k = r0.attrs.cols ? r0.attrs.ncols : 0;
+  if (r0.coords.dtype != BIN_F32 || (k && r0.attrs.dtype != BIN_F32) || r0.n < 1) return false;
+  // union of the columns: each grid's axes, then the shared attributes
+  std::vector<const void*> cols;
+  auto col_index = [&](const void* p) {
+    for (size_t u = 0; u < cols.size(); ++u)
+      if (cols[u] == p) return (int)u;
+    cols.push_back(p);
+    return (int)cols.size() - 1;
+  };
+  bk::MultiScatterArgs m;
+  std::memset(&m, 0, sizeof m);
+  for (int g = 0; g < nreq; ++g) {
+    const bin_request& r = reqs[g];
+    if (r.n != r0.n || r.coords.cols != r0.coords.cols || r.attrs.cols != r0.attrs.cols) return false;
+    m.gx[g] = col_index(r.coords.cols[r.axes[0]]);
+    m.gy[g] = col_index(r.coords.cols[r.axes[1]]);
+  }
+  for (int j = 0; j < k; ++j) m.attr_col[j] = col_index(r0.attrs.cols[j]);
+  if ((int)cols.size() > bk::kMultiCols) return false;
+  DeviceInfo dev;
+  int st = device_info(&dev);
+  if (st) {
+    *status = st;
+    return true;
+  }
+  PlanHints h;
+  h.force_strategy = bk::STRAT_PART;
+  h.scatter_threads = 512;
+  h.scatter_ppt = 4;
+  h.quads = 1;  // record-by-record gather: one launch serves every grid
+  BatchPlan bp;
+  st = plan_batch(reqs, nreq, dev, h, nullptr, &bp);
+  if (st || bp.part.size() != 1 || !bp.lds.empty() || !bp.global_reqs.empty() ||
+      (int)bp.part[0].idx.size() != nreq || bp.part[0].nt != 512 || bp.part[0].ppt != 4)
+    return false;
+  // LDS: staged columns, per grid its counters and staged run-table rows,
+  // the record stage; as many staged rows as fit (a power of two <= 16).
+  const int S = 2048;
+  const PartGroup& g0 = bp.part[0];
+  const size_t limit = dev.lds_per_block - 256;
+  for (int F = 16; F >= 1; F /= 2) {
+    size_t o = al16((size_t)cols.size() * S * 4);
+    m.cols_lds = 0;
+    for (int g = 0; g < nreq; ++g) {
+      const bk::PartArgs& a = g0.args[g];
+      m.grid_lds[g] = (int32_t)o;
+      o = al16(o + 16 * (size_t)a.ntiles);
+      m.grid_ost[g] = (int32_t)o;
+      const int f = std::min(F, std::max(1, (int)a.nbpw));
+      int sh = 0;
+      while ((1 << (sh + 1)) <= f) ++sh;
+      o = al16(o + 2 * ((size_t)a.ntiles + 1) << sh);
+    }
+    m.stage_b = (int32_t)o;
+    o = al16(o + 2 * (size_t)S);
+    m.stage_v = (int32_t)o;
+    o = al16(o + 4 * (size_t)S);
+    if (o <= limit) {
+      m.sub = S;
+      m.ncols = (int32_t)cols.size();
+      m.ngrids = nreq;
+      m.k = k;
+      m.cols_lds = 0;
+      bool vec = true;
+      for (size_t u = 0; u < cols.size(); ++u) {
+        m.cols[u] = static_cast<const float*>(cols[u]);
+        vec = vec && reinterpret_cast<uintptr_t>(cols[u]) % 16 == 0;
+      }
+      m.vec = vec ? 1 : 0;
+      // the staged rows per grid for this F
+      for (int g = 0; g < nreq; ++g) {
+        const int f = std::min(F, std::max(1, (int)g0.args[g].nbpw));
+        int sh = 0;
+        while ((1 << (sh + 1)) <= f) ++sh;
+        bp.part[0].args[g].off_shift = sh;
+      }
+      const size_t lds = o;
+      // lay out the batch with the scratch, then the fused scatter's
+      // arguments after the tables
+      void* scratch = nullptr;
+      const size_t extra = al256(sizeof m);
+      st = scratch_get(dev.device, s, bp.scratch_bytes + extra, &scratch);
+      if (st) {
+        *status = st;
+        return true;
+      }
+      std::vector<int> shifts;
+      for (int g = 0; g < nreq; ++g) shifts.push_back(bp.part[0].args[g].off_shift);
+      st = plan_batch(reqs, nreq, dev, h, static_cast<unsigned char*>(scratch), &bp);
+      if (st) {
+        *status = st;
+        return true;
+      }
+      PartGroup& g = bp.part[0];
+      for (int i = 0; i < nreq; ++i) g.args[i].off_shift = shifts[i];
+      std::memcpy(bp.tables.data() + g.desc_off, g.args.data(), sizeof(bk::PartArgs) * g.args.size());
+      m.grids = g.b.descs;
+      const size_t moff = bp.tables.size();
+      bp.tables.resize(moff + extra, 0);
+      std::memcpy(bp.tables.data() + moff, &m, sizeof m);
+      bp.tables_bytes = bp.tables.size();
+      st = upload_tables(bp, static_cast<unsigned char*>(scratch), s);
+      if (st) {
+        *status = st;
+        return true;
+      }
+      const bk::MultiScatterArgs* dm = reinterpret_cast<const bk::MultiScatterArgs*>(
+          static_cast<unsigned char*>(scratch) + bp.tables_off + moff);
+      bk::KTimer* tm = timing_timer();
+      hipError_t e = bk::launch_scatter_multi(dm, g.args[0].nwg, lds, s, tm);
+      if (e == hipSuccess) e = bk::launch_partition_batch_after_scatter(g.b, g.cf64, g.af64, g.prec, g.cfg, s, tm);
+      if (e != hipSuccess) *status = hip_fail(e, "launch fused multi-grid kernels");
+      return true;
+    }
+  }
+  return false;
+}
+
+int run_batch(const bin_request* reqs, int nreq, hipStream_t s, const PlanHints& hints, bool allow_persist) {
   int st = validate_requests(reqs, nreq);
   if (st) return st;
   if (nreq == 0) return BIN_OK;
@@ -342,17 +610,17 @@ int run_batch(const bin_request* reqs, int nreq, hipStream_t s, const PlanHints&
   st = device_info(&dev);
   if (st) return st;
   BatchPlan bp;
-  st = plan_batch(reqs, nreq, dev, hints, nullptr, &bp);
+  st = plan_batch(reqs, nreq, dev, hints, nullptr, &bp, allow_persist);
   if (st) return st;
   void* scratch = nullptr;
   st = scratch_get(dev.device, s, bp.scratch_bytes, &scratch);
   if (st) return st;
-  st = plan_batch(reqs, nreq, dev, hints, static_cast<unsigned char*>(scratch), &bp);
+  st = plan_batch(reqs, nreq, dev, hints, static_cast<unsigned char*>(scratch), &bp, allow_persist);
   if (st) return st;
   st = upload_tables(bp, static_cast<unsigned char*>(scratch), s);
   if (st) return st;
   bk::KTimer* tm = timing_timer();
-  st = launch_batch(bp, s, tm);
+  st = launch_batch(bp, s, tm, dev.cus);
   if (st) return st;
   for (int i : bp.global_reqs) {
     st = run_request(reqs[i], s, hints);
@@ -361,14 +629,14 @@ int run_batch(const bin_request* reqs, int nreq, hipStream_t s, const PlanHints&
   return BIN_OK;
 }
 
-size_t batch_scratch_bytes(const bin_request* reqs, int nreq, int* status) {
+size_t batch_scratch_bytes(const bin_request* reqs, int nreq, int* status, bool allow_persist) {
   *status = validate_requests(reqs, nreq);
   if (*status || nreq == 0) return 0;
   DeviceInfo dev;
   *status = device_info(&dev);
   if (*status) return 0;
   BatchPlan bp;
-  *status = plan_batch(reqs, nreq, dev, thread_hints(), nullptr, &bp);
+  *status = plan_batch(reqs, nreq, dev, thread_hints(), nullptr, &bp, allow_persist);
   if (*status) return 0;
   size_t extra = 0;  // requests on the global strategy use their own scratch
   for (int i : bp.global_reqs) extra += al256(bp.preps[i].scratch_bytes);
@@ -417,7 +685,11 @@ int bin_particles_multi(const bin_columns* coords, const bin_columns* attrs, int
     r.ops = grids[g].ops;
     r.out = grids[g].out;
   }
-  return run_batch(reqs.data(), ngrids, static_cast<hipStream_t>(stream), thread_hints());
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int st = validate_requests(reqs.data(), ngrids);
+  if (st) return st;
+  if (run_multi_fused(reqs.data(), ngrids, s, &st)) return st;
+  return run_batch(reqs.data(), ngrids, s, thread_hints());
 }
 
 int bin_graph_create(const bin_request* reqs, int32_t nreq, bin_graph** out) {
@@ -459,7 +731,7 @@ int bin_graph_create(const bin_request* reqs, int32_t nreq, bin_graph** out) {
     if (e != hipSuccess) st = hip_fail(e, "hipStreamBeginCapture");
   }
   if (st == BIN_OK) {
-    const int lst = launch_batch(bp, cs, nullptr);
+    const int lst = launch_batch(bp, cs, nullptr, dev.cus);
     e = hipStreamEndCapture(cs, &g->graph);
     if (lst) st = lst;
     else if (e != hipSuccess) st = hip_fail(e, "hipStreamEndCapture");

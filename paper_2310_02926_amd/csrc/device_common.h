@@ -361,13 +361,15 @@ struct Tile {
   // per bin each fold every 16th slot, then the 16 partials are combined in
   // LDS and the finished bin is emitted.  Many slots are merged in
   // parallel instead of one slot after another.
+  // LDS workspace for merge_emit64: 16 x 64 partial sums, keys and counts.
+  static constexpr int kMergeLds = 16 * 64 * (8 + 2 * (int)sizeof(K) + 4);
   __device__ static void merge_emit64(const unsigned char* slots, int64_t slot_bytes, uint32_t first, uint32_t nslot,
                                       const TileLayout& L, const Outs& o, int k, int64_t b0, int64_t nb,
-                                      int64_t goff) {
-    __shared__ double red_s[16][64];
-    __shared__ K red_mn[16][64];
-    __shared__ K red_mx[16][64];
-    __shared__ uint32_t red_c[16][64];
+                                      int64_t goff, unsigned char* lds) {
+    double(*red_s)[64] = reinterpret_cast<double(*)[64]>(lds);
+    K(*red_mn)[64] = reinterpret_cast<K(*)[64]>(lds + 16 * 64 * 8);
+    K(*red_mx)[64] = reinterpret_cast<K(*)[64]>(lds + 16 * 64 * (8 + sizeof(K)));
+    uint32_t(*red_c)[64] = reinterpret_cast<uint32_t(*)[64]>(lds + 16 * 64 * (8 + 2 * sizeof(K)));
     const int bl = threadIdx.x & 63;
     const int sg = threadIdx.x >> 6;  // 16 slot groups (blockDim.x == 1024)
     const int64_t gb = b0 + bl;

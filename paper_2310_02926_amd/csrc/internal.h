@@ -48,6 +48,7 @@ struct DeviceInfo {
   int cus = 256;
   size_t lds_per_block = 65536;
   size_t lds_per_cu = 65536;
+  char arch[48] = "";  // "<architecture>:<compute units>", empty for a device described by sizes only
 };
 int device_info(DeviceInfo* info);
 
@@ -89,7 +90,7 @@ const PlanHints& thread_hints();
 int resolve_precision(uint32_t ops, bool attr_f64);
 // The caller's explicit hints, else the autotuned entry for the request's
 // shape class, else defaults.
-PlanHints effective_hints(const bin_request& r, const PlanHints& explicit_hints);
+PlanHints effective_hints(const bin_request& r, const DeviceInfo& dev, const PlanHints& explicit_hints);
 int autotune(const bin_request* reqs, int count);
 
 // Plan a validated request and lay out its scratch at 'scratch' (may be null
@@ -134,9 +135,11 @@ struct FixedScratch {
 int run_request_in(const bin_request& r, hipStream_t s, const PlanHints& hints, const FixedScratch* fixed,
                    bk::KTimer* tm);
 int run_auto_bounds_in(const bin_request& r, hipStream_t s, const FixedScratch* fixed, bk::KTimer* tm);
-int run_batch(const bin_request* reqs, int nreq, hipStream_t s, const PlanHints& hints);
+// A batch; groups of 1024-thread scatter shapes run as one persistent
+// launch unless allow_persist is false (then one launch per stage).
+int run_batch(const bin_request* reqs, int nreq, hipStream_t s, const PlanHints& hints, bool allow_persist = true);
 // Device scratch a batch needs (0 and *status set on a bad batch).
-size_t batch_scratch_bytes(const bin_request* reqs, int nreq, int* status);
+size_t batch_scratch_bytes(const bin_request* reqs, int nreq, int* status, bool allow_persist = true);
 
 }  // namespace binimpl
 

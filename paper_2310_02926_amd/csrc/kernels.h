@@ -179,11 +179,57 @@ struct PartBatch {
   int32_t nreq, n_wg_blocks, n_walk_blocks, n_item_blocks, n_tile_blocks;
 };
 
+// ---- persistent batch ------------------------------------------------------
+// One launch runs every stage of a group of tile-partition requests (and
+// the whole-grid LDS requests of the same types) from a device work list.
+// Items (two words each: kind << 24 | request, index) in dependency order:
+// LDS chunks and scatter slices (largest request first), then work-item
+// walks, placements, tile binnings and merges.  A workgroup takes the next
+// item from a queue head (atomic), waits - bounded - until the stage its item
+// depends on has finished for that request (per-request counters, release /
+// acquire), runs it and counts it done.  The last workgroup to finish a
+// chunk of an LDS request merges that request's partial slots.
+enum PersistKind { PK_LDS = 0, PK_SCATTER = 1, PK_WALK = 2, PK_PLACE = 3, PK_BIN = 4, PK_MERGE = 5 };
+struct PersistBatch {
+  const PartArgs* part;    // partition requests of the group (descriptors)
+  const LdsArgs* lds;      // LDS-strategy requests run by the same launch, or null
+  const uint32_t* items;   // [nitems][2]
+  uint32_t* ctl;           // [0] queue head, [1] abort flag, then 4 counters per
+                           // partition request (scatter, walk, place, bin done),
+                           // then 1 per LDS request (chunks done); zeroed before the launch
+  uint32_t nitems;
+  int32_t npart, nlds, pad;
+  int64_t wait_ticks;      // longest wait for a stage (100 MHz clock) before the batch is abandoned
+};
+
+// ---- several grids over one table: the fused scatter -----------------------
+// Every grid's requests share the table, n, the slices and the sub-chunk
+// size; per sub-chunk the union of the columns the grids read (f32) is
+// staged in LDS once and each grid then writes its records exactly as the
+// single-grid scatter does.  Sub-chunks are all of sub = 4 * threads
+// particles (the slice shape of unaligned requests).
+constexpr int kMultiGrids = 32;
+constexpr int kMultiCols = 40;
+struct MultiScatterArgs {
+  const PartArgs* grids;            // device descriptors of the grids
+  const float* cols[kMultiCols];    // union of the columns read
+  int32_t gx[kMultiGrids], gy[kMultiGrids];  // union index of each grid's x and y column
+  int32_t attr_col[kMaxAttrs];      // union index of attribute j (shared by every grid)
+  int32_t grid_lds[kMultiGrids];    // byte offset of grid g's counters (cnt[2][T], off[T], tot[T])
+  int32_t grid_ost[kMultiGrids];    // byte offset of grid g's staged run-table rows
+  int32_t ngrids, ncols, k;
+  int32_t cols_lds;                 // byte offset of the staged columns ([ncols][sub] floats)
+  int32_t stage_b, stage_v;         // byte offsets of the record stage (bins u16, values f32)
+  int32_t sub;                      // particles per sub-chunk
+  int32_t vec;                      // every column 16-byte aligned: staged with 16-byte loads
+};
+
 struct PartCfg {
   size_t scatter_lds, bin_lds;
   int ppt;              // particles per thread per scatter sub-chunk
   int scatter_threads;  // threads per scatter workgroup
   int bin_block;
+  int quads;            // batches: the group's requests gather a quad per lane
 };
 
 // Three-axis meshes: axes 1 and 2 folded into one composite coordinate
@@ -231,6 +277,15 @@ hipError_t set_dynamic_lds_limit(const void* fn, size_t total);
 hipError_t launch_bounds(const void* x, const void* y, bool coord_f64, int64_t n, long long* keys, int cus,
                          hipStream_t s, KTimer* tm);
 hipError_t set_partition_lds_limit(size_t bytes);
+// Fused scatter of several grids over one table (args: device copy).
+hipError_t launch_scatter_multi(const MultiScatterArgs* args, int nwg, size_t lds, hipStream_t s, KTimer* tm);
+// The stages after the scatter of a batch of partition requests.
+hipError_t launch_partition_batch_after_scatter(const PartBatch& b, bool coord_f64, bool attr_f64, int prec,
+                                                const PartCfg& c, hipStream_t s, KTimer* tm);
+// Persistent batch: zero the control words, then the persistent launch
+// (grid workgroups of 1024 threads, lds bytes of dynamic LDS).
+hipError_t launch_persist(const PersistBatch& b, uint32_t ctl_words, bool coord_f64, bool attr_f64, int prec,
+                          int ppt, bool quads, int grid, size_t lds, hipStream_t s, KTimer* tm);
 hipError_t launch_fold(const FoldArgs& a, bool coord_f64, int cus, hipStream_t s, KTimer* tm);
 
 }  // namespace bk

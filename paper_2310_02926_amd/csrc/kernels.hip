@@ -25,6 +25,7 @@
 
 #include "device_common.h"
 #include "kernels.h"
+#include "lds_body.h"
 
 namespace bk {
 
@@ -134,58 +135,8 @@ __global__ __launch_bounds__(256) void bin_finalize_kernel(FinArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// LDS strategy: the whole grid in one workgroup's LDS.
+// LDS strategy: the whole grid in one workgroup's LDS (body in lds_body.h).
 // ---------------------------------------------------------------------------
-template <typename CT, typename AT, int PREC>
-__device__ __forceinline__ void bin_lds_body(const LdsArgs& a, int wg) {
-  using TL = Tile<AT, PREC>;
-  extern __shared__ __align__(16) unsigned char smem[];
-  Axis ax = a.ax, ay = a.ay;
-  resolve_axes(a.dyn, ax, ay);
-  TL::init(smem, a.lay, a.k);
-  __syncthreads();
-
-  const int64_t lo = (int64_t)wg * a.chunk;
-  const int64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
-  // Groups of 4 consecutive particles per lane (16-byte loads).
-  const bool vec = a.vec != 0;
-  constexpr int G = 2;
-  for (int64_t base = lo; base < hi; base += (int64_t)4 * G * blockDim.x) {
-    int bin[4 * G];
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const int64_t i = base + 4 * ((int64_t)g * blockDim.x + threadIdx.x);
-      CT xs[4], ys[4];
-      ld4<CT>(a.x, i, hi, vec, xs);
-      ld4<CT>(a.y, i, hi, vec, ys);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int ix, iy;
-        bin[4 * g + e] = -1;
-        if (i + e < hi && locate((double)xs[e], ax, ix) && locate((double)ys[e], ay, iy))
-          bin[4 * g + e] = iy * a.nx + ix;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < 4 * G; ++u)
-      if (bin[u] >= 0) TL::count(smem, bin[u]);
-    for (int j = 0; j < a.k; ++j) {
-      AT v[4 * G];
-#pragma unroll
-      for (int g = 0; g < G; ++g)
-        ld4<AT>(a.attr[j], base + 4 * ((int64_t)g * blockDim.x + threadIdx.x), hi, vec, v + 4 * g);
-#pragma unroll
-      for (int u = 0; u < 4 * G; ++u)
-        if (bin[u] >= 0) TL::add(smem, a.lay, j, bin[u], v[u]);
-    }
-  }
-  __syncthreads();
-  if (a.nslots <= 1)
-    TL::emit_all(smem, a.lay, a.out, a.k, a.nbins, 0);
-  else
-    TL::store_slot(smem, a.lay, a.k, a.nbins, static_cast<unsigned char*>(a.partial) + (int64_t)wg * a.lay.slot_bytes);
-}
-
 template <typename CT, typename AT, int PREC>
 __global__ __launch_bounds__(1024) void bin_lds_kernel(LdsArgs a) {
   bin_lds_body<CT, AT, PREC>(a, blockIdx.x);
@@ -200,18 +151,20 @@ __global__ __launch_bounds__(1024) void bin_lds_batched(const LdsArgs* __restric
 // Merge the slots of bins [b0, b0 + 64) (1024-thread workgroups).
 template <typename AT, int PREC>
 __global__ __launch_bounds__(1024) void lds_merge_kernel(LdsArgs a) {
+  __shared__ __align__(16) unsigned char red[Tile<AT, PREC>::kMergeLds];
   for (int64_t b0 = (int64_t)blockIdx.x * 64; b0 < a.nbins; b0 += (int64_t)gridDim.x * 64)
     Tile<AT, PREC>::merge_emit64(static_cast<const unsigned char*>(a.partial), a.lay.slot_bytes, 0u,
-                                 (uint32_t)a.nslots, a.lay, a.out, a.k, b0, a.nbins, 0);
+                                 (uint32_t)a.nslots, a.lay, a.out, a.k, b0, a.nbins, 0, red);
 }
 template <typename AT, int PREC>
 __global__ __launch_bounds__(1024) void lds_merge_batched(const LdsArgs* __restrict__ d,
                                                           const uint32_t* __restrict__ map) {
+  __shared__ __align__(16) unsigned char red[Tile<AT, PREC>::kMergeLds];
   const uint32_t m = map[blockIdx.x];
   const LdsArgs& a = d[m >> 16];
   if (a.nslots > 1)
     Tile<AT, PREC>::merge_emit64(static_cast<const unsigned char*>(a.partial), a.lay.slot_bytes, 0u,
-                                 (uint32_t)a.nslots, a.lay, a.out, a.k, (int64_t)(m & 0xFFFFu) * 64, a.nbins, 0);
+                                 (uint32_t)a.nslots, a.lay, a.out, a.k, (int64_t)(m & 0xFFFFu) * 64, a.nbins, 0, red);
 }
 
 // ---------------------------------------------------------------------------

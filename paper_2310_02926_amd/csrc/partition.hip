@@ -38,6 +38,7 @@
 
 #include "device_common.h"
 #include "kernels.h"
+#include "lds_body.h"
 
 namespace bk {
 
@@ -442,9 +443,12 @@ __device__ __forceinline__ void part_items_walk_body(const PartArgs& a, int blk)
 
 // Placement: one block numbers the items of all tiles (exclusive scans over
 // tiles, 4 tiles per thread) and writes them out.
-__device__ __forceinline__ void part_items_place_body(const PartArgs& a) {
-  __shared__ uint32_t wave_tot[16];
-  __shared__ uint32_t fi[4096];  // first item of each tile (T <= 4096)
+// LDS workspace: wave_tot[16] then fi[4096] (the first item of each tile;
+// T <= 4096).
+constexpr int kPlaceLds = 4 * (16 + 4096);
+__device__ __forceinline__ void part_items_place_body(const PartArgs& a, uint32_t* lds) {
+  uint32_t* wave_tot = lds;
+  uint32_t* fi = lds + 16;
   const int T = a.ntiles;
   const int t0 = 4 * threadIdx.x;
   uint32_t ni[4], nrec[4];
@@ -510,9 +514,13 @@ __global__ __launch_bounds__(1024) void part_items_walk_batched(const PartArgs* 
   const uint32_t m = map[blockIdx.x];
   part_items_walk_body(d[m >> 16], (int)(m & 0xFFFFu));
 }
-__global__ __launch_bounds__(1024) void part_items_kernel(PartArgs a) { part_items_place_body(a); }
+__global__ __launch_bounds__(1024) void part_items_kernel(PartArgs a) {
+  __shared__ uint32_t lds[kPlaceLds / 4];
+  part_items_place_body(a, lds);
+}
 __global__ __launch_bounds__(1024) void part_items_batched(const PartArgs* __restrict__ d) {
-  part_items_place_body(d[blockIdx.x]);
+  __shared__ uint32_t lds[kPlaceLds / 4];
+  part_items_place_body(d[blockIdx.x], lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -797,12 +805,13 @@ __global__ __launch_bounds__(1024) void part_bin_kernel(PartArgs a) {
   if (s >= per) return;
   part_bin_body<AT, PREC, QUAD>(a, (int)((blockIdx.x % 8) * per + s));
 }
-// Batches gather record by record (their requests are planned without quads).
-template <typename AT, int PREC>
+// Batches: one gather form per launch (a group of requests that all pad
+// their runs to quads, or none).
+template <typename AT, int PREC, bool QUAD>
 __global__ __launch_bounds__(1024) void part_bin_batched(const PartArgs* __restrict__ d,
                                                          const uint32_t* __restrict__ map) {
   const uint32_t m = map[blockIdx.x];
-  part_bin_body<AT, PREC, false>(d[m >> 16], (int)(m & 0xFFFFu));
+  part_bin_body<AT, PREC, QUAD>(d[m >> 16], (int)(m & 0xFFFFu));
 }
 
 // Merge of split tiles: work unit u = (split tile, 1024-bin chunk), one bin
@@ -884,13 +893,20 @@ static hipError_t launch_part_t(const PartArgs& a, const PartCfg& c, hipStream_t
 }
 
 template <typename CT, typename AT, int PREC>
-static hipError_t launch_part_batch_t(const PartBatch& b, const PartCfg& c, hipStream_t s, KTimer* tm) {
+static hipError_t launch_part_batch_t(const PartBatch& b, const PartCfg& c, hipStream_t s, KTimer* tm,
+                                      bool scatter = true) {
   hipError_t e;
-  BK_SCATTER_SWITCH(part_scatter_batched, b.n_wg_blocks, b.descs, b.map_wg)
+  if (scatter) {
+    BK_SCATTER_SWITCH(part_scatter_batched, b.n_wg_blocks, b.descs, b.map_wg)
+  }
   BK_LAUNCH("part_items_walk_kernel", part_items_walk_batched, b.n_walk_blocks, 1024, 0, b.descs, b.map_walk);
   BK_LAUNCH("part_items_kernel", part_items_batched, b.nreq, 1024, 0, b.descs);
-  BK_LAUNCH("part_bin_kernel", (part_bin_batched<AT, PREC>), b.n_item_blocks, c.bin_block, c.bin_lds, b.descs,
-            b.map_item);
+  if (c.quads)
+    BK_LAUNCH("part_bin_kernel", (part_bin_batched<AT, PREC, true>), b.n_item_blocks, c.bin_block, c.bin_lds, b.descs,
+              b.map_item);
+  else
+    BK_LAUNCH("part_bin_kernel", (part_bin_batched<AT, PREC, false>), b.n_item_blocks, c.bin_block, c.bin_lds,
+              b.descs, b.map_item);
   BK_LAUNCH("part_merge_kernel", (part_merge_batched<AT, PREC>), b.n_tile_blocks, 1024, 0, b.descs, b.map_tile);
   return hipSuccess;
 }
@@ -922,8 +938,343 @@ hipError_t launch_partition_batch(const PartBatch& b, bool coord_f64, bool attr_
                                   hipStream_t s, KTimer* tm) {
   BK_PART_DISPATCH(launch_part_batch_t, b, c, s, tm)
 }
+
+hipError_t launch_partition_batch_after_scatter(const PartBatch& b, bool coord_f64, bool attr_f64, int prec,
+                                                const PartCfg& c, hipStream_t s, KTimer* tm) {
+  BK_PART_DISPATCH(launch_part_batch_t, b, c, s, tm, false)
+}
 #undef BK_PART_DISPATCH
 #undef BK_LAUNCH
+
+// ---------------------------------------------------------------------------
+// Fused scatter of several grids over one table (MultiScatterArgs).  One
+// workgroup per slice; per sub-chunk of S = 4 * NT particles: the union of
+// the columns is staged in LDS once, then each grid in turn ranks the
+// sub-chunk's inside particles within its tiles, one wave scans the tile
+// counts, and the records are placed in LDS in tile order and written back
+// over the sub-chunk's own index range - the layout, run table and per-slice
+// counts the single-grid scatter writes (with sub-chunks of S particles).
+// The particle table is read from HBM once for all grids.
+// ---------------------------------------------------------------------------
+template <int NT>
+__global__ __launch_bounds__(NT) void part_scatter_multi_kernel(const MultiScatterArgs* __restrict__ argp) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ uint32_t s_nsub;
+  constexpr int PPT = 4;
+  const MultiScatterArgs& m = *argp;
+  const int S = m.sub;
+  const int w = blockIdx.x;
+  const PartArgs& a0 = m.grids[0];
+  const int64_t lo = (int64_t)w * a0.chunk;
+  const int64_t hi = lo + a0.chunk < a0.n ? lo + a0.chunk : a0.n;
+  float* cols = reinterpret_cast<float*>(smem + m.cols_lds);
+  uint16_t* stg_b = reinterpret_cast<uint16_t*>(smem + m.stage_b);
+  float* stg_v = reinterpret_cast<float*>(smem + m.stage_v);
+  for (int g = 0; g < m.ngrids; ++g) {
+    const int T = m.grids[g].ntiles;
+    uint32_t* c = reinterpret_cast<uint32_t*>(smem + m.grid_lds[g]);
+    for (int t = threadIdx.x; t < 4 * T; t += NT) c[t] = 0u;  // cnt[2][T], off[T], tot[T]
+  }
+  __syncthreads();
+  int j = 0;
+  for (int64_t base = lo; base < hi; base += S, ++j) {
+    const int len = hi - base < S ? (int)(hi - base) : S;
+    // Stage the union of the columns (16-byte loads when every column is
+    // aligned; base is a multiple of 64).
+    for (int u = 0; u < m.ncols; ++u) {
+      const float* src = m.cols[u] + base;
+      float* dst = cols + (int64_t)u * S;
+      if (m.vec && len == S) {
+        for (int q = threadIdx.x; q < S / 4; q += NT)
+          reinterpret_cast<f32x4*>(dst)[q] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(src) + q);
+      } else {
+        for (int p = threadIdx.x; p < S; p += NT) dst[p] = p < len ? __builtin_nontemporal_load(src + p) : 0.0f;
+      }
+    }
+    __syncthreads();
+    const int parity = j & 1;
+    for (int g = 0; g < m.ngrids; ++g) {
+      const PartArgs& a = m.grids[g];
+      const int T = a.ntiles;
+      uint32_t* cbase = reinterpret_cast<uint32_t*>(smem + m.grid_lds[g]);
+      uint32_t* cnt = cbase + parity * T;
+      uint32_t* cprev = cbase + (parity ^ 1) * T;
+      uint32_t* off = cbase + 2 * T;
+      uint32_t* tot = off + T;
+      uint16_t* ost = reinterpret_cast<uint16_t*>(smem + m.grid_ost[g]);
+      const int shift = a.lay.tile_shift;
+      const uint32_t lmask = (1u << shift) - 1u;
+      const float* xs = cols + (int64_t)m.gx[g] * S;
+      const float* ys = cols + (int64_t)m.gy[g] * S;
+      Axis ax = a.ax, ay = a.ay;
+      resolve_axes(a.dyn, ax, ay);
+      uint32_t tb[PPT], pos[PPT];
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) {
+        const int p = q * NT + threadIdx.x;
+        tb[q] = 0xFFFFFFFFu;
+        int ix, iy;
+        if (p < len && locate((double)xs[p], ax, ix) && locate((double)ys[p], ay, iy)) {
+          const uint32_t b = (uint32_t)(iy * a.nx + ix);
+          tb[q] = ((b >> shift) << 16) | (b & lmask);
+        }
+        pos[q] = tb[q] != 0xFFFFFFFFu ? atomicAdd(cnt + (tb[q] >> 16), 1u) : 0u;
+      }
+      __syncthreads();
+      if (threadIdx.x < 64) {  // one wave: lane l owns tiles [l * mt, l * mt + mt)
+        const int lane = threadIdx.x;
+        const int mt = (T + 63) >> 6;
+        const int t0 = lane * mt;
+        const uint32_t padm = a.quads ? 3u : 0u;
+        uint32_t own = 0;
+        for (int q = 0; q < mt; ++q)
+          if (t0 + q < T) own += (cnt[t0 + q] + padm) & ~padm;
+        uint32_t x = own;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const uint32_t y = __shfl_up(x, o);
+          if (lane >= o) x += y;
+        }
+        uint32_t o0 = x - own;
+        for (int q = 0; q < mt; ++q) {
+          const int t = t0 + q;
+          if (t < T) {
+            const uint32_t cc = (cnt[t] + padm) & ~padm;
+            tot[t] += cc;
+            cprev[t] = 0u;
+            off[t] = o0;
+            o0 += cc;
+          }
+        }
+        if (lane == 63) s_nsub = x;
+      }
+      __syncthreads();
+      const uint32_t nsub = s_nsub;
+      const int F = 1 << a.off_shift;
+      for (int t = threadIdx.x; t <= T; t += NT) {
+        ost[(t << a.off_shift) + (j & (F - 1))] = (uint16_t)(t < T ? off[t] : nsub);
+        if (a.quads && t < T) {  // pad the run to a whole quad
+          const uint32_t cc = cnt[t];
+          const uint32_t e = off[t] + ((cc + 3u) & ~3u);
+          for (uint32_t p = off[t] + cc; p < e; ++p) stg_b[p] = 0xFFFFu;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < PPT; ++q)
+        if (tb[q] != 0xFFFFFFFFu) {
+          pos[q] += off[tb[q] >> 16];
+          stg_b[pos[q]] = (uint16_t)(tb[q] & 0xFFFFu);
+        }
+      __syncthreads();
+      // run-table rows [j0, j] of the slice once F are staged or at its end
+      const int nblocks = (int)((hi - lo + S - 1) / S);
+      if (((j + 1) & (F - 1)) == 0 || j + 1 == nblocks) {
+        const int j0 = j & ~(F - 1);
+        const int f = j - j0 + 1;
+        const int64_t nrows = (int64_t)a.nwg * a.nbpw;
+        const int64_t r0 = (int64_t)w * a.nbpw + j0;
+        for (int i2 = threadIdx.x; i2 < ((T + 1) << a.off_shift); i2 += NT) {
+          const int t = i2 >> a.off_shift, jj = i2 & (F - 1);
+          if (jj < f) a.blk_off[(int64_t)t * nrows + r0 + jj] = ost[i2];
+        }
+      }
+      const int64_t rbase = base + ((int64_t)w * a.nbpw + j) * (int64_t)a.pad_row;
+      for (uint32_t p = threadIdx.x; p < nsub; p += NT) __builtin_nontemporal_store(stg_b[p], a.rec_bin + rbase + p);
+      for (int jx = 0; jx < a.k; ++jx) {
+        const float* vs = cols + (int64_t)m.attr_col[jx] * S;
+        if (a.quads)  // padding values are 0 (never read as data)
+          for (int t = threadIdx.x; t < T; t += NT) {
+            const uint32_t cc = cnt[t];
+            const uint32_t e = off[t] + ((cc + 3u) & ~3u);
+            for (uint32_t p = off[t] + cc; p < e; ++p) stg_v[p] = 0.0f;
+          }
+#pragma unroll
+        for (int q = 0; q < PPT; ++q)
+          if (tb[q] != 0xFFFFFFFFu) stg_v[pos[q]] = vs[q * NT + threadIdx.x];
+        __syncthreads();
+        float* rv = static_cast<float*>(a.rec_val[jx]) + rbase;
+        for (uint32_t p = threadIdx.x; p < nsub; p += NT) __builtin_nontemporal_store(stg_v[p], rv + p);
+        __syncthreads();  // the stage is reused by the next attribute
+      }
+      __syncthreads();  // the bin stage and counters are reused by the next grid
+    }
+  }
+  __syncthreads();
+  for (int g = 0; g < m.ngrids; ++g) {
+    const PartArgs& a = m.grids[g];
+    const int T = a.ntiles;
+    const uint32_t* tot = reinterpret_cast<const uint32_t*>(smem + m.grid_lds[g]) + 3 * T;
+    for (int t = threadIdx.x; t < T; t += NT) a.counts[(int64_t)t * a.nwg + w] = tot[t];
+  }
+}
+
+hipError_t launch_scatter_multi(const MultiScatterArgs* args, int nwg, size_t lds, hipStream_t s, KTimer* tm) {
+  if (nwg <= 0) return hipSuccess;
+  if (tm) tm->begin(s);
+  hipLaunchKernelGGL(part_scatter_multi_kernel<512>, dim3(nwg), dim3(512), lds, s, args);
+  if (tm) tm->end("part_scatter_multi_kernel", s);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Persistent batch kernel (see PersistBatch).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void persist_init_kernel(uint32_t* ctl, uint32_t words) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < words; i += gridDim.x * blockDim.x) ctl[i] = 0u;
+}
+
+// Every thread's writes are made visible device-wide, then one thread counts
+// the item done (release).
+__device__ __forceinline__ void persist_signal(uint32_t* ctr) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until *ctr >= need (one thread polls with acquire loads and short
+// sleeps), then every thread acquires.  A wait longer than the batch's limit
+// abandons the batch (its results are then not valid); once abandoned, every
+// wait returns false at once and its item is skipped, so the launch always
+// ends and no skipped stage's output is ever read.
+__device__ __forceinline__ bool persist_wait(const uint32_t* ctr, uint32_t need, uint32_t* abort_flag,
+                                             int64_t wait_ticks, int* s_ok) {
+  if (threadIdx.x == 0) {
+    int ok = __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 0 : 1;
+    if (ok && __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+      const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+      while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          ok = 0;
+          break;
+        }
+        if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t0) > wait_ticks) {
+          __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    *s_ok = ok;
+  }
+  __syncthreads();
+  const bool ok = *s_ok != 0;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return ok;
+}
+
+template <typename CT, typename AT, int PREC, int PPT, bool QUAD>
+__global__ __launch_bounds__(1024) void part_persist_kernel(PersistBatch b) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ uint32_t s_item[2];
+  __shared__ int s_flag;
+  uint32_t* head = b.ctl;
+  uint32_t* abort_flag = b.ctl + 1;
+  uint32_t* pc = b.ctl + 2;               // [npart][4]
+  uint32_t* lc = pc + 4 * (int64_t)b.npart;  // [nlds]
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const uint32_t i = atomicAdd(head, 1u);
+      s_item[0] = i < b.nitems ? b.items[2 * (int64_t)i] : 0xFFFFFFFFu;
+      s_item[1] = i < b.nitems ? b.items[2 * (int64_t)i + 1] : 0u;
+    }
+    __syncthreads();
+    const uint32_t kr = s_item[0], idx = s_item[1];
+    __syncthreads();  // s_item is written again only after every thread has read it
+    if (kr == 0xFFFFFFFFu) break;
+    const uint32_t kind = kr >> 24, r = kr & 0xFFFFFFu;
+    switch (kind) {
+      case PK_LDS: {
+        const LdsArgs& a = b.lds[r];
+        bin_lds_body<CT, AT, PREC>(a, (int)idx);
+        if (a.nslots <= 1) break;  // a lone workgroup wrote the outputs
+        // The last chunk to finish merges the request's slots (acq_rel count).
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0)
+          s_flag = __hip_atomic_fetch_add(lc + r, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
+                   (uint32_t)a.nslots - 1u;
+        __syncthreads();
+        if (s_flag) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          for (int64_t b0 = 0; b0 < a.nbins; b0 += 64)
+            Tile<AT, PREC>::merge_emit64(static_cast<const unsigned char*>(a.partial), a.lay.slot_bytes, 0u,
+                                         (uint32_t)a.nslots, a.lay, a.out, a.k, b0, a.nbins, 0, smem);
+        }
+        break;
+      }
+      case PK_SCATTER:
+        part_scatter_body<CT, AT, PPT, 1024>(b.part[r], (int)idx);
+        persist_signal(pc + 4 * r + 0);
+        break;
+      case PK_WALK:
+        if (persist_wait(pc + 4 * r + 0, (uint32_t)b.part[r].nwg, abort_flag, b.wait_ticks, &s_flag))
+          part_items_walk_body(b.part[r], (int)idx);
+        persist_signal(pc + 4 * r + 1);
+        break;
+      case PK_PLACE:
+        if (persist_wait(pc + 4 * r + 1, (uint32_t)((b.part[r].ntiles + 15) / 16), abort_flag, b.wait_ticks,
+                         &s_flag))
+          part_items_place_body(b.part[r], reinterpret_cast<uint32_t*>(smem));
+        persist_signal(pc + 4 * r + 2);
+        break;
+      case PK_BIN:
+        if (persist_wait(pc + 4 * r + 2, 1u, abort_flag, b.wait_ticks, &s_flag))
+          part_bin_body<AT, PREC, QUAD>(b.part[r], (int)idx);
+        persist_signal(pc + 4 * r + 3);
+        break;
+      case PK_MERGE:
+        if (persist_wait(pc + 4 * r + 3, (uint32_t)b.part[r].max_items, abort_flag, b.wait_ticks, &s_flag))
+          part_merge_body<AT, PREC>(b.part[r], (int)idx);
+        break;
+      default:
+        break;
+    }
+    __syncthreads();  // the next item may reuse the LDS
+  }
+}
+
+template <typename CT, typename AT, int PREC>
+static hipError_t launch_persist_t(const PersistBatch& b, uint32_t words, int ppt, bool quads, int grid, size_t lds,
+                                   hipStream_t s, KTimer* tm) {
+  hipError_t e;
+  if (tm) tm->begin(s);
+  hipLaunchKernelGGL(persist_init_kernel, dim3((words + 255) / 256 < 64 ? (words + 255) / 256 : 64), dim3(256), 0, s,
+                     b.ctl, words);
+  if (tm) tm->end("persist_init_kernel", s);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+#define BK_PERSIST(P, Q)                                                                                     \
+  if (ppt == P && quads == Q) {                                                                              \
+    if (tm) tm->begin(s);                                                                                    \
+    hipLaunchKernelGGL((part_persist_kernel<CT, AT, PREC, P, Q>), dim3(grid), dim3(1024), lds, s, b);       \
+    if (tm) tm->end("part_persist_kernel", s);                                                               \
+    return hipGetLastError();                                                                                \
+  }
+  BK_PERSIST(4, false)
+  BK_PERSIST(8, false)
+  BK_PERSIST(4, true)
+  BK_PERSIST(8, true)
+#undef BK_PERSIST
+  return hipErrorInvalidConfiguration;
+}
+
+hipError_t launch_persist(const PersistBatch& b, uint32_t ctl_words, bool coord_f64, bool attr_f64, int prec,
+                          int ppt, bool quads, int grid, size_t lds, hipStream_t s, KTimer* tm) {
+  if (coord_f64) {
+    if (attr_f64) return launch_persist_t<double, double, PREC_F64>(b, ctl_words, ppt, quads, grid, lds, s, tm);
+    switch (prec) {
+      case PREC_PLAIN: return launch_persist_t<double, float, PREC_PLAIN>(b, ctl_words, ppt, quads, grid, lds, s, tm);
+      case PREC_COMP: return launch_persist_t<double, float, PREC_COMP>(b, ctl_words, ppt, quads, grid, lds, s, tm);
+      default: return launch_persist_t<double, float, PREC_F64>(b, ctl_words, ppt, quads, grid, lds, s, tm);
+    }
+  }
+  if (attr_f64) return launch_persist_t<float, double, PREC_F64>(b, ctl_words, ppt, quads, grid, lds, s, tm);
+  switch (prec) {
+    case PREC_PLAIN: return launch_persist_t<float, float, PREC_PLAIN>(b, ctl_words, ppt, quads, grid, lds, s, tm);
+    case PREC_COMP: return launch_persist_t<float, float, PREC_COMP>(b, ctl_words, ppt, quads, grid, lds, s, tm);
+    default: return launch_persist_t<float, float, PREC_F64>(b, ctl_words, ppt, quads, grid, lds, s, tm);
+  }
+}
 
 hipError_t set_partition_lds_limit(size_t bytes) {
   hipError_t e = hipSuccess;
@@ -936,6 +1287,7 @@ hipError_t set_partition_lds_limit(size_t bytes) {
   BK_SET_NT(K, CT, AT, 1024) BK_SETF(K<CT, AT, 12, 1024>)
 #define BK_SET_TYPES(K) \
   BK_SET_CA(K, float, float) BK_SET_CA(K, float, double) BK_SET_CA(K, double, float) BK_SET_CA(K, double, double)
+  BK_SETF(part_scatter_multi_kernel<512>)
   BK_SET_TYPES(part_scatter_kernel)
   BK_SET_TYPES(part_scatter_batched)
   BK_SETF(part_bin_kernel<float, PREC_F64, false>)
@@ -946,10 +1298,26 @@ hipError_t set_partition_lds_limit(size_t bytes) {
   BK_SETF(part_bin_kernel<float, PREC_COMP, true>)
   BK_SETF(part_bin_kernel<float, PREC_PLAIN, true>)
   BK_SETF(part_bin_kernel<double, PREC_F64, true>)
-  BK_SETF(part_bin_batched<float, PREC_F64>)
-  BK_SETF(part_bin_batched<float, PREC_COMP>)
-  BK_SETF(part_bin_batched<float, PREC_PLAIN>)
-  BK_SETF(part_bin_batched<double, PREC_F64>)
+  BK_SETF(part_bin_batched<float, PREC_F64, false>)
+  BK_SETF(part_bin_batched<float, PREC_COMP, false>)
+  BK_SETF(part_bin_batched<float, PREC_PLAIN, false>)
+  BK_SETF(part_bin_batched<double, PREC_F64, false>)
+  BK_SETF(part_bin_batched<float, PREC_F64, true>)
+  BK_SETF(part_bin_batched<float, PREC_COMP, true>)
+  BK_SETF(part_bin_batched<float, PREC_PLAIN, true>)
+  BK_SETF(part_bin_batched<double, PREC_F64, true>)
+#define BK_SET_PERSIST(CT, AT, P) \
+  BK_SETF(part_persist_kernel<CT, AT, P, 4, false>) BK_SETF(part_persist_kernel<CT, AT, P, 8, false>) \
+  BK_SETF(part_persist_kernel<CT, AT, P, 4, true>) BK_SETF(part_persist_kernel<CT, AT, P, 8, true>)
+  BK_SET_PERSIST(float, float, PREC_F64)
+  BK_SET_PERSIST(float, float, PREC_COMP)
+  BK_SET_PERSIST(float, float, PREC_PLAIN)
+  BK_SET_PERSIST(float, double, PREC_F64)
+  BK_SET_PERSIST(double, float, PREC_F64)
+  BK_SET_PERSIST(double, float, PREC_COMP)
+  BK_SET_PERSIST(double, float, PREC_PLAIN)
+  BK_SET_PERSIST(double, double, PREC_F64)
+#undef BK_SET_PERSIST
 #undef BK_SET_TYPES
 #undef BK_SET_CA
 #undef BK_SET_NT

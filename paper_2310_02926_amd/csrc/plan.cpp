@@ -178,7 +178,7 @@ int resolve_precision(uint32_t ops, bool attr_f64) {
 }
 
 int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints_in, void* scratch, Prepared* p) {
-  const PlanHints hints = effective_hints(r, hints_in);
+  const PlanHints hints = effective_hints(r, dev, hints_in);
   std::memset(&p->bin, 0, sizeof p->bin);
   std::memset(&p->init, 0, sizeof p->init);
   std::memset(&p->fin, 0, sizeof p->fin);

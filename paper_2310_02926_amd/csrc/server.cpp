@@ -1,19 +1,24 @@
 // Request server with continuous batching (binsrv_*).
 //
-// binsrv_submit() may be called from any thread while earlier requests run.
-// One dispatcher thread:
-//   * polls the in-flight batches (one per stream slot) for completion and
-//     stamps their requests done (latency = submit -> completion observed);
-//   * whenever a slot is free, admits waiting requests in arrival order as
-//     long as their result grids and the batch scratch fit the device-memory
-//     budget, and runs them as one batched launch on that slot's stream.
-// Slots run concurrently on the device.  Result grids come from a reuse pool
-// keyed by size and stay resident until binsrv_release().
+// Requests wait in arrival order.  Work is admitted whenever something can
+// make room for it - a submission, a finished batch, a released grid - by
+// the thread that caused it: whenever a stream slot is free, the waiting
+// requests at the head of the queue whose result grids and scratch fit the
+// device-memory budget are launched on that slot's stream as one batch (a
+// lone request runs the single-request kernels).  So a request that finds a
+// slot free is launched by binsrv_submit itself, and requests that arrive
+// while every slot is busy are batched together when the next slot frees.
+// Each slot has a waiter thread that blocks on the slot's completion event
+// and stamps its requests done the moment the batch finishes.  Result grids
+// come from a reuse pool keyed by size and stay resident until
+// binsrv_release(); device memory is allocated and freed outside the lock.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <set>
 #include <thread>
@@ -34,6 +39,10 @@ double ms_between(clk::time_point a, clk::time_point b) {
 
 size_t al256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// Bytes the library's per-stream scratch pool holds after serving a call
+// that needs 'bytes' (its allocation rounds up and never goes below 1 MiB).
+size_t pool_bytes_for(size_t bytes) { return bytes ? std::max(al256(bytes), size_t(1) << 20) : 0; }
+
 enum ReqState { Q_WAITING = 0, Q_RUNNING = 1, Q_DONE = 2 };
 
 struct SrvReq {
@@ -45,8 +54,11 @@ struct SrvReq {
   clk::time_point t_submit, t_dispatch, t_done;
   bool dispatched = false;
   size_t out_bytes = 0;
-  size_t scratch_est = 0;  // library scratch to run it alone
-  // resident result grids (device), grouped as one allocation
+  size_t scratch_est = 0;   // scratch of running it alone (the plan that runs it)
+  hipEvent_t ready = nullptr;  // recorded on the producer stream at submit, or null
+  int slot = -1;               // slot running it, and that slot's launch number
+  uint64_t slot_seq = 0;
+  // resident result grids (device), one allocation
   void* grids = nullptr;
   size_t grid_bytes = 0;
   uint32_t* count = nullptr;
@@ -60,8 +72,12 @@ struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
   bool busy = false;
+  bool launched = false;  // a batch was enqueued and its event recorded; the waiter owns the slot
+  uint64_t seq = 0;       // launches so far (tells a batch's event from a later one's)
   std::vector<uint64_t> tickets;
-  size_t scratch_reserved = 0;  // bytes of the library pool this slot may hold
+  size_t scratch_reserved = 0;  // bytes of the library pool this slot's stream holds
+  std::condition_variable cv;
+  std::thread waiter;
 };
 
 // Bytes of the result grids of a request (all requested ops, default precision rules).
@@ -85,19 +101,19 @@ size_t grid_bytes_of(const binsrv_request& r) {
 struct binsrv {
   binsrv_config cfg{};
   std::mutex mu;
-  std::condition_variable cv_work;  // dispatcher wake-up
   std::condition_variable cv_done;  // waiters
-  std::thread thr;
-  bool stop = false;
+  bool stop = false;      // no more submissions
+  bool quit = false;      // slot waiters exit once their slot is idle
   uint64_t next_ticket = 1;
   std::deque<uint64_t> queue;
   std::unordered_map<uint64_t, SrvReq> reqs;
-  std::vector<Slot> slots;
+  std::vector<std::unique_ptr<Slot>> slots;
   std::unordered_map<size_t, std::vector<void*>> pool;  // free result blocks by size
   size_t pool_bytes = 0;       // bytes in free pool blocks
-  size_t resident_bytes = 0;   // bytes of blocks held by requests
+  size_t resident_bytes = 0;   // bytes of blocks held (or being allocated) for requests
+  int dispatching = 0;         // dispatches between admission and launch
   binsrv_stats st{};
-  int fatal = BIN_OK;
+  std::atomic<int> users{0};   // entry points currently using this server
 };
 
 namespace {
@@ -105,44 +121,34 @@ namespace {
 std::mutex g_live_mu;
 std::set<binsrv*> g_live;
 
-bool live(binsrv* s) {
-  std::lock_guard<std::mutex> lk(g_live_mu);
-  return g_live.count(s) != 0;
-}
+// A reference to a live server for the duration of one entry point call:
+// binsrv_destroy removes the server from the live set first and then waits
+// until no call holds a reference, so a concurrent call either sees it dead
+// or keeps it alive until it returns.
+struct SrvRef {
+  binsrv* s = nullptr;
+  explicit SrvRef(binsrv* p) {
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    if (g_live.count(p)) {
+      s = p;
+      s->users.fetch_add(1);
+    }
+  }
+  ~SrvRef() {
+    if (s) s->users.fetch_sub(1);
+  }
+  SrvRef(const SrvRef&) = delete;
+  SrvRef& operator=(const SrvRef&) = delete;
+};
 
 size_t in_use(const binsrv* s) {
   size_t b = s->pool_bytes + s->resident_bytes;
-  for (const Slot& sl : s->slots) b += sl.scratch_reserved;
+  for (const auto& sl : s->slots) b += sl->scratch_reserved;
   return b;
 }
 
 // Memory that cannot be reclaimed right now (pooled free blocks can).
 size_t committed(const binsrv* s) { return in_use(s) - s->pool_bytes; }
-
-// Take a result block of exactly 'bytes' from the pool or the device.
-int take_block(binsrv* s, size_t bytes, void** out) {
-  auto it = s->pool.find(bytes);
-  if (it != s->pool.end() && !it->second.empty()) {
-    *out = it->second.back();
-    it->second.pop_back();
-    s->pool_bytes -= bytes;
-    s->resident_bytes += bytes;
-    return BIN_OK;
-  }
-  // Make room by freeing pooled blocks of other sizes if the budget is tight.
-  for (auto& kv : s->pool) {
-    while (!kv.second.empty() && in_use(s) + bytes > s->cfg.budget_bytes) {
-      (void)hipFree(kv.second.back());
-      kv.second.pop_back();
-      s->pool_bytes -= kv.first;
-    }
-  }
-  if (fault_injection_hit()) return fail(BIN_ERR_OOM, "injected result-grid allocation failure");
-  hipError_t e = hipMalloc(out, bytes);
-  if (e != hipSuccess) return hip_fail(e, "hipMalloc(result grids)");
-  s->resident_bytes += bytes;
-  return BIN_OK;
-}
 
 void give_block(binsrv* s, void* p, size_t bytes) {
   if (!p) return;
@@ -171,7 +177,14 @@ void carve_outputs(SrvReq& q) {
   }
 }
 
+// The request as a bin_request; with stand-in output pointers when the grids
+// are not allocated yet (sizing only).
 bin_request as_bin_request(SrvReq& q) {
+  // stand-ins: non-null, suitably aligned, never dereferenced
+  static void* const fake[BIN_MAX_ATTRS] = {
+      (void*)0x1000, (void*)0x2000, (void*)0x3000, (void*)0x4000, (void*)0x5000, (void*)0x6000,
+      (void*)0x7000, (void*)0x8000, (void*)0x9000, (void*)0xA000, (void*)0xB000, (void*)0xC000,
+      (void*)0xD000, (void*)0xE000, (void*)0xF000, (void*)0x10000};
   bin_request b;
   std::memset(&b, 0, sizeof b);
   b.coords = q.r.coords;
@@ -185,145 +198,283 @@ bin_request as_bin_request(SrvReq& q) {
   b.nx = q.r.nx;
   b.ny = q.r.ny;
   b.ops = q.r.ops;
-  b.out.count = q.count;
-  b.out.sum = q.sum;
-  b.out.min = q.mn;
-  b.out.max = q.mx;
-  b.out.avg = q.avg;
+  if (q.grids) {
+    b.out.count = q.count;
+    b.out.sum = q.sum;
+    b.out.min = q.mn;
+    b.out.max = q.mx;
+    b.out.avg = q.avg;
+  } else {
+    b.out.count = reinterpret_cast<uint32_t*>(uintptr_t(4096));
+    b.out.sum = b.out.min = b.out.max = b.out.avg = const_cast<void* const*>(fake);
+  }
   return b;
 }
 
-// Completion polling; caller holds the lock.
-void poll_slots(binsrv* s) {
-  for (Slot& sl : s->slots) {
-    if (!sl.busy) continue;
-    hipError_t e = hipEventQuery(sl.done);
-    if (e == hipErrorNotReady) continue;
-    const clk::time_point now = clk::now();
-    for (uint64_t t : sl.tickets) {
-      auto it = s->reqs.find(t);
-      if (it == s->reqs.end()) continue;
-      it->second.state = Q_DONE;
-      it->second.t_done = now;
-      it->second.status = e == hipSuccess ? BIN_OK : BIN_ERR_DEVICE;
-      if (e == hipSuccess) s->st.completed++;
-      else s->st.failed++;
-      s->st.in_flight--;
-    }
-    if (e != hipSuccess) s->fatal = BIN_ERR_DEVICE;
-    sl.tickets.clear();
-    sl.busy = false;
-    s->cv_done.notify_all();
+// Scratch the batch of these requests needs as it will run: the
+// single-request plan for one request, the batch plan for several.
+size_t exact_scratch(std::vector<bin_request>& brs, int* status) {
+  *status = BIN_OK;
+  if (brs.size() == 1) {
+    DeviceInfo dev;
+    *status = device_info(&dev);
+    if (*status) return 0;
+    Prepared p;
+    *status = prepare(brs[0], dev, PlanHints{}, nullptr, &p);
+    return *status ? 0 : p.scratch_bytes;
   }
+  return batch_scratch_bytes(brs.data(), (int)brs.size(), status, false);
 }
 
-// Admit and launch one micro-batch on a free slot; caller holds the lock.
-// Returns true if it launched something.
+void fail_request(binsrv* s, SrvReq& q, int status) {
+  q.state = Q_DONE;
+  q.status = status;
+  q.t_done = clk::now();
+  s->st.failed++;
+}
+
+// Admit and launch one batch on a free slot.  Called with the lock held by
+// whichever thread made room (submit, a slot waiter, release); the lock is
+// dropped while memory is allocated and kernels are enqueued.  Returns true
+// if it launched (or failed) something, so that the caller tries again.
 bool dispatch_one(binsrv* s, std::unique_lock<std::mutex>& lk) {
-  int free_slot = -1;
+  Slot* sl = nullptr;
+  int sl_index = -1;
   for (size_t i = 0; i < s->slots.size(); ++i)
-    if (!s->slots[i].busy) {
-      free_slot = (int)i;
+    if (!s->slots[i]->busy) {
+      sl = s->slots[i].get();
+      sl_index = (int)i;
       break;
     }
-  if (free_slot < 0 || s->queue.empty()) return false;
-  Slot& sl = s->slots[free_slot];
-  // Release this slot's previous scratch reservation; re-reserve below.
-  const size_t old_reserved = sl.scratch_reserved;
-  sl.scratch_reserved = 0;
+  if (!sl || s->queue.empty()) return false;
+  // Candidates in arrival order while their grids and (estimated) scratch fit.
   std::vector<uint64_t> batch;
-  std::vector<bin_request> brs;
-  size_t scratch_need = 0;
-  while (!s->queue.empty() && (int)batch.size() < s->cfg.max_batch) {
-    SrvReq& q = s->reqs[s->queue.front()];
-    // Batch scratch is bounded by the sum of the members' own scratch.
-    const size_t need = scratch_need + q.scratch_est;
-    const size_t reserve = std::max(need, old_reserved);
-    // Not admitted now: wait for running work or released grids.
-    if (committed(s) + q.out_bytes + reserve > s->cfg.budget_bytes) break;
-    void* blk = nullptr;
-    int st = take_block(s, q.out_bytes, &blk);
-    if (st) {
-      q.state = Q_DONE;
-      q.status = st;
-      q.t_done = clk::now();
-      s->st.failed++;
-      s->queue.pop_front();
-      s->cv_done.notify_all();
-      continue;
-    }
-    q.grids = blk;
-    q.grid_bytes = q.out_bytes;
-    carve_outputs(q);
-    scratch_need = need;
-    brs.push_back(as_bin_request(q));
+  size_t grids = 0, est = 0;
+  const size_t base = committed(s) - sl->scratch_reserved;
+  for (size_t i = 0; i < s->queue.size() && (int)batch.size() < s->cfg.max_batch; ++i) {
+    SrvReq& q = s->reqs[s->queue[i]];
+    const size_t scratch = std::max(sl->scratch_reserved, pool_bytes_for(est + q.scratch_est));
+    if (base + grids + q.out_bytes + scratch > s->cfg.budget_bytes) break;
+    grids += q.out_bytes;
+    est += q.scratch_est;
     batch.push_back(q.ticket);
-    s->queue.pop_front();
   }
-  if (batch.empty()) {
-    sl.scratch_reserved = old_reserved;
-    return false;
+  if (batch.empty()) return false;  // wait for running work or released grids
+  // The scratch of the batch as it will run; drop members from the tail
+  // until it fits the budget too.
+  std::vector<bin_request> brs;
+  size_t reserve = 0;
+  for (;;) {
+    brs.clear();
+    grids = 0;
+    for (uint64_t t : batch) {
+      brs.push_back(as_bin_request(s->reqs[t]));
+      grids += s->reqs[t].out_bytes;
+    }
+    int st = BIN_OK;
+    const size_t need = exact_scratch(brs, &st);
+    if (st) {  // cannot be planned: fail the head request alone
+      if (batch.size() > 1) {
+        batch.resize(1);
+        continue;
+      }
+      SrvReq& q = s->reqs[batch[0]];
+      s->queue.pop_front();
+      fail_request(s, q, st);
+      s->cv_done.notify_all();
+      return true;
+    }
+    reserve = std::max(sl->scratch_reserved, pool_bytes_for(need));
+    if (base + grids + reserve <= s->cfg.budget_bytes) break;
+    if (batch.size() == 1) return false;  // fits once more memory is free
+    batch.resize(batch.size() / 2);
   }
-  sl.scratch_reserved = std::max(scratch_need, old_reserved);
-  sl.busy = true;
-  sl.tickets = batch;
+  // Commit: the slot, its scratch reservation, the members' grid bytes.
+  for (size_t i = 0; i < batch.size(); ++i) s->queue.pop_front();
+  sl->busy = true;
+  sl->launched = false;
+  sl->seq++;
+  sl->tickets = batch;
+  sl->scratch_reserved = reserve;
   const clk::time_point now = clk::now();
+  std::vector<std::pair<SrvReq*, void*>> members;  // request, pooled block (or null: allocate)
   for (uint64_t t : batch) {
     SrvReq& q = s->reqs[t];
     q.state = Q_RUNNING;
     q.t_dispatch = now;
     q.dispatched = true;
+    q.slot = sl_index;
+    q.slot_seq = sl->seq;
+    void* blk = nullptr;
+    auto it = s->pool.find(q.out_bytes);
+    if (it != s->pool.end() && !it->second.empty()) {
+      blk = it->second.back();
+      it->second.pop_back();
+      s->pool_bytes -= q.out_bytes;
+    }
+    s->resident_bytes += q.out_bytes;
+    members.emplace_back(&q, blk);
   }
+  // Pooled blocks of other sizes go back to the device while the budget is
+  // tight.
+  std::vector<void*> evict;
+  for (auto& kv : s->pool)
+    while (!kv.second.empty() && in_use(s) > s->cfg.budget_bytes) {
+      evict.push_back(kv.second.back());
+      kv.second.pop_back();
+      s->pool_bytes -= kv.first;
+    }
   s->st.batches++;
   s->st.in_flight += batch.size();
   s->st.queued = s->queue.size();
   s->st.bytes_in_use = in_use(s);
   s->st.peak_bytes = std::max<uint64_t>(s->st.peak_bytes, s->st.bytes_in_use);
-  hipStream_t stream = sl.stream;
-  hipEvent_t ev = sl.done;
-  // Launch outside the lock: submitters and waiters keep going.
+  s->dispatching++;
   lk.unlock();
-  // A lone request takes the single-request kernels (their tuned shapes).
-  int st = brs.size() == 1 ? run_request(brs[0], stream, PlanHints{})
-                           : run_batch(brs.data(), (int)brs.size(), stream, PlanHints{});
-  hipError_t e = hipSuccess;
-  if (st == BIN_OK) e = hipEventRecord(ev, stream);
+
+  for (void* p : evict) (void)hipFree(p);
+  // Grids: pooled blocks, else fresh allocations (a failed one fails only
+  // its own request).
+  std::vector<int> status(members.size(), BIN_OK);
+  std::vector<bin_request> run;
+  std::vector<hipEvent_t> ready;
+  for (size_t i = 0; i < members.size(); ++i) {
+    SrvReq& q = *members[i].first;
+    void* blk = members[i].second;
+    if (!blk) {
+      if (fault_injection_hit()) {
+        status[i] = fail(BIN_ERR_OOM, "injected result-grid allocation failure");
+      } else {
+        const hipError_t e = hipMalloc(&blk, q.out_bytes);
+        if (e != hipSuccess) {
+          blk = nullptr;
+          status[i] = hip_fail(e, "hipMalloc(result grids)");
+        }
+      }
+    }
+    if (status[i] != BIN_OK) continue;
+    q.grids = blk;
+    q.grid_bytes = q.out_bytes;
+    carve_outputs(q);
+    run.push_back(as_bin_request(q));
+    if (q.ready) ready.push_back(q.ready);
+  }
+  // Inputs written on a producer stream are read only after that work.
+  int st = BIN_OK;
+  for (hipEvent_t ev : ready) {
+    const hipError_t e = hipStreamWaitEvent(sl->stream, ev, 0);
+    if (e != hipSuccess && st == BIN_OK) st = hip_fail(e, "hipStreamWaitEvent(producer)");
+  }
+  // Batches here run one launch per stage rather than the persistent
+  // launch: several slots run at once, and persistent workgroups waiting for
+  // a stage would hold CUs that the other slots' batches could use.
+  if (st == BIN_OK && !run.empty())
+    st = run.size() == 1 ? run_request(run[0], sl->stream, PlanHints{})
+                         : run_batch(run.data(), (int)run.size(), sl->stream, PlanHints{}, false);
+  const hipError_t er = hipEventRecord(sl->done, sl->stream);
+
   lk.lock();
-  if (st != BIN_OK || e != hipSuccess) {
-    // Nothing usable was enqueued: fail the batch now (the slot's stream
-    // has no pending work of ours, so the slot is free again).
-    (void)hipStreamSynchronize(stream);
-    for (uint64_t t : batch) {
-      SrvReq& q = s->reqs[t];
-      q.state = Q_DONE;
-      q.status = st != BIN_OK ? st : BIN_ERR_DEVICE;
-      q.t_done = clk::now();
-      s->st.failed++;
+  s->dispatching--;
+  for (size_t i = 0; i < members.size(); ++i) {
+    SrvReq& q = *members[i].first;
+    if (status[i] != BIN_OK) {  // its grid never existed
+      s->resident_bytes -= q.out_bytes;
+      fail_request(s, q, status[i]);
+      s->st.in_flight--;
+    } else if (st != BIN_OK) {  // the launch failed: the batch's requests fail
+      fail_request(s, q, st);
       s->st.in_flight--;
     }
-    sl.busy = false;
-    sl.tickets.clear();
-    s->cv_done.notify_all();
   }
+  if (st != BIN_OK || er != hipSuccess) {
+    std::vector<uint64_t> keep;
+    sl->tickets.swap(keep);  // every member is failed above (or below)
+    if (er != hipSuccess) {
+      for (uint64_t t : keep) {
+        SrvReq& q = s->reqs[t];
+        if (q.state != Q_DONE) {
+          fail_request(s, q, hip_fail(er, "hipEventRecord(slot)"));
+          s->st.in_flight--;
+        }
+      }
+      // No event to wait on: drain the stream here, then the slot is free.
+      lk.unlock();
+      (void)hipStreamSynchronize(sl->stream);
+      lk.lock();
+      sl->busy = false;
+      s->cv_done.notify_all();
+      return true;
+    }
+  } else {
+    // drop failed members; the rest complete with the slot's event
+    std::vector<uint64_t> keep;
+    for (uint64_t t : sl->tickets)
+      if (s->reqs[t].state != Q_DONE) keep.push_back(t);
+    sl->tickets.swap(keep);
+  }
+  sl->launched = true;
+  sl->cv.notify_one();
+  s->cv_done.notify_all();
   return true;
 }
 
-void dispatcher(binsrv* s) {
+void dispatch_all(binsrv* s, std::unique_lock<std::mutex>& lk) {
+  while (dispatch_one(s, lk)) {
+  }
+}
+
+// The slot's batch (launch number seq) has finished with status e at 'now':
+// stamp its requests done, free the slot and admit waiting work.  Called
+// with the lock held by whichever thread saw the event first - the slot's
+// waiter, or a client in binsrv_wait - and a no-op for the other.
+void complete_slot(binsrv* s, Slot* sl, uint64_t seq, hipError_t e, clk::time_point now,
+                   std::unique_lock<std::mutex>& lk) {
+  if (!sl->launched || sl->seq != seq) return;
+  for (uint64_t t : sl->tickets) {
+    auto it = s->reqs.find(t);
+    if (it == s->reqs.end() || it->second.state == Q_DONE) continue;
+    it->second.state = Q_DONE;
+    it->second.t_done = now;
+    it->second.status = e == hipSuccess ? BIN_OK : BIN_ERR_DEVICE;
+    if (e == hipSuccess) s->st.completed++;
+    else s->st.failed++;
+    s->st.in_flight--;
+  }
+  sl->tickets.clear();
+  sl->launched = false;
+  sl->busy = false;
+  s->cv_done.notify_all();
+  dispatch_all(s, lk);
+}
+
+// One per slot: waits for the slot's batch to finish (the completion event,
+// outside the lock) and completes it.
+void slot_waiter(binsrv* s, Slot* sl) {
   (void)hipSetDevice(s->cfg.device);
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
-    poll_slots(s);
-    bool launched = false;
-    while (dispatch_one(s, lk)) launched = true;
-    bool any_busy = false;
-    for (const Slot& sl : s->slots) any_busy |= sl.busy;
-    if (s->stop && s->queue.empty() && !any_busy) break;
-    if (launched) continue;
-    // Sleep until a submission arrives, or briefly while work is in flight
-    // (completion is polled).
-    if (any_busy) s->cv_work.wait_for(lk, std::chrono::microseconds(20));
-    else s->cv_work.wait_for(lk, std::chrono::milliseconds(5));
+    sl->cv.wait(lk, [&] { return sl->launched || (s->quit && !sl->busy); });
+    if (!sl->launched) break;
+    hipEvent_t ev = sl->done;
+    const uint64_t seq = sl->seq;
+    lk.unlock();
+    const hipError_t e = hipEventSynchronize(ev);
+    const clk::time_point now = clk::now();
+    lk.lock();
+    complete_slot(s, sl, seq, e, now, lk);
   }
+}
+
+int check_request(const binsrv_request* req) {
+  bin_output none;
+  std::memset(&none, 0, sizeof none);
+  // Validate with stand-in outputs (the server owns the real ones).
+  void* fake[BIN_MAX_ATTRS];
+  for (int j = 0; j < BIN_MAX_ATTRS; ++j) fake[j] = reinterpret_cast<void*>(uintptr_t(256) * (j + 1));
+  none.count = reinterpret_cast<uint32_t*>(uintptr_t(4096));
+  none.sum = none.min = none.max = none.avg = fake;
+  return validate(&req->coords, &req->attrs, req->n, req->axes, req->bounds, req->nx, req->ny, req->ops, &none,
+                  false);
 }
 
 }  // namespace
@@ -341,20 +492,22 @@ int binsrv_create(const binsrv_config* cfg, binsrv** out) {
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   binsrv* s = new binsrv;
   s->cfg = *cfg;
-  s->slots.resize(cfg->n_slots);
-  for (Slot& sl : s->slots) {
-    e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+  for (int i = 0; i < cfg->n_slots; ++i) {
+    auto sl = std::make_unique<Slot>();
+    e = hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl->done, hipEventDisableTiming);
     if (e != hipSuccess) {
-      for (Slot& x : s->slots) {
-        if (x.done) (void)hipEventDestroy(x.done);
-        if (x.stream) (void)hipStreamDestroy(x.stream);
+      if (sl->stream) (void)hipStreamDestroy(sl->stream);
+      for (auto& x : s->slots) {
+        (void)hipEventDestroy(x->done);
+        (void)hipStreamDestroy(x->stream);
       }
       delete s;
       return hip_fail(e, "server stream setup");
     }
+    s->slots.push_back(std::move(sl));
   }
-  s->thr = std::thread(dispatcher, s);
+  for (auto& sl : s->slots) sl->waiter = std::thread(slot_waiter, s, sl.get());
   {
     std::lock_guard<std::mutex> lk(g_live_mu);
     g_live.insert(s);
@@ -363,57 +516,81 @@ int binsrv_create(const binsrv_config* cfg, binsrv** out) {
   return BIN_OK;
 }
 
-int binsrv_submit(binsrv* s, const binsrv_request* req, uint64_t* ticket) {
+int binsrv_submit(binsrv* srv, const binsrv_request* req, uint64_t* ticket) {
+  const clk::time_point t_arrival = clk::now();
   clear_error();
-  if (!live(s)) return fail(BIN_ERR_INVALID_ARG, "not a live server");
+  SrvRef ref(srv);
+  binsrv* s = ref.s;
+  if (!s) return fail(BIN_ERR_INVALID_ARG, "not a live server");
   if (!req || !ticket) return fail(BIN_ERR_INVALID_ARG, "req or ticket is NULL");
-  bin_output none;
-  std::memset(&none, 0, sizeof none);
-  // Validate with stand-in outputs (the server owns the real ones).
-  void* fake[BIN_MAX_ATTRS];
-  for (int j = 0; j < BIN_MAX_ATTRS; ++j) fake[j] = reinterpret_cast<void*>(uintptr_t(256) * (j + 1));
-  none.count = reinterpret_cast<uint32_t*>(uintptr_t(4096));
-  none.sum = none.min = none.max = none.avg = fake;
-  int st = validate(&req->coords, &req->attrs, req->n, req->axes, req->bounds, req->nx, req->ny, req->ops, &none, false);
+  int st = check_request(req);
   if (st) return st;
   SrvReq q;
   q.r = *req;
   q.coord_cols.assign(req->coords.cols, req->coords.cols + req->coords.ncols);
   if (req->attrs.cols && req->attrs.ncols > 0) q.attr_cols.assign(req->attrs.cols, req->attrs.cols + req->attrs.ncols);
   q.out_bytes = grid_bytes_of(*req);
-  // Can it ever fit?  Its grids plus the scratch of running it alone.
-  bin_request alone = as_bin_request(q);
-  void* dummy[BIN_MAX_ATTRS];
-  for (int j = 0; j < BIN_MAX_ATTRS; ++j) dummy[j] = fake[j];
-  alone.out.count = none.count;
-  alone.out.sum = alone.out.min = alone.out.max = alone.out.avg = dummy;
-  const size_t need = batch_scratch_bytes(&alone, 1, &st);
+  // Can it ever fit?  Its grids plus the scratch of running it alone (the
+  // single-request plan that runs a lone request).
+  std::vector<bin_request> alone{as_bin_request(q)};
+  const size_t need = exact_scratch(alone, &st);
   if (st) return st;
   q.scratch_est = need;
-  std::lock_guard<std::mutex> lk(s->mu);
-  if (s->stop) return fail(BIN_ERR_INVALID_ARG, "server is shutting down");
-  if (q.out_bytes + need > s->cfg.budget_bytes)
-    return fail(BIN_ERR_ADMISSION, "request needs %zu bytes, budget is %llu", q.out_bytes + need,
+  if (q.out_bytes + pool_bytes_for(need) > s->cfg.budget_bytes)
+    return fail(BIN_ERR_ADMISSION, "request needs %zu bytes, budget is %llu", q.out_bytes + pool_bytes_for(need),
                 (unsigned long long)s->cfg.budget_bytes);
+  if (req->producer_stream) {
+    hipError_t e = hipEventCreateWithFlags(&q.ready, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(q.ready, static_cast<hipStream_t>(req->producer_stream));
+    if (e != hipSuccess) {
+      if (q.ready) (void)hipEventDestroy(q.ready);
+      return hip_fail(e, "record the producer stream's event");
+    }
+  }
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (s->stop) {
+    if (q.ready) (void)hipEventDestroy(q.ready);
+    return fail(BIN_ERR_INVALID_ARG, "server is shutting down");
+  }
   q.ticket = s->next_ticket++;
-  q.t_submit = clk::now();
+  q.t_submit = t_arrival;
   *ticket = q.ticket;
   s->queue.push_back(q.ticket);
   s->reqs.emplace(q.ticket, std::move(q));
   s->st.submitted++;
   s->st.queued = s->queue.size();
-  s->cv_work.notify_one();
+  dispatch_all(s, lk);  // a free slot takes it at once
   return BIN_OK;
 }
 
-int binsrv_wait(binsrv* s, uint64_t ticket, int64_t timeout_ns, bin_result* res) {
+int binsrv_wait(binsrv* srv, uint64_t ticket, int64_t timeout_ns, bin_result* res) {
   clear_error();
-  if (!live(s)) return fail(BIN_ERR_INVALID_ARG, "not a live server");
+  SrvRef ref(srv);
+  binsrv* s = ref.s;
+  if (!s) return fail(BIN_ERR_INVALID_ARG, "not a live server");
   std::unique_lock<std::mutex> lk(s->mu);
   auto done = [&] {
     auto it = s->reqs.find(ticket);
     return it == s->reqs.end() || it->second.state == Q_DONE;
   };
+  // A launched request is observed directly: this thread waits on its
+  // batch's completion event (as a caller of a plain launch would wait on
+  // its stream), so the result is seen without a hand-over between threads.
+  if (timeout_ns < 0) {
+    auto it = s->reqs.find(ticket);
+    if (it != s->reqs.end() && it->second.state == Q_RUNNING && it->second.slot >= 0) {
+      Slot* sl = s->slots[it->second.slot].get();
+      const uint64_t seq = it->second.slot_seq;
+      if (sl->launched && sl->seq == seq) {
+        hipEvent_t ev = sl->done;
+        lk.unlock();
+        const hipError_t e = hipEventSynchronize(ev);
+        const clk::time_point now = clk::now();
+        lk.lock();
+        complete_slot(s, sl, seq, e, now, lk);
+      }
+    }
+  }
   if (timeout_ns < 0) s->cv_done.wait(lk, done);
   else if (!s->cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), done))
     return fail(BIN_ERR_TIMEOUT, "ticket %llu not done after %lld ns", (unsigned long long)ticket, (long long)timeout_ns);
@@ -434,27 +611,35 @@ int binsrv_wait(binsrv* s, uint64_t ticket, int64_t timeout_ns, bin_result* res)
     res->submit_to_done_ms = ms_between(q.t_submit, q.t_done);
     res->queue_ms = q.dispatched ? ms_between(q.t_submit, q.t_dispatch) : 0.0;
   }
-  return q.status;
+  if (q.status != BIN_OK) return fail(q.status, "ticket %llu failed", (unsigned long long)ticket);
+  return BIN_OK;
 }
 
-int binsrv_release(binsrv* s, uint64_t ticket) {
+int binsrv_release(binsrv* srv, uint64_t ticket) {
   clear_error();
-  if (!live(s)) return fail(BIN_ERR_INVALID_ARG, "not a live server");
-  std::lock_guard<std::mutex> lk(s->mu);
+  SrvRef ref(srv);
+  binsrv* s = ref.s;
+  if (!s) return fail(BIN_ERR_INVALID_ARG, "not a live server");
+  std::unique_lock<std::mutex> lk(s->mu);
   auto it = s->reqs.find(ticket);
   if (it == s->reqs.end()) return fail(BIN_ERR_NOT_FOUND, "unknown or already released ticket %llu", (unsigned long long)ticket);
   if (it->second.state != Q_DONE) return fail(BIN_ERR_INVALID_ARG, "ticket %llu is not finished", (unsigned long long)ticket);
   give_block(s, it->second.grids, it->second.grid_bytes);
+  hipEvent_t ready = it->second.ready;
   s->reqs.erase(it);
   s->st.released++;
   s->st.bytes_in_use = in_use(s);
-  s->cv_work.notify_one();  // released memory may admit waiting requests
+  dispatch_all(s, lk);  // the released memory may admit waiting requests
+  lk.unlock();
+  if (ready) (void)hipEventDestroy(ready);
   return BIN_OK;
 }
 
-int binsrv_get_stats(binsrv* s, binsrv_stats* out) {
+int binsrv_get_stats(binsrv* srv, binsrv_stats* out) {
   clear_error();
-  if (!live(s)) return fail(BIN_ERR_INVALID_ARG, "not a live server");
+  SrvRef ref(srv);
+  binsrv* s = ref.s;
+  if (!s) return fail(BIN_ERR_INVALID_ARG, "not a live server");
   if (!out) return fail(BIN_ERR_INVALID_ARG, "stats is NULL");
   std::lock_guard<std::mutex> lk(s->mu);
   s->st.queued = s->queue.size();
@@ -468,21 +653,43 @@ int binsrv_destroy(binsrv* s) {
   {
     std::lock_guard<std::mutex> lk(g_live_mu);
     if (!g_live.count(s)) return fail(BIN_ERR_INVALID_ARG, "not a live server");
-    g_live.erase(s);
+    g_live.erase(s);  // no new references from here on
   }
   {
-    std::lock_guard<std::mutex> lk(s->mu);
+    // Drain: waiting requests still run (a request that can never be
+    // admitted is failed), then the slot waiters exit.
+    std::unique_lock<std::mutex> lk(s->mu);
     s->stop = true;
-    s->cv_work.notify_all();
+    for (;;) {
+      dispatch_all(s, lk);
+      bool busy = s->dispatching > 0;
+      for (auto& sl : s->slots) busy |= sl->busy;
+      if (!busy && !s->queue.empty()) {  // nothing running and the head cannot be admitted
+        SrvReq& q = s->reqs[s->queue.front()];
+        s->queue.pop_front();
+        fail_request(s, q, BIN_ERR_ADMISSION);
+        s->cv_done.notify_all();
+        continue;
+      }
+      if (!busy) break;
+      s->cv_done.wait(lk);
+    }
+    s->quit = true;
+    for (auto& sl : s->slots) sl->cv.notify_one();
   }
-  s->thr.join();  // drains the queue and in-flight batches
-  for (Slot& sl : s->slots) {
-    (void)hipStreamSynchronize(sl.stream);
-    (void)hipEventDestroy(sl.done);
-    (void)hipStreamDestroy(sl.stream);
+  for (auto& sl : s->slots) sl->waiter.join();
+  // Calls that took a reference before the server left the live set return
+  // promptly now (every request is done); wait for them.
+  while (s->users.load() > 0) std::this_thread::yield();
+  for (auto& sl : s->slots) {
+    (void)hipStreamSynchronize(sl->stream);
+    (void)hipEventDestroy(sl->done);
+    (void)hipStreamDestroy(sl->stream);
   }
-  for (auto& kv : s->reqs)
+  for (auto& kv : s->reqs) {
     if (kv.second.grids) (void)hipFree(kv.second.grids);
+    if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
+  }
   for (auto& kv : s->pool)
     for (void* p : kv.second) (void)hipFree(p);
   delete s;

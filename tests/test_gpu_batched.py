@@ -212,8 +212,13 @@ def test_multi_grid_nine_planes_ten_variables():
     for (a, b), bd, side in zip(tab.planes, tab.bounds, sides):
         out = B.alloc_outputs(cols, side, side // 2 + 1, 31, "cuda")
         grids.append(dict(axes=(a, b), bounds=bd, nx=side, ny=side // 2 + 1, ops=31, out=out))
+    B.bin_timing_enable(True)
     B.bin_particles_multi(cols, cols, tab.n, grids)
     torch.cuda.synchronize()
+    B.bin_timing_enable(False)
+    rep = B.bin_timing_report()
+    assert rep.get("part_scatter_multi_kernel", (0, 0))[0] == 1, rep  # one fused pass over the table
+    assert "part_scatter_kernel" not in rep, rep
     for g, grid in enumerate(grids):
         ws = synth.Workload(tab.columns, tab.columns, axes=grid["axes"], bounds=grid["bounds"], nx=grid["nx"],
                             ny=grid["ny"], ops=31)
@@ -230,3 +235,64 @@ def test_multi_grid_nine_planes_ten_variables():
         for key in ("sum", "avg"):
             for x, y in zip(got[key], a[key]):
                 assert np.allclose(x, y, rtol=1e-12, atol=1e-9, equal_nan=True), (g, key)
+
+
+_TUNE_CHILD = r'''
+import json, sys
+import numpy as np
+import torch
+sys.path.insert(0, sys.argv[1])
+from paper_2310_02926_amd import binding as B
+from paper_2310_02926_amd import synth
+from tests import gpu_check as G
+ws = synth.gmm_f32(n=200_000, seed=9, nx=256, ny=256, k=1)
+c, a = G.to_device(ws)
+out = B.alloc_outputs(a, ws.nx, ws.ny, ws.ops, "cuda")
+req, keep = B.request(c, a, ws.n, ws.axes, ws.bounds, ws.nx, ws.ny, ws.ops, out)
+before = B.bin_describe_plan(req)
+if sys.argv[2] == "tune":
+    B.bin_autotune([dict(coords=c, attrs=a, n=ws.n, axes=ws.axes, bounds=ws.bounds, nx=ws.nx, ny=ws.ny,
+                         ops=ws.ops, out=out)])
+print(json.dumps({"before": before, "after": B.bin_describe_plan(req),
+                  "arch": torch.cuda.get_device_properties(0).gcnArchName.split(":")[0],
+                  "cus": torch.cuda.get_device_properties(0).multi_processor_count}))
+'''
+
+
+def test_autotune_cache_is_json_keyed_by_device(tmp_path):
+    """BIN_TUNE_CACHE: the autotuner writes JSON entries keyed by the
+    device's architecture and compute units, with every hint (quads
+    included); a fresh process reads them back and plans with them; entries
+    for another device are ignored."""
+    import json
+    import os
+    import subprocess
+    import sys as _sys
+    _case("autotune cache")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    script = tmp_path / "child.py"
+    script.write_text(_TUNE_CHILD)
+    cache = tmp_path / "tune.json"
+    env = dict(os.environ, BIN_TUNE_CACHE=str(cache))
+
+    def child(mode):
+        p = subprocess.run([_sys.executable, str(script), root, mode], capture_output=True, text=True, env=env,
+                           timeout=300, cwd=root)
+        assert p.returncode == 0, p.stderr[-2000:]
+        return json.loads(p.stdout.strip().splitlines()[-1])
+
+    tuned = child("tune")
+    doc = json.loads(cache.read_text())
+    assert doc["version"] == 1 and doc["entries"]
+    prefix = f"{tuned['arch']}:{tuned['cus']}|"
+    for key, e in doc["entries"].items():
+        assert key.startswith(prefix), key
+        assert set(e) == {"strategy", "block", "grid", "part_wg", "scatter_ppt", "scatter_threads", "tile_shift",
+                          "split_len", "quads"}, e
+    again = child("plan")
+    assert again["before"] == tuned["after"]  # the fresh process plans with the cached entry
+    # the same entries filed under another device are not used here
+    doc["entries"] = {"gfx000:1|" + k.split("|", 1)[1]: v for k, v in doc["entries"].items()}
+    cache.write_text(json.dumps(doc))
+    other = child("plan")
+    assert other["before"] == tuned["before"]
