@@ -212,12 +212,16 @@ int bin_validate_nd(const bin_columns* coords, const bin_columns* attrs, int64_t
                     const bin_output* out);
 
 /* ---- batched entry point ------------------------------------------------ */
-/* Run nreq independent requests (uneven n and grid sizes allowed) in one
- * persistent kernel launch on 'stream' (plus one initialisation and one
- * finalisation launch for the whole batch).  Each result equals what
- * bin_particles gives for the same request, within the sum tolerance; counts,
- * min and max are identical.  Requests must not share output buffers.  The
- * request array is read during the call only.  Enqueues and returns. */
+/* Run nreq independent requests (uneven n and grid sizes allowed) on
+ * 'stream'.  Requests are planned one by one and grouped by strategy, element
+ * types, precision, scatter shape and gather form; each group runs one
+ * table-driven launch per stage (scatter, work items, tile binning, merge;
+ * or whole-grid LDS binning and merge) for all its requests, a block map
+ * listing each block's request and index.  Each result equals
+ * what bin_particles gives for the same request, within the sum tolerance;
+ * counts, min and max are identical.  Requests must not share output
+ * buffers.  The request array is read during the call only.  Enqueues and
+ * returns. */
 int bin_particles_batched(const bin_request* reqs, int32_t nreq, void* stream);
 
 /* ---- asynchronous in situ binning ------------------------------------------ */

@@ -1,13 +1,15 @@
 // Batched binning: many independent requests of uneven size run as a few
-// table-driven launches (one per kernel stage and request group) instead of
-// a launch sequence per request.  Also the HIP-graph capture of a batch.
+// launches instead of a launch sequence per request.  Also the HIP-graph
+// capture of a batch, and the fused multi-grid path (several grids over
+// one table).
 //
 // Requests are planned one by one, then grouped by (strategy, coordinate
-// type, attribute type, precision).  A partition group shares one
-// concatenated count matrix (one global scan gives every request its record
-// offsets) and one concatenated record array; an LDS group shares nothing
-// but the launches.  Requests that need the global-atomic strategy run one
-// by one.
+// type, attribute type, precision) and, for tile partitions, by the scatter
+// shape and gather form their own plans chose.  Every request keeps its own
+// scratch (records, run table, counts, items, partial slots); the groups
+// share device tables of descriptors and block maps, uploaded once, and
+// each group runs one table-driven launch per stage for all its requests.
+// Requests that need the global-atomic strategy run one by one.
 #include <algorithm>
 #include <cstring>
 #include <map>
@@ -38,16 +40,6 @@ struct PartGroup {
   bk::PartBatch b{};
   size_t desc_off = 0, map_wg_off = 0, map_walk_off = 0, map_item_off = 0, map_tile_off = 0;
   std::vector<uint32_t> map_wg, map_walk, map_item, map_tile;
-  // Persistent launch (1024-thread scatter shapes): the work list, its
-  // control words, and the LDS group it also runs (index, or -1).
-  bool persist = false;
-  int lds_group = -1;
-  std::vector<uint32_t> items;
-  size_t items_off = 0;
-  uint32_t* ctl = nullptr;
-  uint32_t ctl_words = 0;
-  size_t persist_lds = 0;
-  bk::PersistBatch pb{};
 };
 
 struct LdsGroup {
@@ -60,7 +52,6 @@ struct LdsGroup {
   bk::LdsBatch b{};
   size_t desc_off = 0, map_slot_off = 0, map_merge_off = 0;
   std::vector<uint32_t> map_slot, map_merge;
-  bool in_persist = false;  // run by a partition group's persistent launch
 };
 
 }  // namespace
@@ -79,7 +70,7 @@ namespace {
 
 // Pass 1 (base == nullptr) sizes everything; pass 2 lays out pointers.
 int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const PlanHints& hints,
-               unsigned char* base, BatchPlan* bp, bool allow_persist = true) {
+               unsigned char* base, BatchPlan* bp) {
   bp->preps.assign(nreq, Prepared{});
   bp->part.clear();
   bp->lds.clear();
@@ -248,62 +239,6 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
     g.b.n_slot_blocks = (int32_t)g.map_slot.size();
     g.b.n_merge_blocks = (int32_t)g.map_merge.size();
   }
-  // --- persistent launches: a partition group whose scatter runs 1024
-  // threads takes every stage of its requests in one launch, together with
-  // the LDS requests of the same types.  Work list in dependency order,
-  // larger requests first within each stage.
-  for (auto& g : bp->part) {
-    g.persist = allow_persist && g.nt == 1024 && (g.ppt == 4 || g.ppt == 8);
-    if (!g.persist) continue;
-    g.lds_group = -1;
-    for (size_t li = 0; li < bp->lds.size(); ++li) {
-      LdsGroup& lg = bp->lds[li];
-      if (!lg.in_persist && lg.cf64 == g.cf64 && lg.af64 == g.af64 && lg.prec == g.prec && lg.block <= 1024) {
-        lg.in_persist = true;
-        g.lds_group = (int)li;
-        break;
-      }
-    }
-    const LdsGroup* lg = g.lds_group >= 0 ? &bp->lds[g.lds_group] : nullptr;
-    const int R = (int)g.args.size();
-    const int RL = lg ? (int)lg->args.size() : 0;
-    auto item = [&](int kind, int r, uint32_t i) {
-      g.items.push_back(((uint32_t)kind << 24) | (uint32_t)r);
-      g.items.push_back(i);
-    };
-    // requests by size, largest first (partition: r, LDS: R + r)
-    std::vector<int> order;
-    for (int r = 0; r < R + RL; ++r) order.push_back(r);
-    auto n_of = [&](int r) { return r < R ? g.args[r].n : lg->args[r - R].n; };
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return n_of(x) > n_of(y); });
-    g.items.clear();
-    for (int r : order) {
-      if (r < R)
-        for (int w = 0; w < g.args[r].nwg; ++w) item(bk::PK_SCATTER, r, (uint32_t)w);
-      else
-        for (int c = 0; c < lg->args[r - R].nslots; ++c) item(bk::PK_LDS, r - R, (uint32_t)c);
-    }
-    for (int r : order)
-      if (r < R)
-        for (int b = 0; b < (g.args[r].ntiles + 15) / 16; ++b) item(bk::PK_WALK, r, (uint32_t)b);
-    for (int r : order)
-      if (r < R) item(bk::PK_PLACE, r, 0u);
-    for (int r : order)
-      if (r < R)
-        for (int i = 0; i < g.args[r].max_items; ++i) item(bk::PK_BIN, r, (uint32_t)i);
-    for (int r : order)
-      if (r < R)
-        for (int b = 0; b < g.args[r].merge_blocks; ++b) item(bk::PK_MERGE, r, (uint32_t)b);
-    g.ctl_words = 2 + 4 * (uint32_t)R + (uint32_t)RL;
-    g.ctl = reinterpret_cast<uint32_t*>(take(4 * (size_t)g.ctl_words));
-    // LDS: the largest stage of any item (the merge and placement
-    // workspaces included).
-    size_t lds = std::max({g.cfg.scatter_lds, g.cfg.bin_lds, (size_t)(4 * (16 + 4096)), (size_t)(16 * 64 * 28)});
-    if (lg) lds = std::max(lds, lg->lds_bytes);
-    g.persist_lds = lds;
-    if (lds + 256 > dev.lds_per_block) g.persist = false;
-    if (!g.persist && lg) bp->lds[g.lds_group].in_persist = false;
-  }
   // --- tables: descriptors and maps, one upload
   size_t t = 0;
   auto tab = [&](size_t bytes) {
@@ -317,7 +252,6 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
     g.map_walk_off = tab(4 * g.map_walk.size());
     g.map_item_off = tab(4 * g.map_item.size());
     g.map_tile_off = tab(4 * g.map_tile.size());
-    if (g.persist) g.items_off = tab(4 * g.items.size());
   }
   for (auto& g : bp->lds) {
     g.desc_off = tab(sizeof(bk::LdsArgs) * g.args.size());
@@ -351,35 +285,16 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
     g.b.map_slot = reinterpret_cast<const uint32_t*>(tdev + g.map_slot_off);
     g.b.map_merge = reinterpret_cast<const uint32_t*>(tdev + g.map_merge_off);
   }
-  for (auto& g : bp->part) {
-    if (!g.persist) continue;
-    std::memcpy(h + g.items_off, g.items.data(), 4 * g.items.size());
-    bk::PersistBatch& pb = g.pb;
-    pb.part = g.b.descs;
-    pb.lds = g.lds_group >= 0 ? bp->lds[g.lds_group].b.descs : nullptr;
-    pb.items = reinterpret_cast<const uint32_t*>(tdev + g.items_off);
-    pb.ctl = g.ctl;
-    pb.nitems = (uint32_t)(g.items.size() / 2);
-    pb.npart = (int32_t)g.args.size();
-    pb.nlds = g.lds_group >= 0 ? (int32_t)bp->lds[g.lds_group].args.size() : 0;
-    pb.wait_ticks = 200000000;  // 2 s of the 100 MHz clock: far beyond any batch
-  }
   return BIN_OK;
 }
 
 // Kernel launches of a laid-out batch (tables already on the device).
-int launch_batch(const BatchPlan& bp, hipStream_t s, bk::KTimer* tm, int cus) {
+int launch_batch(const BatchPlan& bp, hipStream_t s, bk::KTimer* tm) {
   for (const auto& g : bp.part) {
-    hipError_t e;
-    if (g.persist)
-      e = bk::launch_persist(g.pb, g.ctl_words, g.cf64, g.af64, g.prec, g.ppt, g.quads,
-                             std::max(1, std::min(cus, (int)g.pb.nitems)), g.persist_lds, s, tm);
-    else
-      e = bk::launch_partition_batch(g.b, g.cf64, g.af64, g.prec, g.cfg, s, tm);
+    hipError_t e = bk::launch_partition_batch(g.b, g.cf64, g.af64, g.prec, g.cfg, s, tm);
     if (e != hipSuccess) return hip_fail(e, "launch batched partition kernels");
   }
   for (const auto& g : bp.lds) {
-    if (g.in_persist) continue;
     hipError_t e = bk::launch_lds_batch(g.b, g.cf64, g.af64, g.prec, g.lds_bytes, g.block, s, tm);
     if (e != hipSuccess) return hip_fail(e, "launch batched LDS kernels");
   }
@@ -534,12 +449,12 @@ bool run_multi_fused(const bin_request* reqs, int nreq, hipStream_t s, int* stat
       const int f = std::min(F, std::max(1, (int)a.nbpw));
       int sh = 0;
       while ((1 << (sh + 1)) <= f) ++sh;
-      o = al16(o + 2 * ((size_t)a.ntiles + 1) << sh);
+      o = al16(o + ((2 * ((size_t)a.ntiles + 1)) << sh));
     }
     m.stage_b = (int32_t)o;
     o = al16(o + 2 * (size_t)S);
     m.stage_v = (int32_t)o;
-    o = al16(o + 4 * (size_t)S);
+    o = al16(o + 2 * (size_t)S);
     if (o <= limit) {
       m.sub = S;
       m.ncols = (int32_t)cols.size();
@@ -601,7 +516,7 @@ bool run_multi_fused(const bin_request* reqs, int nreq, hipStream_t s, int* stat
   return false;
 }
 
-int run_batch(const bin_request* reqs, int nreq, hipStream_t s, const PlanHints& hints, bool allow_persist) {
+int run_batch(const bin_request* reqs, int nreq, hipStream_t s, const PlanHints& hints) {
   int st = validate_requests(reqs, nreq);
   if (st) return st;
   if (nreq == 0) return BIN_OK;
@@ -610,17 +525,17 @@ int run_batch(const bin_request* reqs, int nreq, hipStream_t s, const PlanHints&
   st = device_info(&dev);
   if (st) return st;
   BatchPlan bp;
-  st = plan_batch(reqs, nreq, dev, hints, nullptr, &bp, allow_persist);
+  st = plan_batch(reqs, nreq, dev, hints, nullptr, &bp);
   if (st) return st;
   void* scratch = nullptr;
   st = scratch_get(dev.device, s, bp.scratch_bytes, &scratch);
   if (st) return st;
-  st = plan_batch(reqs, nreq, dev, hints, static_cast<unsigned char*>(scratch), &bp, allow_persist);
+  st = plan_batch(reqs, nreq, dev, hints, static_cast<unsigned char*>(scratch), &bp);
   if (st) return st;
   st = upload_tables(bp, static_cast<unsigned char*>(scratch), s);
   if (st) return st;
   bk::KTimer* tm = timing_timer();
-  st = launch_batch(bp, s, tm, dev.cus);
+  st = launch_batch(bp, s, tm);
   if (st) return st;
   for (int i : bp.global_reqs) {
     st = run_request(reqs[i], s, hints);
@@ -629,14 +544,14 @@ int run_batch(const bin_request* reqs, int nreq, hipStream_t s, const PlanHints&
   return BIN_OK;
 }
 
-size_t batch_scratch_bytes(const bin_request* reqs, int nreq, int* status, bool allow_persist) {
+size_t batch_scratch_bytes(const bin_request* reqs, int nreq, int* status) {
   *status = validate_requests(reqs, nreq);
   if (*status || nreq == 0) return 0;
   DeviceInfo dev;
   *status = device_info(&dev);
   if (*status) return 0;
   BatchPlan bp;
-  *status = plan_batch(reqs, nreq, dev, thread_hints(), nullptr, &bp, allow_persist);
+  *status = plan_batch(reqs, nreq, dev, thread_hints(), nullptr, &bp);
   if (*status) return 0;
   size_t extra = 0;  // requests on the global strategy use their own scratch
   for (int i : bp.global_reqs) extra += al256(bp.preps[i].scratch_bytes);
@@ -731,7 +646,7 @@ int bin_graph_create(const bin_request* reqs, int32_t nreq, bin_graph** out) {
     if (e != hipSuccess) st = hip_fail(e, "hipStreamBeginCapture");
   }
   if (st == BIN_OK) {
-    const int lst = launch_batch(bp, cs, nullptr, dev.cus);
+    const int lst = launch_batch(bp, cs, nullptr);
     e = hipStreamEndCapture(cs, &g->graph);
     if (lst) st = lst;
     else if (e != hipSuccess) st = hip_fail(e, "hipStreamEndCapture");

@@ -186,6 +186,9 @@ template <typename AT, int PREC>
 struct Tile {
   using K = typename KeyOf<AT>::T;
   static constexpr int kSumBytes = (PREC == PREC_PLAIN) ? 4 : 8;
+  // Element of local bin b in the min (or max) array: interleaved pairs
+  // when both are kept.
+  __device__ static int mm(const TileLayout& L, int b) { return L.mm_pair ? 2 * b : b; }
 
   __device__ static void init(unsigned char* smem, const TileLayout& L, int k) {
     const int tb = L.tb;
@@ -199,11 +202,11 @@ struct Tile {
       }
       if (L.want_min) {
         K* m = reinterpret_cast<K*>(smem + L.lds_min_off[j]);
-        for (int b = threadIdx.x; b < tb; b += blockDim.x) m[b] = fkey((AT)INFINITY);
+        for (int b = threadIdx.x; b < tb; b += blockDim.x) m[mm(L, b)] = fkey((AT)INFINITY);
       }
       if (L.want_max) {
         K* m = reinterpret_cast<K*>(smem + L.lds_max_off[j]);
-        for (int b = threadIdx.x; b < tb; b += blockDim.x) m[b] = fkey((AT)-INFINITY);
+        for (int b = threadIdx.x; b < tb; b += blockDim.x) m[mm(L, b)] = fkey((AT)-INFINITY);
       }
     }
   }
@@ -231,11 +234,11 @@ struct Tile {
     if (L.want_min || L.want_max) {
       const K kv = fkey(v);
       if (L.want_min) {
-        K* m = reinterpret_cast<K*>(smem + L.lds_min_off[j]) + b;
+        K* m = reinterpret_cast<K*>(smem + L.lds_min_off[j]) + mm(L, b);
         if (kv < __hip_atomic_load(m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) atomicMin(m, kv);
       }
       if (L.want_max) {
-        K* m = reinterpret_cast<K*>(smem + L.lds_max_off[j]) + b;
+        K* m = reinterpret_cast<K*>(smem + L.lds_max_off[j]) + mm(L, b);
         if (kv > __hip_atomic_load(m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) atomicMax(m, kv);
       }
     }
@@ -279,14 +282,23 @@ struct Tile {
       for (int u = 0; u < R; ++u) {
         kv[u] = fkey(v[u]);
         const int b = lb[u] >= 0 ? lb[u] : 0;
-        cmin[u] = L.want_min ? __hip_atomic_load(mn + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : K(0);
-        cmax[u] = L.want_max ? __hip_atomic_load(mx + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : K(0);
+        if constexpr (sizeof(K) == 4) {
+          if (L.mm_pair) {  // both keys of the bin in one 8-byte read
+            const long long pr = __hip_atomic_load(reinterpret_cast<const long long*>(mn + 2 * b), __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            cmin[u] = (K)(int)(pr & 0xFFFFFFFFll);
+            cmax[u] = (K)(int)(pr >> 32);
+            continue;
+          }
+        }
+        cmin[u] = L.want_min ? __hip_atomic_load(mn + mm(L, b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : K(0);
+        cmax[u] = L.want_max ? __hip_atomic_load(mx + mm(L, b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : K(0);
       }
 #pragma unroll
       for (int u = 0; u < R; ++u) {
         if (lb[u] < 0) continue;
-        if (L.want_min && kv[u] < cmin[u]) atomicMin(mn + lb[u], kv[u]);
-        if (L.want_max && kv[u] > cmax[u]) atomicMax(mx + lb[u], kv[u]);
+        if (L.want_min && kv[u] < cmin[u]) atomicMin(mn + mm(L, lb[u]), kv[u]);
+        if (L.want_max && kv[u] > cmax[u]) atomicMax(mx + mm(L, lb[u]), kv[u]);
       }
     }
   }
@@ -305,10 +317,10 @@ struct Tile {
     }
   }
   __device__ static K min_get(const unsigned char* smem, const TileLayout& L, int j, int b) {
-    return reinterpret_cast<const K*>(smem + L.lds_min_off[j])[b];
+    return reinterpret_cast<const K*>(smem + L.lds_min_off[j])[mm(L, b)];
   }
   __device__ static K max_get(const unsigned char* smem, const TileLayout& L, int j, int b) {
-    return reinterpret_cast<const K*>(smem + L.lds_max_off[j])[b];
+    return reinterpret_cast<const K*>(smem + L.lds_max_off[j])[mm(L, b)];
   }
 
   // Final values of attribute j in one bin: sum (binary64 or float), min/max

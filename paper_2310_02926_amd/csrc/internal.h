@@ -135,11 +135,9 @@ struct FixedScratch {
 int run_request_in(const bin_request& r, hipStream_t s, const PlanHints& hints, const FixedScratch* fixed,
                    bk::KTimer* tm);
 int run_auto_bounds_in(const bin_request& r, hipStream_t s, const FixedScratch* fixed, bk::KTimer* tm);
-// A batch; groups of 1024-thread scatter shapes run as one persistent
-// launch unless allow_persist is false (then one launch per stage).
-int run_batch(const bin_request* reqs, int nreq, hipStream_t s, const PlanHints& hints, bool allow_persist = true);
+int run_batch(const bin_request* reqs, int nreq, hipStream_t s, const PlanHints& hints);
 // Device scratch a batch needs (0 and *status set on a bad batch).
-size_t batch_scratch_bytes(const bin_request* reqs, int nreq, int* status, bool allow_persist = true);
+size_t batch_scratch_bytes(const bin_request* reqs, int nreq, int* status);
 
 }  // namespace binimpl
 

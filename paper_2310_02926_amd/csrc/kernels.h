@@ -50,7 +50,9 @@ struct TileLayout {
   int32_t tile_shift;  // TB = 1 << tile_shift (partition); LDS strategy: TB = nbins
   int32_t tb;          // bins held in LDS per tile
   int32_t want_sum;    // accumulate sums (SUM or AVG requested)
-  int32_t want_min, want_max, pad;
+  int32_t want_min, want_max;
+  int32_t mm_pair;     // min and max both kept: interleaved in LDS (min of local bin b at
+                       // element 2b of the min array, max at 2b + 1 = the max array's 2b)
 };
 
 // ---- global-atomic strategy ---------------------------------------------
@@ -179,29 +181,6 @@ struct PartBatch {
   int32_t nreq, n_wg_blocks, n_walk_blocks, n_item_blocks, n_tile_blocks;
 };
 
-// ---- persistent batch ------------------------------------------------------
-// One launch runs every stage of a group of tile-partition requests (and
-// the whole-grid LDS requests of the same types) from a device work list.
-// Items (two words each: kind << 24 | request, index) in dependency order:
-// LDS chunks and scatter slices (largest request first), then work-item
-// walks, placements, tile binnings and merges.  A workgroup takes the next
-// item from a queue head (atomic), waits - bounded - until the stage its item
-// depends on has finished for that request (per-request counters, release /
-// acquire), runs it and counts it done.  The last workgroup to finish a
-// chunk of an LDS request merges that request's partial slots.
-enum PersistKind { PK_LDS = 0, PK_SCATTER = 1, PK_WALK = 2, PK_PLACE = 3, PK_BIN = 4, PK_MERGE = 5 };
-struct PersistBatch {
-  const PartArgs* part;    // partition requests of the group (descriptors)
-  const LdsArgs* lds;      // LDS-strategy requests run by the same launch, or null
-  const uint32_t* items;   // [nitems][2]
-  uint32_t* ctl;           // [0] queue head, [1] abort flag, then 4 counters per
-                           // partition request (scatter, walk, place, bin done),
-                           // then 1 per LDS request (chunks done); zeroed before the launch
-  uint32_t nitems;
-  int32_t npart, nlds, pad;
-  int64_t wait_ticks;      // longest wait for a stage (100 MHz clock) before the batch is abandoned
-};
-
 // ---- several grids over one table: the fused scatter -----------------------
 // Every grid's requests share the table, n, the slices and the sub-chunk
 // size; per sub-chunk the union of the columns the grids read (f32) is
@@ -219,7 +198,7 @@ struct MultiScatterArgs {
   int32_t grid_ost[kMultiGrids];    // byte offset of grid g's staged run-table rows
   int32_t ngrids, ncols, k;
   int32_t cols_lds;                 // byte offset of the staged columns ([ncols][sub] floats)
-  int32_t stage_b, stage_v;         // byte offsets of the record stage (bins u16, values f32)
+  int32_t stage_b, stage_v;         // byte offsets of the record stage: bins and source particles (u16 each)
   int32_t sub;                      // particles per sub-chunk
   int32_t vec;                      // every column 16-byte aligned: staged with 16-byte loads
 };
@@ -282,10 +261,7 @@ hipError_t launch_scatter_multi(const MultiScatterArgs* args, int nwg, size_t ld
 // The stages after the scatter of a batch of partition requests.
 hipError_t launch_partition_batch_after_scatter(const PartBatch& b, bool coord_f64, bool attr_f64, int prec,
                                                 const PartCfg& c, hipStream_t s, KTimer* tm);
-// Persistent batch: zero the control words, then the persistent launch
-// (grid workgroups of 1024 threads, lds bytes of dynamic LDS).
-hipError_t launch_persist(const PersistBatch& b, uint32_t ctl_words, bool coord_f64, bool attr_f64, int prec,
-                          int ppt, bool quads, int grid, size_t lds, hipStream_t s, KTimer* tm);
+
 hipError_t launch_fold(const FoldArgs& a, bool coord_f64, int cus, hipStream_t s, KTimer* tm);
 
 }  // namespace bk

@@ -1,5 +1,5 @@
-// Body of the whole-grid LDS strategy, shared by its own kernels and the
-// persistent batch kernel: one workgroup bins particles [wg * chunk,
+// Body of the whole-grid LDS strategy, shared by its single-request and
+// batched kernels: one workgroup bins particles [wg * chunk,
 // (wg + 1) * chunk) of a request into the grid held in LDS, then writes the
 // finished outputs (a lone workgroup) or its accumulators as partial slot wg.
 #ifndef BINNING_LDS_BODY_H

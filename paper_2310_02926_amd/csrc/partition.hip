@@ -38,7 +38,6 @@
 
 #include "device_common.h"
 #include "kernels.h"
-#include "lds_body.h"
 
 namespace bk {
 
@@ -951,8 +950,10 @@ hipError_t launch_partition_batch_after_scatter(const PartBatch& b, bool coord_f
 // workgroup per slice; per sub-chunk of S = 4 * NT particles: the union of
 // the columns is staged in LDS once, then each grid in turn ranks the
 // sub-chunk's inside particles within its tiles, one wave scans the tile
-// counts, and the records are placed in LDS in tile order and written back
-// over the sub-chunk's own index range - the layout, run table and per-slice
+// counts, and the records' bins and source particles are placed in LDS in
+// tile order; each output column (bins, then every attribute's values read
+// from the staged columns through that permutation) is written back over
+// the sub-chunk's own index range - the layout, run table and per-slice
 // counts the single-grid scatter writes (with sub-chunks of S particles).
 // The particle table is read from HBM once for all grids.
 // ---------------------------------------------------------------------------
@@ -969,7 +970,7 @@ __global__ __launch_bounds__(NT) void part_scatter_multi_kernel(const MultiScatt
   const int64_t hi = lo + a0.chunk < a0.n ? lo + a0.chunk : a0.n;
   float* cols = reinterpret_cast<float*>(smem + m.cols_lds);
   uint16_t* stg_b = reinterpret_cast<uint16_t*>(smem + m.stage_b);
-  float* stg_v = reinterpret_cast<float*>(smem + m.stage_v);
+  uint16_t* perm = reinterpret_cast<uint16_t*>(smem + m.stage_v);
   for (int g = 0; g < m.ngrids; ++g) {
     const int T = m.grids[g].ntiles;
     uint32_t* c = reinterpret_cast<uint32_t*>(smem + m.grid_lds[g]);
@@ -1053,17 +1054,23 @@ __global__ __launch_bounds__(NT) void part_scatter_multi_kernel(const MultiScatt
       const int F = 1 << a.off_shift;
       for (int t = threadIdx.x; t <= T; t += NT) {
         ost[(t << a.off_shift) + (j & (F - 1))] = (uint16_t)(t < T ? off[t] : nsub);
-        if (a.quads && t < T) {  // pad the run to a whole quad
+        if (a.quads && t < T) {  // pad the run to a whole quad (no particle: value 0)
           const uint32_t cc = cnt[t];
           const uint32_t e = off[t] + ((cc + 3u) & ~3u);
-          for (uint32_t p = off[t] + cc; p < e; ++p) stg_b[p] = 0xFFFFu;
+          for (uint32_t p = off[t] + cc; p < e; ++p) {
+            stg_b[p] = 0xFFFFu;
+            perm[p] = 0xFFFFu;
+          }
         }
       }
+      // Records in tile order: the local bin, and the particle (its index in
+      // the sub-chunk) each slot takes its values from.
 #pragma unroll
       for (int q = 0; q < PPT; ++q)
         if (tb[q] != 0xFFFFFFFFu) {
           pos[q] += off[tb[q] >> 16];
           stg_b[pos[q]] = (uint16_t)(tb[q] & 0xFFFFu);
+          perm[pos[q]] = (uint16_t)(q * NT + threadIdx.x);
         }
       __syncthreads();
       // run-table rows [j0, j] of the slice once F are staged or at its end
@@ -1078,23 +1085,17 @@ __global__ __launch_bounds__(NT) void part_scatter_multi_kernel(const MultiScatt
           if (jj < f) a.blk_off[(int64_t)t * nrows + r0 + jj] = ost[i2];
         }
       }
+      // One contiguous stream per output column: the bins, then each
+      // attribute's values gathered from the staged columns through perm.
       const int64_t rbase = base + ((int64_t)w * a.nbpw + j) * (int64_t)a.pad_row;
       for (uint32_t p = threadIdx.x; p < nsub; p += NT) __builtin_nontemporal_store(stg_b[p], a.rec_bin + rbase + p);
       for (int jx = 0; jx < a.k; ++jx) {
         const float* vs = cols + (int64_t)m.attr_col[jx] * S;
-        if (a.quads)  // padding values are 0 (never read as data)
-          for (int t = threadIdx.x; t < T; t += NT) {
-            const uint32_t cc = cnt[t];
-            const uint32_t e = off[t] + ((cc + 3u) & ~3u);
-            for (uint32_t p = off[t] + cc; p < e; ++p) stg_v[p] = 0.0f;
-          }
-#pragma unroll
-        for (int q = 0; q < PPT; ++q)
-          if (tb[q] != 0xFFFFFFFFu) stg_v[pos[q]] = vs[q * NT + threadIdx.x];
-        __syncthreads();
         float* rv = static_cast<float*>(a.rec_val[jx]) + rbase;
-        for (uint32_t p = threadIdx.x; p < nsub; p += NT) __builtin_nontemporal_store(stg_v[p], rv + p);
-        __syncthreads();  // the stage is reused by the next attribute
+        for (uint32_t p = threadIdx.x; p < nsub; p += NT) {
+          const uint32_t src = perm[p];
+          __builtin_nontemporal_store(src == 0xFFFFu ? 0.0f : vs[src], rv + p);
+        }
       }
       __syncthreads();  // the bin stage and counters are reused by the next grid
     }
@@ -1114,166 +1115,6 @@ hipError_t launch_scatter_multi(const MultiScatterArgs* args, int nwg, size_t ld
   hipLaunchKernelGGL(part_scatter_multi_kernel<512>, dim3(nwg), dim3(512), lds, s, args);
   if (tm) tm->end("part_scatter_multi_kernel", s);
   return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Persistent batch kernel (see PersistBatch).
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void persist_init_kernel(uint32_t* ctl, uint32_t words) {
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < words; i += gridDim.x * blockDim.x) ctl[i] = 0u;
-}
-
-// Every thread's writes are made visible device-wide, then one thread counts
-// the item done (release).
-__device__ __forceinline__ void persist_signal(uint32_t* ctr) {
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Wait until *ctr >= need (one thread polls with acquire loads and short
-// sleeps), then every thread acquires.  A wait longer than the batch's limit
-// abandons the batch (its results are then not valid); once abandoned, every
-// wait returns false at once and its item is skipped, so the launch always
-// ends and no skipped stage's output is ever read.
-__device__ __forceinline__ bool persist_wait(const uint32_t* ctr, uint32_t need, uint32_t* abort_flag,
-                                             int64_t wait_ticks, int* s_ok) {
-  if (threadIdx.x == 0) {
-    int ok = __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 0 : 1;
-    if (ok && __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
-      const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-      while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
-        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-          ok = 0;
-          break;
-        }
-        if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t0) > wait_ticks) {
-          __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          ok = 0;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(2);
-      }
-    }
-    *s_ok = ok;
-  }
-  __syncthreads();
-  const bool ok = *s_ok != 0;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  return ok;
-}
-
-template <typename CT, typename AT, int PREC, int PPT, bool QUAD>
-__global__ __launch_bounds__(1024) void part_persist_kernel(PersistBatch b) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ uint32_t s_item[2];
-  __shared__ int s_flag;
-  uint32_t* head = b.ctl;
-  uint32_t* abort_flag = b.ctl + 1;
-  uint32_t* pc = b.ctl + 2;               // [npart][4]
-  uint32_t* lc = pc + 4 * (int64_t)b.npart;  // [nlds]
-  for (;;) {
-    if (threadIdx.x == 0) {
-      const uint32_t i = atomicAdd(head, 1u);
-      s_item[0] = i < b.nitems ? b.items[2 * (int64_t)i] : 0xFFFFFFFFu;
-      s_item[1] = i < b.nitems ? b.items[2 * (int64_t)i + 1] : 0u;
-    }
-    __syncthreads();
-    const uint32_t kr = s_item[0], idx = s_item[1];
-    __syncthreads();  // s_item is written again only after every thread has read it
-    if (kr == 0xFFFFFFFFu) break;
-    const uint32_t kind = kr >> 24, r = kr & 0xFFFFFFu;
-    switch (kind) {
-      case PK_LDS: {
-        const LdsArgs& a = b.lds[r];
-        bin_lds_body<CT, AT, PREC>(a, (int)idx);
-        if (a.nslots <= 1) break;  // a lone workgroup wrote the outputs
-        // The last chunk to finish merges the request's slots (acq_rel count).
-        __threadfence();
-        __syncthreads();
-        if (threadIdx.x == 0)
-          s_flag = __hip_atomic_fetch_add(lc + r, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
-                   (uint32_t)a.nslots - 1u;
-        __syncthreads();
-        if (s_flag) {
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-          for (int64_t b0 = 0; b0 < a.nbins; b0 += 64)
-            Tile<AT, PREC>::merge_emit64(static_cast<const unsigned char*>(a.partial), a.lay.slot_bytes, 0u,
-                                         (uint32_t)a.nslots, a.lay, a.out, a.k, b0, a.nbins, 0, smem);
-        }
-        break;
-      }
-      case PK_SCATTER:
-        part_scatter_body<CT, AT, PPT, 1024>(b.part[r], (int)idx);
-        persist_signal(pc + 4 * r + 0);
-        break;
-      case PK_WALK:
-        if (persist_wait(pc + 4 * r + 0, (uint32_t)b.part[r].nwg, abort_flag, b.wait_ticks, &s_flag))
-          part_items_walk_body(b.part[r], (int)idx);
-        persist_signal(pc + 4 * r + 1);
-        break;
-      case PK_PLACE:
-        if (persist_wait(pc + 4 * r + 1, (uint32_t)((b.part[r].ntiles + 15) / 16), abort_flag, b.wait_ticks,
-                         &s_flag))
-          part_items_place_body(b.part[r], reinterpret_cast<uint32_t*>(smem));
-        persist_signal(pc + 4 * r + 2);
-        break;
-      case PK_BIN:
-        if (persist_wait(pc + 4 * r + 2, 1u, abort_flag, b.wait_ticks, &s_flag))
-          part_bin_body<AT, PREC, QUAD>(b.part[r], (int)idx);
-        persist_signal(pc + 4 * r + 3);
-        break;
-      case PK_MERGE:
-        if (persist_wait(pc + 4 * r + 3, (uint32_t)b.part[r].max_items, abort_flag, b.wait_ticks, &s_flag))
-          part_merge_body<AT, PREC>(b.part[r], (int)idx);
-        break;
-      default:
-        break;
-    }
-    __syncthreads();  // the next item may reuse the LDS
-  }
-}
-
-template <typename CT, typename AT, int PREC>
-static hipError_t launch_persist_t(const PersistBatch& b, uint32_t words, int ppt, bool quads, int grid, size_t lds,
-                                   hipStream_t s, KTimer* tm) {
-  hipError_t e;
-  if (tm) tm->begin(s);
-  hipLaunchKernelGGL(persist_init_kernel, dim3((words + 255) / 256 < 64 ? (words + 255) / 256 : 64), dim3(256), 0, s,
-                     b.ctl, words);
-  if (tm) tm->end("persist_init_kernel", s);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-#define BK_PERSIST(P, Q)                                                                                     \
-  if (ppt == P && quads == Q) {                                                                              \
-    if (tm) tm->begin(s);                                                                                    \
-    hipLaunchKernelGGL((part_persist_kernel<CT, AT, PREC, P, Q>), dim3(grid), dim3(1024), lds, s, b);       \
-    if (tm) tm->end("part_persist_kernel", s);                                                               \
-    return hipGetLastError();                                                                                \
-  }
-  BK_PERSIST(4, false)
-  BK_PERSIST(8, false)
-  BK_PERSIST(4, true)
-  BK_PERSIST(8, true)
-#undef BK_PERSIST
-  return hipErrorInvalidConfiguration;
-}
-
-hipError_t launch_persist(const PersistBatch& b, uint32_t ctl_words, bool coord_f64, bool attr_f64, int prec,
-                          int ppt, bool quads, int grid, size_t lds, hipStream_t s, KTimer* tm) {
-  if (coord_f64) {
-    if (attr_f64) return launch_persist_t<double, double, PREC_F64>(b, ctl_words, ppt, quads, grid, lds, s, tm);
-    switch (prec) {
-      case PREC_PLAIN: return launch_persist_t<double, float, PREC_PLAIN>(b, ctl_words, ppt, quads, grid, lds, s, tm);
-      case PREC_COMP: return launch_persist_t<double, float, PREC_COMP>(b, ctl_words, ppt, quads, grid, lds, s, tm);
-      default: return launch_persist_t<double, float, PREC_F64>(b, ctl_words, ppt, quads, grid, lds, s, tm);
-    }
-  }
-  if (attr_f64) return launch_persist_t<float, double, PREC_F64>(b, ctl_words, ppt, quads, grid, lds, s, tm);
-  switch (prec) {
-    case PREC_PLAIN: return launch_persist_t<float, float, PREC_PLAIN>(b, ctl_words, ppt, quads, grid, lds, s, tm);
-    case PREC_COMP: return launch_persist_t<float, float, PREC_COMP>(b, ctl_words, ppt, quads, grid, lds, s, tm);
-    default: return launch_persist_t<float, float, PREC_F64>(b, ctl_words, ppt, quads, grid, lds, s, tm);
-  }
 }
 
 hipError_t set_partition_lds_limit(size_t bytes) {
@@ -1306,18 +1147,6 @@ hipError_t set_partition_lds_limit(size_t bytes) {
   BK_SETF(part_bin_batched<float, PREC_COMP, true>)
   BK_SETF(part_bin_batched<float, PREC_PLAIN, true>)
   BK_SETF(part_bin_batched<double, PREC_F64, true>)
-#define BK_SET_PERSIST(CT, AT, P) \
-  BK_SETF(part_persist_kernel<CT, AT, P, 4, false>) BK_SETF(part_persist_kernel<CT, AT, P, 8, false>) \
-  BK_SETF(part_persist_kernel<CT, AT, P, 4, true>) BK_SETF(part_persist_kernel<CT, AT, P, 8, true>)
-  BK_SET_PERSIST(float, float, PREC_F64)
-  BK_SET_PERSIST(float, float, PREC_COMP)
-  BK_SET_PERSIST(float, float, PREC_PLAIN)
-  BK_SET_PERSIST(float, double, PREC_F64)
-  BK_SET_PERSIST(double, float, PREC_F64)
-  BK_SET_PERSIST(double, float, PREC_COMP)
-  BK_SET_PERSIST(double, float, PREC_PLAIN)
-  BK_SET_PERSIST(double, double, PREC_F64)
-#undef BK_SET_PERSIST
 #undef BK_SET_TYPES
 #undef BK_SET_CA
 #undef BK_SET_NT

@@ -136,16 +136,23 @@ size_t tile_layout(int tb, int k, bool sum, bool mn, bool mx, int prec, size_t a
       lo = align16(lo + lds_sum * tb);
       so = align16(so + slot_sum * tb);
     }
+    // With both min and max kept, the LDS holds them interleaved (one
+    // 8-byte read per record for both filters); slots keep two arrays.
+    L->mm_pair = mn && mx;
     L->lds_min_off[j] = (int32_t)std::min<size_t>(lo, INT32_MAX);
     L->slot_min_off[j] = (int32_t)std::min<size_t>(so, INT32_MAX);
-    if (mn) {
+    if (L->mm_pair) {
+      L->lds_max_off[j] = (int32_t)std::min<size_t>(lo + asz, INT32_MAX);
+      lo = align16(lo + 2 * asz * tb);
+      so = align16(so + asz * tb);
+    } else if (mn) {
       lo = align16(lo + asz * tb);
       so = align16(so + asz * tb);
     }
-    L->lds_max_off[j] = (int32_t)std::min<size_t>(lo, INT32_MAX);
+    if (!L->mm_pair) L->lds_max_off[j] = (int32_t)std::min<size_t>(lo, INT32_MAX);
     L->slot_max_off[j] = (int32_t)std::min<size_t>(so, INT32_MAX);
     if (mx) {
-      lo = align16(lo + asz * tb);
+      if (!L->mm_pair) lo = align16(lo + asz * tb);
       so = align16(so + asz * tb);
     }
   }

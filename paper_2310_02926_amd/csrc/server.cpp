@@ -223,7 +223,7 @@ size_t exact_scratch(std::vector<bin_request>& brs, int* status) {
     *status = prepare(brs[0], dev, PlanHints{}, nullptr, &p);
     return *status ? 0 : p.scratch_bytes;
   }
-  return batch_scratch_bytes(brs.data(), (int)brs.size(), status, false);
+  return batch_scratch_bytes(brs.data(), (int)brs.size(), status);
 }
 
 void fail_request(binsrv* s, SrvReq& q, int status) {
@@ -365,12 +365,9 @@ bool dispatch_one(binsrv* s, std::unique_lock<std::mutex>& lk) {
     const hipError_t e = hipStreamWaitEvent(sl->stream, ev, 0);
     if (e != hipSuccess && st == BIN_OK) st = hip_fail(e, "hipStreamWaitEvent(producer)");
   }
-  // Batches here run one launch per stage rather than the persistent
-  // launch: several slots run at once, and persistent workgroups waiting for
-  // a stage would hold CUs that the other slots' batches could use.
   if (st == BIN_OK && !run.empty())
     st = run.size() == 1 ? run_request(run[0], sl->stream, PlanHints{})
-                         : run_batch(run.data(), (int)run.size(), sl->stream, PlanHints{}, false);
+                         : run_batch(run.data(), (int)run.size(), sl->stream, PlanHints{});
   const hipError_t er = hipEventRecord(sl->done, sl->stream);
 
   lk.lock();
