@@ -302,8 +302,9 @@ def run_batched(args):
     torch.cuda.synchronize()
     stream = torch.cuda.Stream()
     t0 = time.time()
-    B.bin_autotune(reqs)
-    log(f"autotune {time.time() - t0:.1f}s")
+    if not args.no_autotune:
+        B.bin_autotune(reqs)
+        log(f"autotune {time.time() - t0:.1f}s")
     batch = B.Batch(reqs)
 
     def one_at_a_time():
@@ -338,7 +339,8 @@ def run_batched(args):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batched_256_requests", "n_total": total_n, "input_bytes": in_bytes,
                    "requests": "n log-uniform [1e3,1e7], square side in {32..1024}, 1-4 f32 attrs, random ops",
-                   "tuning": "bin_autotune over the request shapes"},
+                   "tuning": ("the tuning cache or planner defaults" if args.no_autotune
+                              else "bin_autotune over the request shapes")},
         "batched": {"graph_ms": round(ms_graph, 4), "batched_call_ms": round(ms_batch, 4),
                     "one_at_a_time_ms": round(ms_one, 4), "graph_Gps": gp(ms_graph),
                     "batched_call_Gps": gp(ms_batch), "one_at_a_time_Gps": gp(ms_one),
@@ -703,6 +705,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-studies", action="store_true",
                     help="skip the precision study and the bounds-from-data leg of the headline")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched: skip bin_autotune (plans come from the BIN_TUNE_CACHE file, else the planner)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of known size (for HBM counter scaling)")
     args = ap.parse_args()

@@ -248,7 +248,12 @@ int bin_particles_async(const bin_columns* coords, const bin_columns* attrs, int
 /* One binning of the table per grid spec.  The in situ load of the paper's
  * experiments (Section 4.3) bins the same variables over several coordinate
  * systems at every step, each system as its own operator instance run in
- * sequence; here all of them are one enqueue.  Each spec picks its own axes
+ * sequence; here all of them are one enqueue.  When the specs qualify (f32
+ * columns, 2 to 32 specs on the tile partition, at most 40 distinct columns)
+ * the table is read from device memory once: one fused scatter stages each
+ * block of particles' columns on chip and writes every grid's tile-ordered
+ * records, then one tile-binning launch serves all grids.  Other spec sets
+ * run as one batch (bin_particles_batched).  Each spec picks its own axes
  * (two columns of coords), bounds ({xlo, xhi, ylo, yhi}, explicit), mesh,
  * ops and outputs, with the rules of bin_particles; all specs share coords,
  * attrs and n.  Attributes binned on the same axes belong in one spec (k

@@ -210,6 +210,23 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
       if (a.nwg > 65536 || a.max_items > 65536 || a.ntiles > 65536)
         return fail(BIN_ERR_UNSUPPORTED, "request too large for a batch block map");
     }
+    // Workgroups go to the 8 XCDs round-robin.  The tile-binning blocks are
+    // reordered so that each XCD takes runs of C = 8 consecutive items (the
+    // items of neighbouring tiles, whose runs share cache lines, read
+    // through one L2), the runs dealt round-robin so that every XCD gets a
+    // share of every request; 0xFFFFFFFF pads to a whole round.  (Runs of
+    // 8 beat 1, 4 and 32 on the 256-request batch and the nine-plane
+    // multi-grid call.)
+    {
+      const size_t C = 8, round = 8 * C;
+      const size_t nat = g.map_item.size(), npad = (nat + round - 1) / round * round;
+      std::vector<uint32_t> xm(npad);
+      for (size_t b = 0; b < npad; ++b) {
+        const size_t i = b / round * round + (b % 8) * C + (b / 8) % C;
+        xm[b] = i < nat ? g.map_item[i] : 0xFFFFFFFFu;
+      }
+      g.map_item.swap(xm);
+    }
     g.b.n_wg_blocks = (int32_t)g.map_wg.size();
     g.b.n_walk_blocks = (int32_t)g.map_walk.size();
     g.b.n_item_blocks = (int32_t)g.map_item.size();
@@ -431,13 +448,16 @@ bool run_multi_fused(const bin_request* reqs, int nreq, hipStream_t s, int* stat
   BatchPlan bp;
   st = plan_batch(reqs, nreq, dev, h, nullptr, &bp);
   if (st || bp.part.size() != 1 || !bp.lds.empty() || !bp.global_reqs.empty() ||
-      (int)bp.part[0].idx.size() != nreq || bp.part[0].nt != 512 || bp.part[0].ppt != 4)
-    return false;
+      (int)bp.part[0].idx.size() != nreq || bp.part[0].nt != 512 || bp.part[0].ppt != 4 || bp.part[0].quads)
+    return false;  // (the record stages hold kMultiSub records: no quad padding)
   // LDS: staged columns, per grid its counters and staged run-table rows,
-  // the record stage; as many staged rows as fit (a power of two <= 16).
-  const int S = 2048;
+  // the record stages of a group of grids; the largest group, then the most
+  // staged rows (a power of two <= 16), that fit.
+  const int S = bk::kMultiSub;
+  static_assert(bk::kMultiSub == 512 * 4, "the plan's sub-chunk is 512 threads of 4 particles");
   const PartGroup& g0 = bp.part[0];
   const size_t limit = dev.lds_per_block - 256;
+  for (int G = bk::kMultiGroup; G >= 1; --G) {
   for (int F = 16; F >= 1; F /= 2) {
     size_t o = al16((size_t)cols.size() * S * 4);
     m.cols_lds = 0;
@@ -451,12 +471,10 @@ bool run_multi_fused(const bin_request* reqs, int nreq, hipStream_t s, int* stat
       while ((1 << (sh + 1)) <= f) ++sh;
       o = al16(o + ((2 * ((size_t)a.ntiles + 1)) << sh));
     }
-    m.stage_b = (int32_t)o;
-    o = al16(o + 2 * (size_t)S);
-    m.stage_v = (int32_t)o;
-    o = al16(o + 2 * (size_t)S);
+    m.stage = (int32_t)o;
+    o = al16(o + (size_t)G * 4 * S);
     if (o <= limit) {
-      m.sub = S;
+      m.group = std::min(G, nreq);
       m.ncols = (int32_t)cols.size();
       m.ngrids = nreq;
       m.k = k;
@@ -512,6 +530,7 @@ bool run_multi_fused(const bin_request* reqs, int nreq, hipStream_t s, int* stat
       if (e != hipSuccess) *status = hip_fail(e, "launch fused multi-grid kernels");
       return true;
     }
+  }
   }
   return false;
 }

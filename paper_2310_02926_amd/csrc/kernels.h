@@ -185,10 +185,14 @@ struct PartBatch {
 // Every grid's requests share the table, n, the slices and the sub-chunk
 // size; per sub-chunk the union of the columns the grids read (f32) is
 // staged in LDS once and each grid then writes its records exactly as the
-// single-grid scatter does.  Sub-chunks are all of sub = 4 * threads
-// particles (the slice shape of unaligned requests).
+// single-grid scatter does.  Sub-chunks are all of kMultiSub particles (the
+// slice shape of unaligned requests with 512 threads of 4 particles).
 constexpr int kMultiGrids = 32;
 constexpr int kMultiCols = 40;
+constexpr int kMultiSub = 2048;      // particles per sub-chunk
+constexpr int kMultiThreads = 1024;  // threads per workgroup (2 particles each)
+constexpr int kMultiGroup = 4;       // grids ranked and staged together
+constexpr int kMultiPrefetch = 12;   // columns whose next sub-chunk is read ahead in registers
 struct MultiScatterArgs {
   const PartArgs* grids;            // device descriptors of the grids
   const float* cols[kMultiCols];    // union of the columns read
@@ -198,9 +202,10 @@ struct MultiScatterArgs {
   int32_t grid_ost[kMultiGrids];    // byte offset of grid g's staged run-table rows
   int32_t ngrids, ncols, k;
   int32_t cols_lds;                 // byte offset of the staged columns ([ncols][sub] floats)
-  int32_t stage_b, stage_v;         // byte offsets of the record stage: bins and source particles (u16 each)
-  int32_t sub;                      // particles per sub-chunk
-  int32_t vec;                      // every column 16-byte aligned: staged with 16-byte loads
+  int32_t stage;                    // byte offset of the record stages, one per grid of a group:
+                                    //   bins u16[kMultiSub], then source particles u16[kMultiSub]
+  int32_t group;                    // grids ranked and staged together (1..kMultiGroup)
+  int32_t vec;                      // every column 16-byte aligned: staged with wide loads
 };
 
 struct PartCfg {

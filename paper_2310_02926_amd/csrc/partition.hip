@@ -810,6 +810,7 @@ template <typename AT, int PREC, bool QUAD>
 __global__ __launch_bounds__(1024) void part_bin_batched(const PartArgs* __restrict__ d,
                                                          const uint32_t* __restrict__ map) {
   const uint32_t m = map[blockIdx.x];
+  if (m == 0xFFFFFFFFu) return;  // padding of the XCD-aware block order
   part_bin_body<AT, PREC, QUAD>(d[m >> 16], (int)(m & 0xFFFFu));
 }
 
@@ -947,42 +948,66 @@ hipError_t launch_partition_batch_after_scatter(const PartBatch& b, bool coord_f
 
 // ---------------------------------------------------------------------------
 // Fused scatter of several grids over one table (MultiScatterArgs).  One
-// workgroup per slice; per sub-chunk of S = 4 * NT particles: the union of
-// the columns is staged in LDS once, then each grid in turn ranks the
-// sub-chunk's inside particles within its tiles, one wave scans the tile
-// counts, and the records' bins and source particles are placed in LDS in
-// tile order; each output column (bins, then every attribute's values read
-// from the staged columns through that permutation) is written back over
-// the sub-chunk's own index range - the layout, run table and per-slice
-// counts the single-grid scatter writes (with sub-chunks of S particles).
-// The particle table is read from HBM once for all grids.
+// workgroup of kMultiThreads per slice; per sub-chunk of kMultiSub
+// particles the union of the columns is staged in LDS once (the first
+// kMultiPrefetch columns of the next sub-chunk are read into registers while
+// the grids of this one are processed).  The grids then go in groups of
+// up to kMultiGroup: every thread ranks its particles within each grid's
+// tiles, one wave per grid scans that grid's tile counts, the records' bins
+// and source particles are placed in LDS in tile order (a stage per grid of
+// the group), and each output column - the bins, then every attribute's
+// values read from the staged columns through that permutation - is written
+// back over the sub-chunk's own index range with 8- and 16-byte stores.  The
+// layout, run table and per-slice counts are the single-grid scatter's; the
+// particle table is read from HBM once for all grids.
 // ---------------------------------------------------------------------------
-template <int NT>
-__global__ __launch_bounds__(NT) void part_scatter_multi_kernel(const MultiScatterArgs* __restrict__ argp) {
+__global__ __launch_bounds__(kMultiThreads) void part_scatter_multi_kernel(const MultiScatterArgs* __restrict__ argp) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ uint32_t s_nsub;
-  constexpr int PPT = 4;
+  __shared__ uint32_t s_nsub[kMultiGroup];
+  constexpr int NT = kMultiThreads;
+  constexpr int S = kMultiSub;
+  constexpr int PPT = S / NT;
+  static_assert(S == 2 * NT, "each thread stages one pair of particles per column");
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
   const MultiScatterArgs& m = *argp;
-  const int S = m.sub;
   const int w = blockIdx.x;
   const PartArgs& a0 = m.grids[0];
   const int64_t lo = (int64_t)w * a0.chunk;
   const int64_t hi = lo + a0.chunk < a0.n ? lo + a0.chunk : a0.n;
   float* cols = reinterpret_cast<float*>(smem + m.cols_lds);
-  uint16_t* stg_b = reinterpret_cast<uint16_t*>(smem + m.stage_b);
-  uint16_t* perm = reinterpret_cast<uint16_t*>(smem + m.stage_v);
   for (int g = 0; g < m.ngrids; ++g) {
     const int T = m.grids[g].ntiles;
     uint32_t* c = reinterpret_cast<uint32_t*>(smem + m.grid_lds[g]);
     for (int t = threadIdx.x; t < 4 * T; t += NT) c[t] = 0u;  // cnt[2][T], off[T], tot[T]
   }
+  // The first npf columns of a sub-chunk, a pair of particles per thread.
+  const int npf = m.ncols < kMultiPrefetch ? m.ncols : kMultiPrefetch;
+  f32x2 pf[kMultiPrefetch];
+  auto fetch = [&](int64_t base) {
+    const int len = hi - base < S ? (int)(hi - base) : S;
+    const int p = 2 * threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < kMultiPrefetch; ++u)
+      if (u < npf) {
+        const float* src = m.cols[u] + base;
+        if (m.vec && p + 1 < len) {
+          pf[u] = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(src + p));
+        } else {
+          pf[u].x = p < len ? __builtin_nontemporal_load(src + p) : 0.0f;
+          pf[u].y = p + 1 < len ? __builtin_nontemporal_load(src + p + 1) : 0.0f;
+        }
+      }
+  };
+  if (lo < hi) fetch(lo);
   __syncthreads();
+  const int nblocks = (int)((hi - lo + S - 1) / S);
   int j = 0;
   for (int64_t base = lo; base < hi; base += S, ++j) {
     const int len = hi - base < S ? (int)(hi - base) : S;
-    // Stage the union of the columns (16-byte loads when every column is
-    // aligned; base is a multiple of 64).
-    for (int u = 0; u < m.ncols; ++u) {
+#pragma unroll
+    for (int u = 0; u < kMultiPrefetch; ++u)
+      if (u < npf) reinterpret_cast<f32x2*>(cols + (int64_t)u * S)[threadIdx.x] = pf[u];
+    for (int u = npf; u < m.ncols; ++u) {
       const float* src = m.cols[u] + base;
       float* dst = cols + (int64_t)u * S;
       if (m.vec && len == S) {
@@ -993,37 +1018,54 @@ __global__ __launch_bounds__(NT) void part_scatter_multi_kernel(const MultiScatt
       }
     }
     __syncthreads();
+    if (base + S < hi) fetch(base + S);  // in flight while the grids below run
     const int parity = j & 1;
-    for (int g = 0; g < m.ngrids; ++g) {
-      const PartArgs& a = m.grids[g];
-      const int T = a.ntiles;
-      uint32_t* cbase = reinterpret_cast<uint32_t*>(smem + m.grid_lds[g]);
-      uint32_t* cnt = cbase + parity * T;
-      uint32_t* cprev = cbase + (parity ^ 1) * T;
-      uint32_t* off = cbase + 2 * T;
-      uint32_t* tot = off + T;
-      uint16_t* ost = reinterpret_cast<uint16_t*>(smem + m.grid_ost[g]);
-      const int shift = a.lay.tile_shift;
-      const uint32_t lmask = (1u << shift) - 1u;
-      const float* xs = cols + (int64_t)m.gx[g] * S;
-      const float* ys = cols + (int64_t)m.gy[g] * S;
-      Axis ax = a.ax, ay = a.ay;
-      resolve_axes(a.dyn, ax, ay);
-      uint32_t tb[PPT], pos[PPT];
+    for (int g0 = 0; g0 < m.ngrids; g0 += m.group) {
+      const int G = m.ngrids - g0 < m.group ? m.ngrids - g0 : m.group;
+      // rank each particle within its tile, every grid of the group
+      uint32_t tb[kMultiGroup][PPT], pos[kMultiGroup][PPT];
 #pragma unroll
-      for (int q = 0; q < PPT; ++q) {
-        const int p = q * NT + threadIdx.x;
-        tb[q] = 0xFFFFFFFFu;
-        int ix, iy;
-        if (p < len && locate((double)xs[p], ax, ix) && locate((double)ys[p], ay, iy)) {
-          const uint32_t b = (uint32_t)(iy * a.nx + ix);
-          tb[q] = ((b >> shift) << 16) | (b & lmask);
+      for (int gi = 0; gi < kMultiGroup; ++gi) {
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+          tb[gi][q] = 0xFFFFFFFFu;
+          pos[gi][q] = 0u;
         }
-        pos[q] = tb[q] != 0xFFFFFFFFu ? atomicAdd(cnt + (tb[q] >> 16), 1u) : 0u;
+        if (gi < G) {
+          const int g = g0 + gi;
+          const PartArgs& a = m.grids[g];
+          uint32_t* cnt = reinterpret_cast<uint32_t*>(smem + m.grid_lds[g]) + parity * a.ntiles;
+          const int shift = a.lay.tile_shift;
+          const uint32_t lmask = (1u << shift) - 1u;
+          const float* xs = cols + (int64_t)m.gx[g] * S;
+          const float* ys = cols + (int64_t)m.gy[g] * S;
+          Axis ax = a.ax, ay = a.ay;
+          resolve_axes(a.dyn, ax, ay);
+#pragma unroll
+          for (int q = 0; q < PPT; ++q) {
+            const int p = q * NT + threadIdx.x;
+            int ix, iy;
+            if (p < len && locate((double)xs[p], ax, ix) && locate((double)ys[p], ay, iy)) {
+              const uint32_t b = (uint32_t)(iy * a.nx + ix);
+              tb[gi][q] = ((b >> shift) << 16) | (b & lmask);
+              pos[gi][q] = atomicAdd(cnt + (tb[gi][q] >> 16), 1u);
+            }
+          }
+        }
       }
       __syncthreads();
-      if (threadIdx.x < 64) {  // one wave: lane l owns tiles [l * mt, l * mt + mt)
-        const int lane = threadIdx.x;
+      // wave gi scans grid g0 + gi: lane l owns tiles [l * mt, l * mt + mt)
+      const int wave = threadIdx.x >> 6;
+      if (wave < G) {
+        const int g = g0 + wave;
+        const PartArgs& a = m.grids[g];
+        const int T = a.ntiles;
+        uint32_t* cbase = reinterpret_cast<uint32_t*>(smem + m.grid_lds[g]);
+        uint32_t* cnt = cbase + parity * T;
+        uint32_t* cprev = cbase + (parity ^ 1) * T;
+        uint32_t* off = cbase + 2 * T;
+        uint32_t* tot = off + T;
+        const int lane = threadIdx.x & 63;
         const int mt = (T + 63) >> 6;
         const int t0 = lane * mt;
         const uint32_t padm = a.quads ? 3u : 0u;
@@ -1047,60 +1089,105 @@ __global__ __launch_bounds__(NT) void part_scatter_multi_kernel(const MultiScatt
             o0 += cc;
           }
         }
-        if (lane == 63) s_nsub = x;
+        if (lane == 63) s_nsub[wave] = x;
       }
       __syncthreads();
-      const uint32_t nsub = s_nsub;
-      const int F = 1 << a.off_shift;
-      for (int t = threadIdx.x; t <= T; t += NT) {
-        ost[(t << a.off_shift) + (j & (F - 1))] = (uint16_t)(t < T ? off[t] : nsub);
-        if (a.quads && t < T) {  // pad the run to a whole quad (no particle: value 0)
-          const uint32_t cc = cnt[t];
-          const uint32_t e = off[t] + ((cc + 3u) & ~3u);
-          for (uint32_t p = off[t] + cc; p < e; ++p) {
-            stg_b[p] = 0xFFFFu;
-            perm[p] = 0xFFFFu;
+      // place the records in tile order: the local bin, and the particle
+      // (its index in the sub-chunk) each slot takes its values from
+#pragma unroll
+      for (int gi = 0; gi < kMultiGroup; ++gi) {
+        if (gi >= G) break;
+        const int g = g0 + gi;
+        const PartArgs& a = m.grids[g];
+        const int T = a.ntiles;
+        const uint32_t* cbase = reinterpret_cast<const uint32_t*>(smem + m.grid_lds[g]);
+        const uint32_t* cnt = cbase + parity * T;
+        const uint32_t* off = cbase + 2 * T;
+        uint16_t* ost = reinterpret_cast<uint16_t*>(smem + m.grid_ost[g]);
+        uint16_t* stg_b = reinterpret_cast<uint16_t*>(smem + m.stage + gi * 4 * S);
+        uint16_t* perm = stg_b + S;
+        const int F = 1 << a.off_shift;
+        for (int t = threadIdx.x; t <= T; t += NT) {
+          ost[(t << a.off_shift) + (j & (F - 1))] = (uint16_t)(t < T ? off[t] : s_nsub[gi]);
+          if (a.quads && t < T) {  // pad the run to a whole quad (no particle: value 0)
+            const uint32_t cc = cnt[t];
+            const uint32_t e = off[t] + ((cc + 3u) & ~3u);
+            for (uint32_t p = off[t] + cc; p < e; ++p) {
+              stg_b[p] = 0xFFFFu;
+              perm[p] = 0xFFFFu;
+            }
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < PPT; ++q)
+          if (tb[gi][q] != 0xFFFFFFFFu) {
+            const uint32_t p = pos[gi][q] + off[tb[gi][q] >> 16];
+            stg_b[p] = (uint16_t)(tb[gi][q] & 0xFFFFu);
+            perm[p] = (uint16_t)(q * NT + threadIdx.x);
+          }
+      }
+      __syncthreads();
+      // Write out the group's grids.  The next group's stages are filled
+      // only after two more barriers, so no barrier follows.
+      for (int gi = 0; gi < G; ++gi) {
+        const int g = g0 + gi;
+        const PartArgs& a = m.grids[g];
+        const int T = a.ntiles;
+        const uint16_t* ost = reinterpret_cast<const uint16_t*>(smem + m.grid_ost[g]);
+        const uint16_t* stg_b = reinterpret_cast<const uint16_t*>(smem + m.stage + gi * 4 * S);
+        const uint16_t* perm = stg_b + S;
+        // run-table rows [j0, j] of the slice once F are staged or at its end
+        const int F = 1 << a.off_shift;
+        if (((j + 1) & (F - 1)) == 0 || j + 1 == nblocks) {
+          const int j0 = j & ~(F - 1);
+          const int f = j - j0 + 1;
+          const int64_t nrows = (int64_t)a.nwg * a.nbpw;
+          const int64_t r0 = (int64_t)w * a.nbpw + j0;
+          for (int i2 = threadIdx.x; i2 < ((T + 1) << a.off_shift); i2 += NT) {
+            const int t = i2 >> a.off_shift, jj = i2 & (F - 1);
+            if (jj < f) a.blk_off[(int64_t)t * nrows + r0 + jj] = ost[i2];
+          }
+        }
+        // One contiguous stream per output column, four records per thread.
+        const uint32_t nsub = s_nsub[gi];
+        const uint32_t nq = (nsub + 3u) >> 2;
+        const int64_t rbase = base + ((int64_t)w * a.nbpw + j) * (int64_t)a.pad_row;
+        const uint32_t nwork = (uint32_t)(a.k + 1) * nq;
+        for (uint32_t i = threadIdx.x; i < nwork; i += NT) {
+          const uint32_t c = i / nq;
+          const uint32_t p = 4u * (i - c * nq);
+          const uint32_t rem = nsub - p;  // records of this quad: 1..4 (p + 3 < S)
+          const bool full = rem >= 4u;
+          const u32x2 pp = *reinterpret_cast<const u32x2*>((c ? perm : stg_b) + p);
+          if (c == 0) {
+            uint16_t* rb = a.rec_bin + rbase + p;
+            if (full && (reinterpret_cast<uintptr_t>(rb) & 7) == 0) {
+              __builtin_nontemporal_store(pp, reinterpret_cast<u32x2*>(rb));
+            } else {
+              for (uint32_t e = 0; e < rem && e < 4u; ++e) rb[e] = stg_b[p + e];
+            }
+          } else {
+            const float* vs = cols + (int64_t)m.attr_col[c - 1] * S;
+            float* rv = static_cast<float*>(a.rec_val[c - 1]) + rbase + p;
+            // slots past the sub-chunk's records hold stale entries: not read
+            const uint32_t s0 = pp.x & 0xFFFFu, s1 = pp.x >> 16, s2 = pp.y & 0xFFFFu, s3 = pp.y >> 16;
+            f32x4 v;
+            v.x = s0 < (uint32_t)S ? vs[s0] : 0.0f;
+            v.y = rem > 1u && s1 < (uint32_t)S ? vs[s1] : 0.0f;
+            v.z = rem > 2u && s2 < (uint32_t)S ? vs[s2] : 0.0f;
+            v.w = rem > 3u && s3 < (uint32_t)S ? vs[s3] : 0.0f;
+            if (full && (reinterpret_cast<uintptr_t>(rv) & 15) == 0) {
+              __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(rv));
+            } else {
+              const float ve[4] = {v.x, v.y, v.z, v.w};
+              for (uint32_t e = 0; e < rem && e < 4u; ++e) rv[e] = ve[e];
+            }
           }
         }
       }
-      // Records in tile order: the local bin, and the particle (its index in
-      // the sub-chunk) each slot takes its values from.
-#pragma unroll
-      for (int q = 0; q < PPT; ++q)
-        if (tb[q] != 0xFFFFFFFFu) {
-          pos[q] += off[tb[q] >> 16];
-          stg_b[pos[q]] = (uint16_t)(tb[q] & 0xFFFFu);
-          perm[pos[q]] = (uint16_t)(q * NT + threadIdx.x);
-        }
-      __syncthreads();
-      // run-table rows [j0, j] of the slice once F are staged or at its end
-      const int nblocks = (int)((hi - lo + S - 1) / S);
-      if (((j + 1) & (F - 1)) == 0 || j + 1 == nblocks) {
-        const int j0 = j & ~(F - 1);
-        const int f = j - j0 + 1;
-        const int64_t nrows = (int64_t)a.nwg * a.nbpw;
-        const int64_t r0 = (int64_t)w * a.nbpw + j0;
-        for (int i2 = threadIdx.x; i2 < ((T + 1) << a.off_shift); i2 += NT) {
-          const int t = i2 >> a.off_shift, jj = i2 & (F - 1);
-          if (jj < f) a.blk_off[(int64_t)t * nrows + r0 + jj] = ost[i2];
-        }
-      }
-      // One contiguous stream per output column: the bins, then each
-      // attribute's values gathered from the staged columns through perm.
-      const int64_t rbase = base + ((int64_t)w * a.nbpw + j) * (int64_t)a.pad_row;
-      for (uint32_t p = threadIdx.x; p < nsub; p += NT) __builtin_nontemporal_store(stg_b[p], a.rec_bin + rbase + p);
-      for (int jx = 0; jx < a.k; ++jx) {
-        const float* vs = cols + (int64_t)m.attr_col[jx] * S;
-        float* rv = static_cast<float*>(a.rec_val[jx]) + rbase;
-        for (uint32_t p = threadIdx.x; p < nsub; p += NT) {
-          const uint32_t src = perm[p];
-          __builtin_nontemporal_store(src == 0xFFFFu ? 0.0f : vs[src], rv + p);
-        }
-      }
-      __syncthreads();  // the bin stage and counters are reused by the next grid
     }
+    __syncthreads();  // the staged columns are refilled by the next sub-chunk
   }
-  __syncthreads();
   for (int g = 0; g < m.ngrids; ++g) {
     const PartArgs& a = m.grids[g];
     const int T = a.ntiles;
@@ -1112,7 +1199,7 @@ __global__ __launch_bounds__(NT) void part_scatter_multi_kernel(const MultiScatt
 hipError_t launch_scatter_multi(const MultiScatterArgs* args, int nwg, size_t lds, hipStream_t s, KTimer* tm) {
   if (nwg <= 0) return hipSuccess;
   if (tm) tm->begin(s);
-  hipLaunchKernelGGL(part_scatter_multi_kernel<512>, dim3(nwg), dim3(512), lds, s, args);
+  hipLaunchKernelGGL(part_scatter_multi_kernel, dim3(nwg), dim3(kMultiThreads), lds, s, args);
   if (tm) tm->end("part_scatter_multi_kernel", s);
   return hipGetLastError();
 }
@@ -1128,7 +1215,7 @@ hipError_t set_partition_lds_limit(size_t bytes) {
   BK_SET_NT(K, CT, AT, 1024) BK_SETF(K<CT, AT, 12, 1024>)
 #define BK_SET_TYPES(K) \
   BK_SET_CA(K, float, float) BK_SET_CA(K, float, double) BK_SET_CA(K, double, float) BK_SET_CA(K, double, double)
-  BK_SETF(part_scatter_multi_kernel<512>)
+  BK_SETF(part_scatter_multi_kernel)
   BK_SET_TYPES(part_scatter_kernel)
   BK_SET_TYPES(part_scatter_batched)
   BK_SETF(part_bin_kernel<float, PREC_F64, false>)

@@ -122,6 +122,11 @@ def _quad_cases():
     yield "f64 attrs k=2", _ws([x.astype(np.float32), y.astype(np.float32)],
                                [rng.standard_normal(n), rng.lognormal(0, 1, n)], 700, 900), 0
     yield "f64 coords count only", _ws([x, y], [], 2048, 1000, ops=1), 0
+    # more attributes than one load round trip holds (4 f32, 2 f64)
+    yield "f32 attrs k=9", _ws([x.astype(np.float32), y.astype(np.float32)],
+                               [rng.standard_normal(n).astype(np.float32) for _ in range(9)], 300, 200), 0
+    yield "f64 attrs k=5", _ws([x.astype(np.float32), y.astype(np.float32)],
+                               [rng.lognormal(0, 1, n) for _ in range(5)], 300, 200), 0
     e = synth.edge_points(0.0, 1.0, 1024, np.float32)
     yield "edges", _ws([rng.choice(e, n), rng.choice(e, n)], [rng.standard_normal(n).astype(np.float32)],
                        1024, 1024), 0
@@ -135,8 +140,8 @@ def _quad_cases():
 def test_partition_record_and_quad_gathers(quads):
     """Both gathers of the tile binning - record by record, and whole quads
     of 4 records (each tile's run padded with empty records) - on the cases
-    the planner would send to either: one or several attributes, f64
-    attributes and coordinates, count only, bin edges, sparse tiles with
+    the planner would send to either: one or several attributes (more than
+    one load round trip holds), f64 attributes and coordinates, count only, bin edges, sparse tiles with
     runs of a few records, a ragged size and unaligned columns."""
     from paper_2310_02926_amd import binding as B
     for name, ws, shift in _quad_cases():

@@ -2,8 +2,9 @@
 (same generators and seeds) and in its launch configuration (automatic plan,
 a side stream, all five operations): hotspot 2^27 particles on 2048^2,
 Gaussian mixture 2^24 with four attributes on 1024^2, 64 halos 2^26 on a
-128^3 mesh, and the batch of 256 requests (2.7e8 particles) after the
-autotuner, as one batched call and as a graph.  The oracle bins the whole
+128^3 mesh, the batch of 256 requests (2.7e8 particles) after the
+autotuner, as one batched call and as a graph, and nine 256^2 planes over one
+2^24-particle table of ten variables in one multi-grid call.  The oracle bins the whole
 set in seconds, so every bin is compared (for the batch: every bin of a
 seeded sample of 40 requests, the largest and smallest among them): count/min/max bit-exact, sum/avg within 1e-5 * sum|a| (the plain
 FP32 mode within its sequential error bound).  The largest relative sum error
@@ -192,3 +193,41 @@ def test_full_size_batch(mode):
         ws = w.wss[i]
         G.assert_parity(_to_np(w.reqs[i]["out"]), w.refs[i], ws.ops,
                         what=f"{mode} request {i} (n={ws.n}, {ws.nx}^2, k={ws.k})")
+
+
+def test_full_size_multi():
+    """The benchmark's multi-grid workload: nine planes of 256^2 bins over one
+    2^24-particle table of ten f32 variables, every variable reduced on every
+    plane, in one bin_particles_multi call (one fused pass over the table),
+    called twice on the same outputs; every bin of every grid against the
+    oracle."""
+    from paper_2310_02926_amd import binding as B
+    _case("full size multi-grid: n=2^24, 9 planes of 256^2, 10 variables")
+    n, side = 1 << 24, 256
+    tab = synth.insitu_table(n, seed=0)
+    dev = torch.device("cuda:0")
+    cols = [torch.from_numpy(c).to(dev) for c in tab.columns]
+    grids = []
+    for (a, b), bd in zip(tab.planes, tab.bounds):
+        grids.append(dict(axes=(a, b), bounds=bd, nx=side, ny=side, ops=31,
+                          out=B.alloc_outputs(cols, side, side, 31, dev)))
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    B.bin_timing_enable(True)
+    for _ in range(2):
+        B.bin_particles_multi(cols, cols, n, grids, stream=stream)
+    stream.synchronize()
+    B.bin_timing_enable(False)
+    rep = B.bin_timing_report()
+    assert rep.get("part_scatter_multi_kernel", (0, 0))[0] == 2, rep
+    assert "part_scatter_kernel" not in rep, rep
+
+    def ref(g):
+        ws = synth.Workload(tab.columns, tab.columns, axes=g["axes"], bounds=g["bounds"], nx=side, ny=side, ops=31)
+        return G.oracle(ws)
+    with ThreadPoolExecutor(3) as ex:
+        refs = list(ex.map(ref, grids))
+    for gi, (g, r) in enumerate(zip(grids, refs)):
+        got = _to_np(g["out"])
+        assert int(got["count"].sum()) == int(r["count"].sum()), gi
+        G.assert_parity(got, r, 31, what=f"multi grid {gi}")
