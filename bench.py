@@ -50,12 +50,12 @@ def log(msg):
 
 def kernel_source_hash() -> str:
     """Hash of the sources that decide what a single call launches: the
-    device code and the planner (host-side batching, serving and API files
-    are left out)."""
+    device code, its headers and the planner (host-side batching, serving,
+    tuning and API files, and their shared host header, are left out)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2310_02926_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")) or f == "plan.cpp":
+        if (f.endswith((".hip", ".h")) and f != "internal.h") or f == "plan.cpp":
             h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -287,17 +287,24 @@ int bin_graph_destroy(bin_graph* graph);
  * reqs[0..count) and remember the fastest per (device, shape class).  The
  * candidates include the strategy itself where both apply (whole grid in
  * LDS, tile partition), the tile size, the scatter shape and the gather
- * form.  The table is kept in memory
- * and, if the environment variable BIN_TUNE_CACHE names a file, read from
- * and written back to it as JSON:
+ * form.  With two or more requests it then times the whole set as one batch
+ * under each batch policy - every request's tuned plan, the planner's rules,
+ * or the rules with one shared scatter shape - and keeps the fastest for the
+ * device: batched calls, graphs and the server plan under it (plans tuned
+ * one request at a time can split a batch into more, smaller launch groups).
+ * The tables are kept in memory and, if the environment variable
+ * BIN_TUNE_CACHE names a file, read from and written back to it as JSON:
  *   {"version": 1, "entries": {"gfx950:256|n20_b16_k1_c0_a0_o31":
  *     {"strategy": 2, "block": 0, "grid": 0, "part_wg": 512,
  *      "scatter_ppt": 16, "scatter_threads": 1024, "tile_shift": 13,
- *      "split_len": 0, "quads": 2}, ...}}
- * (key: device architecture and compute units, then log2 of n and of the
- * bin count, attributes, coordinate and attribute dtypes, ops).  Runs
- * kernels on a private stream and synchronises it; it overwrites the
- * requests' output buffers.  Without tuning data the built-in rules apply. */
+ *      "split_len": 0, "quads": 2}, ...},
+ *    "batch": {"gfx950:256": {"strategy": 0, ...}}}
+ * (entry key: device architecture and compute units, then log2 of n and of
+ * the bin count, attributes, coordinate and attribute dtypes, ops; batch
+ * "strategy": 0 rules, 1 tuned plans, 2 rules with the entry's
+ * scatter_threads and scatter_ppt).  Runs kernels on a private stream and
+ * synchronises it; it overwrites the requests' output buffers.  Without
+ * tuning data the built-in rules apply. */
 int bin_autotune(const bin_request* reqs, int32_t count);
 
 /* ---- diagnostics -------------------------------------------------------- */

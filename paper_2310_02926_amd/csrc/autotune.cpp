@@ -6,11 +6,19 @@
 //
 // Shape class: log2 buckets of n and of the bin count, attribute count,
 // coordinate and attribute types and the op mask (precision flags included).
-// The table lives in memory and, when the environment variable
-// BIN_TUNE_CACHE names a file, is loaded from and saved to that file as JSON:
+// A batch (bin_particles_batched, graphs, the server) plans its requests
+// under a policy that the autotuner also chooses, by timing the whole set
+// of requests it was given as one batch: each request's tuned plan, the
+// planner's rules, or the rules with one shared scatter shape.
+//
+// The tables live in memory and, when the environment variable
+// BIN_TUNE_CACHE names a file, are loaded from and saved to that file as
+// JSON:
 //   {"version": 1, "entries": {"<device>|<class>": {"strategy": s, "block": b,
 //    "grid": g, "part_wg": w, "scatter_ppt": p, "scatter_threads": t,
-//    "tile_shift": h, "split_len": l, "quads": q}, ...}}
+//    "tile_shift": h, "split_len": l, "quads": q}, ...},
+//    "batch": {"<device>": {"strategy": policy, "scatter_ppt": p,
+//    "scatter_threads": t, ...}}}
 // where <device> is the device's architecture name and compute-unit count,
 // so one file can hold the tunings of several kinds of GPU.
 #include <algorithm>
@@ -34,7 +42,11 @@ namespace {
 
 std::mutex g_tune_mu;
 std::map<std::string, PlanHints> g_tune;
+// batch policy per device: force_strategy holds BatchPolicy::mode,
+// scatter_threads and scatter_ppt its shared scatter shape
+std::map<std::string, PlanHints> g_batch;
 bool g_tune_loaded = false;
+thread_local int t_lookup_off = 0;
 
 int log2_bucket(int64_t v) {
   int b = 0;
@@ -44,6 +56,8 @@ int log2_bucket(int64_t v) {
   }
   return b;
 }
+
+std::string device_key(const DeviceInfo& dev) { return dev.arch[0] ? dev.arch : "unknown"; }
 
 std::string class_key(const bin_request& r, const DeviceInfo& dev) {
   const int k = r.attrs.cols ? r.attrs.ncols : 0;
@@ -120,22 +134,26 @@ struct JsonIn {
     } while (eat(','));
     return eat('}');
   }
-  bool file(std::map<std::string, PlanHints>& out) {
+  bool table(std::map<std::string, PlanHints>& out) {
+    if (!eat('{')) return false;
+    if (eat('}')) return true;
+    do {
+      std::string key;
+      PlanHints h;
+      if (!str(key) || !eat(':') || !entry(h)) return false;
+      out[key] = h;
+    } while (eat(','));
+    return eat('}');
+  }
+  bool file(std::map<std::string, PlanHints>& out, std::map<std::string, PlanHints>& batch) {
     if (!eat('{')) return false;
     do {
       std::string name;
       if (!str(name) || !eat(':')) return false;
       if (name == "entries") {
-        if (!eat('{')) return false;
-        if (!eat('}')) {
-          do {
-            std::string key;
-            PlanHints h;
-            if (!str(key) || !eat(':') || !entry(h)) return false;
-            out[key] = h;
-          } while (eat(','));
-          if (!eat('}')) return false;
-        }
+        if (!table(out)) return false;
+      } else if (name == "batch") {
+        if (!table(batch)) return false;
       } else {
         long long v;
         if (!num(v)) return false;
@@ -155,19 +173,18 @@ void load_locked() {
   std::stringstream ss;
   ss << f.rdbuf();
   const std::string text = ss.str();
-  std::map<std::string, PlanHints> m;
+  std::map<std::string, PlanHints> m, b;
   JsonIn in{text};
-  if (in.file(m))
+  if (in.file(m, b)) {
     for (auto& kv : m) g_tune[kv.first] = kv.second;
+    for (auto& kv : b) g_batch[kv.first] = kv.second;
+  }
 }
 
-void save_locked() {
-  const char* p = cache_path();
-  if (!p) return;
-  std::ofstream f(p, std::ios::trunc);
-  f << "{\"version\": 1, \"entries\": {";
+void write_table(std::ofstream& f, const std::map<std::string, PlanHints>& t) {
+  f << '{';
   bool first = true;
-  for (auto& kv : g_tune) {
+  for (auto& kv : t) {
     f << (first ? "\n  " : ",\n  ") << '"' << kv.first << "\": {";
     first = false;
     const PlanHints& h = kv.second;
@@ -177,7 +194,18 @@ void save_locked() {
     }
     f << '}';
   }
-  f << "\n}}\n";
+  f << "\n}";
+}
+
+void save_locked() {
+  const char* p = cache_path();
+  if (!p) return;
+  std::ofstream f(p, std::ios::trunc);
+  f << "{\"version\": 1, \"entries\": ";
+  write_table(f, g_tune);
+  f << ", \"batch\": ";
+  write_table(f, g_batch);
+  f << "}\n";
 }
 
 bool is_default(const PlanHints& h) {
@@ -187,10 +215,28 @@ bool is_default(const PlanHints& h) {
 
 }  // namespace
 
+bool hints_are_default(const PlanHints& h) { return is_default(h); }
+
+TunedLookupOff::TunedLookupOff() { ++t_lookup_off; }
+TunedLookupOff::~TunedLookupOff() { --t_lookup_off; }
+
+BatchPolicy batch_policy(const DeviceInfo& dev) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  load_locked();
+  BatchPolicy p;
+  auto it = g_batch.find(device_key(dev));
+  if (it != g_batch.end()) {
+    p.mode = it->second.force_strategy;
+    p.nt = it->second.scatter_threads;
+    p.ppt = it->second.scatter_ppt;
+  }
+  return p;
+}
+
 // Hints for a request: the caller's explicit override if any, else the
 // tuned entry of its shape class, else defaults.
 PlanHints effective_hints(const bin_request& r, const DeviceInfo& dev, const PlanHints& explicit_hints) {
-  if (!is_default(explicit_hints)) return explicit_hints;
+  if (!is_default(explicit_hints) || t_lookup_off) return explicit_hints;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   load_locked();
   if (g_tune.empty()) return explicit_hints;
@@ -304,6 +350,56 @@ int autotune(const bin_request* reqs, int count) {
       load_locked();
       g_tune[class_key(r, dev)] = best_h;
     }
+  }
+  // The batch policy: the whole set as one batch (bin_particles_batched,
+  // graphs and the server plan this way) under each policy; per-request
+  // plans tuned alone can split a batch into more, smaller launch groups.
+  if (st == BIN_OK && count >= 2) {
+    std::vector<PlanHints> pols;
+    for (int mode : {1, 0}) {
+      PlanHints h;
+      h.force_strategy = mode;
+      pols.push_back(h);
+    }
+    for (auto shape : {std::make_pair(1024, 8), std::make_pair(1024, 4), std::make_pair(512, 8)}) {
+      PlanHints h;
+      h.force_strategy = 2;
+      h.scatter_threads = shape.first;
+      h.scatter_ppt = shape.second;
+      pols.push_back(h);
+    }
+    const std::string dk = device_key(dev);
+    float best = 1e30f;
+    PlanHints best_p = pols[0];
+    for (const PlanHints& pol : pols) {
+      {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_batch[dk] = pol;
+      }
+      float t[3];
+      int bst = run_batch(reqs, count, s, PlanHints{});  // warm-up
+      for (int i = 0; i < 3 && bst == BIN_OK; ++i) {
+        hipError_t e = hipEventRecord(e0, s);
+        if (e == hipSuccess) bst = run_batch(reqs, count, s, PlanHints{});
+        if (bst) break;
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t[i], e0, e1);
+        if (e != hipSuccess) bst = hip_fail(e, "autotune batch timing");
+      }
+      if (bst == BIN_ERR_UNSUPPORTED) continue;
+      if (bst) {
+        st = bst;
+        break;
+      }
+      std::sort(t, t + 3);
+      if (t[1] < best) {
+        best = t[1];
+        best_p = pol;
+      }
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_batch[dk] = best_p;
   }
   (void)hipStreamSynchronize(s);
   (void)hipEventDestroy(e0);

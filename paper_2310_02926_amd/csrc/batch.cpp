@@ -15,6 +15,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <optional>
 #include <tuple>
 #include <unordered_map>
 #include <vector>
@@ -80,9 +81,26 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
   // shape; requests of different shapes go to different groups rather than
   // all taking the smallest shape).
   std::map<std::tuple<int, int, int, int, int, int, int>, int> gmap;
+  // Without an explicit override the batch policy chosen by bin_autotune
+  // applies: each request's tuned plan, the planner's rules, or the rules
+  // with one shared scatter shape.
+  PlanHints bh = hints;
+  std::optional<TunedLookupOff> rules_only;
+  if (hints_are_default(hints)) {
+    const BatchPolicy pol = batch_policy(dev);
+    if (pol.mode != 1) rules_only.emplace();
+    if (pol.mode == 2) {
+      bh.scatter_threads = pol.nt;
+      bh.scatter_ppt = pol.ppt;
+    }
+  }
   for (int i = 0; i < nreq; ++i) {
     Prepared& p = bp->preps[i];
-    int st = prepare(reqs[i], dev, hints, nullptr, &p);
+    int st = prepare(reqs[i], dev, bh, nullptr, &p);
+    if (st == BIN_ERR_UNSUPPORTED && !hints_are_default(bh) && hints_are_default(hints)) {
+      clear_error();
+      st = prepare(reqs[i], dev, hints, nullptr, &p);  // the shared shape does not fit this request
+    }
     if (st) return st;
     const int strat = p.cfg.strategy;
     if (strat == bk::STRAT_GLOBAL) {

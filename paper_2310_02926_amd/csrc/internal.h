@@ -91,6 +91,21 @@ int resolve_precision(uint32_t ops, bool attr_f64);
 // The caller's explicit hints, else the autotuned entry for the request's
 // shape class, else defaults.
 PlanHints effective_hints(const bin_request& r, const DeviceInfo& dev, const PlanHints& explicit_hints);
+bool hints_are_default(const PlanHints& h);
+// How a batch plans its requests, chosen by bin_autotune by timing the
+// whole set: 0 the planner's rules, 1 each request's tuned plan (also the
+// choice without tuning data), 2 the planner's rules with one scatter shape
+// (nt threads of ppt particles) for every tile-partition request.
+struct BatchPolicy {
+  int mode = 1;
+  int nt = 0, ppt = 0;
+};
+BatchPolicy batch_policy(const DeviceInfo& dev);
+// While alive, effective_hints on this thread ignores the tuning table.
+struct TunedLookupOff {
+  TunedLookupOff();
+  ~TunedLookupOff();
+};
 int autotune(const bin_request* reqs, int count);
 
 // Plan a validated request and lay out its scratch at 'scratch' (may be null

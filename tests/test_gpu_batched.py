@@ -185,10 +185,19 @@ def test_autotune_then_bin(tmp_path, monkeypatch):
     """The autotuner picks a configuration per shape class; results stay
     exact/within tolerance with the tuned configuration."""
     from paper_2310_02926_amd import binding as B
+    import json
     _case("autotune")
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("BIN_TUNE_CACHE", str(cache))
     specs, wss = _mix(3, 11, n_hi=200_000, sides=(48, 600))
     reqs = _requests(wss)
     B.bin_autotune(reqs)
+    # the batch policy was timed on the whole set and filed under this device
+    pols = json.loads(cache.read_text())["batch"]
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert list(pols) == [f"{arch}:{cus}"], pols
+    assert next(iter(pols.values()))["strategy"] in (0, 1, 2), pols
     B.bin_particles_batched(reqs)
     torch.cuda.synchronize()
     _check_vs_oracle(reqs, wss, "after autotune")
@@ -257,6 +266,59 @@ print(json.dumps({"before": before, "after": B.bin_describe_plan(req),
                   "arch": torch.cuda.get_device_properties(0).gcnArchName.split(":")[0],
                   "cus": torch.cuda.get_device_properties(0).multi_processor_count}))
 '''
+
+
+_POLICY_CHILD = r'''
+import json, sys
+import numpy as np
+import torch
+sys.path.insert(0, sys.argv[1])
+from paper_2310_02926_amd import binding as B
+from paper_2310_02926_amd import synth
+from tests import gpu_check as G
+specs = synth.batch_specs(12, seed=5, n_hi=300_000)
+wss = [synth.instance(sp) for sp in specs]
+reqs = []
+for ws in wss:
+    c, a = G.to_device(ws)
+    reqs.append(dict(coords=c, attrs=a, n=ws.n, axes=ws.axes, bounds=ws.bounds, nx=ws.nx, ny=ws.ny, ops=ws.ops,
+                     out=B.alloc_outputs(a, ws.nx, ws.ny, ws.ops, "cuda")))
+B.bin_particles_batched(reqs)
+torch.cuda.synchronize()
+for r, ws in zip(reqs, wss):
+    got = {"count": r["out"]["count"].cpu().numpy().view(np.uint32).astype(np.int64)} if "count" in r["out"] else {}
+    for key in ("sum", "min", "max", "avg"):
+        if key in r["out"]:
+            got[key] = [t.cpu().numpy() for t in r["out"][key]]
+    G.assert_parity(got, G.oracle(ws), ws.ops, what=f"policy {sys.argv[2]}")
+print("ok")
+'''
+
+
+@pytest.mark.parametrize("policy", [(0, 0, 0), (2, 1024, 4), (2, 512, 8), (2, 1024, 16)],
+                         ids=["rules", "shape1024x4", "shape512x8", "shape1024x16"])
+def test_batch_policy_from_the_tuning_cache(tmp_path, policy):
+    """Every batch policy the autotuner can file - the planner's rules, or
+    one shared scatter shape (a shape a request cannot take falls back to
+    its own) - gives the oracle's results; the policy is read from the
+    BIN_TUNE_CACHE file in a fresh process."""
+    import json
+    import os
+    import subprocess
+    import sys as _sys
+    _case(f"batch policy {policy}")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    mode, nt, ppt = policy
+    cache = tmp_path / "tune.json"
+    cache.write_text(json.dumps({"version": 1, "entries": {}, "batch": {
+        f"{arch}:{cus}": {"strategy": mode, "scatter_threads": nt, "scatter_ppt": ppt}}}))
+    script = tmp_path / "child.py"
+    script.write_text(_POLICY_CHILD)
+    p = subprocess.run([_sys.executable, str(script), root, str(policy)], capture_output=True, text=True,
+                       env=dict(os.environ, BIN_TUNE_CACHE=str(cache)), timeout=300, cwd=root)
+    assert p.returncode == 0 and p.stdout.strip().endswith("ok"), p.stderr[-3000:]
 
 
 def test_autotune_cache_is_json_keyed_by_device(tmp_path):
