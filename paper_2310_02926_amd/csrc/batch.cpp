@@ -3,9 +3,11 @@
 // capture of a batch, and the fused multi-grid path (several grids over
 // one table).
 //
-// Requests are planned one by one, then grouped by (strategy, coordinate
-// type, attribute type, precision) and, for tile partitions, by the scatter
-// shape and gather form their own plans chose.  Every request keeps its own
+// Requests are planned one by one - under the batch policy bin_autotune
+// chose: each request's tuned plan, the planner's rules, or the rules with
+// one shared scatter shape - then grouped by (strategy, coordinate type,
+// attribute type, precision) and, for tile partitions, by the scatter shape
+// and gather form their plans chose.  Every request keeps its own
 // scratch (records, run table, counts, items, partial slots); the groups
 // share device tables of descriptors and block maps, uploaded once, and
 // each group runs one table-driven launch per stage for all its requests.

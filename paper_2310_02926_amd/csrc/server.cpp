@@ -10,7 +10,7 @@
 // while every slot is busy are batched together when the next slot frees.
 // Each slot has a waiter thread that blocks on the slot's completion event
 // and stamps its requests done the moment the batch finishes.  Result grids
-// come from a reuse pool keyed by size and stay resident until
+// come from a reuse pool keyed by size class and stay resident until
 // binsrv_release(); device memory is allocated and freed outside the lock.
 #include <algorithm>
 #include <atomic>
@@ -93,7 +93,12 @@ size_t grid_bytes_of(const binsrv_request& r) {
   if (r.ops & BIN_MIN) b += k * al256(mm * nb);
   if (r.ops & BIN_MAX) b += k * al256(mm * nb);
   if (r.ops & BIN_AVG) b += k * al256(sa * nb);
-  return std::max<size_t>(b, 256);
+  // Blocks come in size classes (2^j and 3 * 2^(j-1) bytes, at least
+  // 64 KiB), so that released blocks serve later requests of other grid
+  // shapes and the pool rarely has to allocate: at most a third is unused.
+  size_t c = size_t(1) << 16;
+  while (c < b) c = (c & (c - 1)) ? (c / 3) * 4 : c + c / 2;  // 2^j -> 1.5 * 2^j -> 2^(j+1)
+  return c;
 }
 
 }  // namespace
