@@ -221,7 +221,9 @@ int bin_validate_nd(const bin_columns* coords, const bin_columns* attrs, int64_t
  * what bin_particles gives for the same request, within the sum tolerance;
  * counts, min and max are identical.  Requests must not share output
  * buffers.  The request array is read during the call only.  Enqueues and
- * returns. */
+ * returns; the descriptor tables go up through a ring of 4 pinned buffers
+ * per stream, so the host waits only when 4 earlier batched calls on the
+ * same stream have not yet reached the device. */
 int bin_particles_batched(const bin_request* reqs, int32_t nreq, void* stream);
 
 /* ---- asynchronous in situ binning ------------------------------------------ */
