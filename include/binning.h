@@ -281,6 +281,14 @@ int bin_particles_multi(const bin_columns* coords, const bin_columns* attrs, int
  * launches.  Creating a graph synchronises the device once. */
 typedef struct bin_graph bin_graph;
 int bin_graph_create(const bin_request* reqs, int32_t nreq, bin_graph** graph);
+/* The same for what bin_particles_multi(coords, attrs, n, grids, ngrids)
+ * enqueues (the fused pass over the table when the specs qualify, else
+ * their batch): the per-step in situ load of the paper's experiments
+ * (Section 4.3), replayed every step.  The columns and outputs named here are
+ * borrowed by every launch; refill them between launches.  Arguments are
+ * checked as by bin_particles_multi, before any HIP call. */
+int bin_graph_create_multi(const bin_columns* coords, const bin_columns* attrs, int64_t n,
+                           const bin_grid_spec* grids, int32_t ngrids, bin_graph** graph);
 int bin_graph_launch(bin_graph* graph, void* stream);
 int bin_graph_destroy(bin_graph* graph);
 

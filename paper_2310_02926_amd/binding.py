@@ -29,7 +29,7 @@ MAX_ATTRS = 16
 
 #: Every function declared in include/binning.h.
 EXPORTS = (
-    "bin_particles", "bin_particles_noalloc", "bin_validate", "bin_particles_nd", "bin_validate_nd", "bin_particles_async", "bin_particles_batched", "bin_particles_multi", "bin_graph_create", "bin_graph_launch",
+    "bin_particles", "bin_particles_noalloc", "bin_validate", "bin_particles_nd", "bin_validate_nd", "bin_particles_async", "bin_particles_batched", "bin_particles_multi", "bin_graph_create", "bin_graph_create_multi", "bin_graph_launch",
     "bin_graph_destroy", "bin_autotune", "bin_status_string", "bin_last_error_message",
     "bin_stream_status", "bin_release_workspace", "bin_version", "bin_timing_enable", "bin_timing_read",
     "bin_timing_report",
@@ -118,6 +118,8 @@ def lib() -> ctypes.CDLL:
         "bin_particles_multi": (c_int, [POINTER(Columns), POINTER(Columns), c_int64, POINTER(GridSpec), c_int32,
                                         c_void_p]),
         "bin_graph_create": (c_int, [POINTER(Request), c_int32, POINTER(c_void_p)]),
+        "bin_graph_create_multi": (c_int, [POINTER(Columns), POINTER(Columns), c_int64, POINTER(GridSpec), c_int32,
+                                           POINTER(c_void_p)]),
         "bin_graph_launch": (c_int, [c_void_p, c_void_p]),
         "bin_graph_destroy": (c_int, [c_void_p]),
         "bin_autotune": (c_int, [POINTER(Request), c_int32]),
@@ -428,13 +430,28 @@ class Batch:
 
 
 class BinGraph:
-    """A captured batch: create once, launch many times, destroy."""
+    """A captured batch (or, with multi(), a captured multi-grid call):
+    create once, launch many times, destroy."""
 
     def __init__(self, reqs: Sequence[Dict]):
         arr, self._keep = request_array(reqs)
         h = c_void_p()
         check(lib().bin_graph_create(arr, len(reqs), ctypes.byref(h)))
         self._h = h
+
+    @classmethod
+    def multi(cls, coords, attrs, n: int, grids: Sequence[Dict], coord_dtype=None, attr_dtype=None) -> "BinGraph":
+        """bin_graph_create_multi: what bin_particles_multi enqueues, captured."""
+        g = cls.__new__(cls)
+        c, ck = columns(coords, coord_dtype)
+        a, ak = columns(attrs, attr_dtype) if attrs else (None, None)
+        arr, keep = grid_specs(grids)
+        h = c_void_p()
+        check(lib().bin_graph_create_multi(ctypes.byref(c), ctypes.byref(a) if a is not None else None, n, arr,
+                                           len(grids), ctypes.byref(h)))
+        g._h = h
+        g._keep = (c, ck, a, ak, arr, keep)
+        return g
 
     def launch(self, stream=None) -> None:
         check(lib().bin_graph_launch(self._h, _stream_handle(stream)))

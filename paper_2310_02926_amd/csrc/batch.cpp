@@ -14,6 +14,7 @@
 // Requests that need the global-atomic strategy run one by one.
 #include <algorithm>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -420,17 +421,37 @@ int upload_tables(const BatchPlan& bp, unsigned char* scratch, hipStream_t s) {
   return BIN_OK;
 }
 
-}  // namespace
-
 // Several grids over one table in one pass over the table: every grid is a
 // tile-partition request with the same slices and sub-chunks of 2048
 // particles (512 threads x 4); one fused scatter stages the union of the
 // columns per sub-chunk in LDS and writes every grid's records, then the
-// rest of the batch's stages run as usual.  Returns false (nothing done)
-// when the requests do not qualify: f32 columns, 2..kMultiGrids grids, all
-// on the partition strategy, at most kMultiCols distinct columns, and the
-// LDS stage fits.
-bool run_multi_fused(const bin_request* reqs, int nreq, hipStream_t s, int* status) {
+// rest of the batch's stages run as usual.  The requests qualify with f32
+// columns, 2..kMultiGrids grids, all on the partition strategy, at most
+// kMultiCols distinct columns, and an LDS stage that fits.
+
+// The fused path's plan: tile partition, 512 threads of 4 particles per
+// scatter sub-chunk, record-by-record gather (one launch serves every grid).
+PlanHints multi_hints() {
+  PlanHints h;
+  h.force_strategy = bk::STRAT_PART;
+  h.scatter_threads = 512;
+  h.scatter_ppt = 4;
+  h.quads = 1;
+  return h;
+}
+
+struct MultiPlan {
+  BatchPlan bp;
+  bk::MultiScatterArgs m;
+  size_t lds = 0;    // dynamic LDS of the fused scatter
+  size_t extra = 0;  // bytes of its arguments, after the batch's tables
+  std::vector<int> shifts;  // staged run-table rows per grid (log2)
+  size_t scratch_bytes() const { return bp.scratch_bytes + extra; }
+};
+
+// Sizing pass.  Returns false when the requests do not qualify (*status
+// BIN_OK) or on an error (*status set).
+bool multi_plan(const bin_request* reqs, int nreq, const DeviceInfo& dev, MultiPlan* mp, int* status) {
   *status = BIN_OK;
   if (nreq < 2 || nreq > bk::kMultiGrids) return false;
   const bin_request& r0 = reqs[0];
@@ -444,7 +465,7 @@ bool run_multi_fused(const bin_request* reqs, int nreq, hipStream_t s, int* stat
     cols.push_back(p);
     return (int)cols.size() - 1;
   };
-  bk::MultiScatterArgs m;
+  bk::MultiScatterArgs& m = mp->m;
   std::memset(&m, 0, sizeof m);
   for (int g = 0; g < nreq; ++g) {
     const bin_request& r = reqs[g];
@@ -454,22 +475,13 @@ bool run_multi_fused(const bin_request* reqs, int nreq, hipStream_t s, int* stat
   }
   for (int j = 0; j < k; ++j) m.attr_col[j] = col_index(r0.attrs.cols[j]);
   if ((int)cols.size() > bk::kMultiCols) return false;
-  DeviceInfo dev;
-  int st = device_info(&dev);
-  if (st) {
-    *status = st;
-    return true;
-  }
-  PlanHints h;
-  h.force_strategy = bk::STRAT_PART;
-  h.scatter_threads = 512;
-  h.scatter_ppt = 4;
-  h.quads = 1;  // record-by-record gather: one launch serves every grid
-  BatchPlan bp;
-  st = plan_batch(reqs, nreq, dev, h, nullptr, &bp);
+  BatchPlan& bp = mp->bp;
+  const int st = plan_batch(reqs, nreq, dev, multi_hints(), nullptr, &bp);
   if (st || bp.part.size() != 1 || !bp.lds.empty() || !bp.global_reqs.empty() ||
-      (int)bp.part[0].idx.size() != nreq || bp.part[0].nt != 512 || bp.part[0].ppt != 4 || bp.part[0].quads)
+      (int)bp.part[0].idx.size() != nreq || bp.part[0].nt != 512 || bp.part[0].ppt != 4 || bp.part[0].quads) {
+    clear_error();
     return false;  // (the record stages hold kMultiSub records: no quad padding)
+  }
   // LDS: staged columns, per grid its counters and staged run-table rows,
   // the record stages of a group of grids; the largest group, then the most
   // staged rows (a power of two <= 16), that fit.
@@ -478,22 +490,23 @@ bool run_multi_fused(const bin_request* reqs, int nreq, hipStream_t s, int* stat
   const PartGroup& g0 = bp.part[0];
   const size_t limit = dev.lds_per_block - 256;
   for (int G = bk::kMultiGroup; G >= 1; --G) {
-  for (int F = 16; F >= 1; F /= 2) {
-    size_t o = al16((size_t)cols.size() * S * 4);
-    m.cols_lds = 0;
-    for (int g = 0; g < nreq; ++g) {
-      const bk::PartArgs& a = g0.args[g];
-      m.grid_lds[g] = (int32_t)o;
-      o = al16(o + 16 * (size_t)a.ntiles);
-      m.grid_ost[g] = (int32_t)o;
-      const int f = std::min(F, std::max(1, (int)a.nbpw));
-      int sh = 0;
-      while ((1 << (sh + 1)) <= f) ++sh;
-      o = al16(o + ((2 * ((size_t)a.ntiles + 1)) << sh));
-    }
-    m.stage = (int32_t)o;
-    o = al16(o + (size_t)G * 4 * S);
-    if (o <= limit) {
+    for (int F = 16; F >= 1; F /= 2) {
+      std::vector<int> shifts;
+      size_t o = al16((size_t)cols.size() * S * 4);
+      for (int g = 0; g < nreq; ++g) {
+        const bk::PartArgs& a = g0.args[g];
+        m.grid_lds[g] = (int32_t)o;
+        o = al16(o + 16 * (size_t)a.ntiles);
+        m.grid_ost[g] = (int32_t)o;
+        const int f = std::min(F, std::max(1, (int)a.nbpw));
+        int sh = 0;
+        while ((1 << (sh + 1)) <= f) ++sh;
+        shifts.push_back(sh);
+        o = al16(o + ((2 * ((size_t)a.ntiles + 1)) << sh));
+      }
+      m.stage = (int32_t)o;
+      o = al16(o + (size_t)G * 4 * S);
+      if (o > limit) continue;
       m.group = std::min(G, nreq);
       m.ncols = (int32_t)cols.size();
       m.ngrids = nreq;
@@ -505,55 +518,61 @@ bool run_multi_fused(const bin_request* reqs, int nreq, hipStream_t s, int* stat
         vec = vec && reinterpret_cast<uintptr_t>(cols[u]) % 16 == 0;
       }
       m.vec = vec ? 1 : 0;
-      // the staged rows per grid for this F
-      for (int g = 0; g < nreq; ++g) {
-        const int f = std::min(F, std::max(1, (int)g0.args[g].nbpw));
-        int sh = 0;
-        while ((1 << (sh + 1)) <= f) ++sh;
-        bp.part[0].args[g].off_shift = sh;
-      }
-      const size_t lds = o;
-      // lay out the batch with the scratch, then the fused scatter's
-      // arguments after the tables
-      void* scratch = nullptr;
-      const size_t extra = al256(sizeof m);
-      st = scratch_get(dev.device, s, bp.scratch_bytes + extra, &scratch);
-      if (st) {
-        *status = st;
-        return true;
-      }
-      std::vector<int> shifts;
-      for (int g = 0; g < nreq; ++g) shifts.push_back(bp.part[0].args[g].off_shift);
-      st = plan_batch(reqs, nreq, dev, h, static_cast<unsigned char*>(scratch), &bp);
-      if (st) {
-        *status = st;
-        return true;
-      }
-      PartGroup& g = bp.part[0];
-      for (int i = 0; i < nreq; ++i) g.args[i].off_shift = shifts[i];
-      std::memcpy(bp.tables.data() + g.desc_off, g.args.data(), sizeof(bk::PartArgs) * g.args.size());
-      m.grids = g.b.descs;
-      const size_t moff = bp.tables.size();
-      bp.tables.resize(moff + extra, 0);
-      std::memcpy(bp.tables.data() + moff, &m, sizeof m);
-      bp.tables_bytes = bp.tables.size();
-      st = upload_tables(bp, static_cast<unsigned char*>(scratch), s);
-      if (st) {
-        *status = st;
-        return true;
-      }
-      const bk::MultiScatterArgs* dm = reinterpret_cast<const bk::MultiScatterArgs*>(
-          static_cast<unsigned char*>(scratch) + bp.tables_off + moff);
-      bk::KTimer* tm = timing_timer();
-      hipError_t e = bk::launch_scatter_multi(dm, g.args[0].nwg, lds, s, tm);
-      if (e == hipSuccess) e = bk::launch_partition_batch_after_scatter(g.b, g.cf64, g.af64, g.prec, g.cfg, s, tm);
-      if (e != hipSuccess) *status = hip_fail(e, "launch fused multi-grid kernels");
+      mp->shifts = shifts;
+      mp->lds = o;
+      mp->extra = al256(sizeof m);
       return true;
     }
   }
-  }
   return false;
 }
+
+// Layout pass in 'scratch' (MultiPlan::scratch_bytes() bytes): the batch's
+// pointers and its tables image, the fused scatter's arguments appended.
+// *dm is their device address.
+int multi_layout(const bin_request* reqs, int nreq, const DeviceInfo& dev, unsigned char* scratch, MultiPlan* mp,
+                 const bk::MultiScatterArgs** dm) {
+  BatchPlan& bp = mp->bp;
+  const int st = plan_batch(reqs, nreq, dev, multi_hints(), scratch, &bp);
+  if (st) return st;
+  PartGroup& g = bp.part[0];
+  for (int i = 0; i < nreq; ++i) g.args[i].off_shift = mp->shifts[i];
+  std::memcpy(bp.tables.data() + g.desc_off, g.args.data(), sizeof(bk::PartArgs) * g.args.size());
+  mp->m.grids = g.b.descs;
+  const size_t moff = bp.tables.size();
+  bp.tables.resize(moff + mp->extra, 0);
+  std::memcpy(bp.tables.data() + moff, &mp->m, sizeof mp->m);
+  bp.tables_bytes = bp.tables.size();
+  *dm = reinterpret_cast<const bk::MultiScatterArgs*>(scratch + bp.tables_off + moff);
+  return BIN_OK;
+}
+
+int multi_launch(const MultiPlan& mp, const bk::MultiScatterArgs* dm, hipStream_t s, bk::KTimer* tm) {
+  const PartGroup& g = mp.bp.part[0];
+  hipError_t e = bk::launch_scatter_multi(dm, g.args[0].nwg, mp.lds, s, tm);
+  if (e == hipSuccess) e = bk::launch_partition_batch_after_scatter(g.b, g.cf64, g.af64, g.prec, g.cfg, s, tm);
+  if (e != hipSuccess) return hip_fail(e, "launch fused multi-grid kernels");
+  return BIN_OK;
+}
+
+// Returns false (nothing done) when the requests do not qualify.
+bool run_multi_fused(const bin_request* reqs, int nreq, hipStream_t s, int* status) {
+  DeviceInfo dev;
+  *status = device_info(&dev);
+  if (*status) return true;
+  MultiPlan mp;
+  if (!multi_plan(reqs, nreq, dev, &mp, status)) return *status != BIN_OK;
+  void* scratch = nullptr;
+  *status = scratch_get(dev.device, s, mp.scratch_bytes(), &scratch);
+  if (*status) return true;
+  const bk::MultiScatterArgs* dm = nullptr;
+  *status = multi_layout(reqs, nreq, dev, static_cast<unsigned char*>(scratch), &mp, &dm);
+  if (*status == BIN_OK) *status = upload_tables(mp.bp, static_cast<unsigned char*>(scratch), s);
+  if (*status == BIN_OK) *status = multi_launch(mp, dm, s, timing_timer());
+  return true;
+}
+
+}  // namespace
 
 int run_batch(const bin_request* reqs, int nreq, hipStream_t s, const PlanHints& hints) {
   int st = validate_requests(reqs, nreq);
@@ -609,22 +628,18 @@ struct bin_graph {
   int device = 0;
 };
 
-using namespace binimpl;
+namespace binimpl {
+namespace {
 
-extern "C" {
-
-int bin_particles_batched(const bin_request* reqs, int32_t nreq, void* stream) {
-  clear_error();
-  return run_batch(reqs, nreq, static_cast<hipStream_t>(stream), thread_hints());
-}
-
-int bin_particles_multi(const bin_columns* coords, const bin_columns* attrs, int64_t n,
-                        const bin_grid_spec* grids, int32_t ngrids, void* stream) {
-  clear_error();
+// The requests of a multi-grid call: one per grid spec, all over the same
+// columns; checked as bin_particles checks its arguments.
+int specs_to_requests(const bin_columns* coords, const bin_columns* attrs, int64_t n, const bin_grid_spec* grids,
+                      int32_t ngrids, std::vector<bin_request>* out) {
   if (!coords) return fail(BIN_ERR_INVALID_ARG, "coords is NULL");
   if (ngrids < 0 || ngrids > 65535) return fail(BIN_ERR_INVALID_ARG, "ngrids must be in [0, 65535]");
   if (ngrids > 0 && !grids) return fail(BIN_ERR_INVALID_ARG, "grids is NULL");
-  std::vector<bin_request> reqs((size_t)ngrids);
+  std::vector<bin_request>& reqs = *out;
+  reqs.assign((size_t)ngrids, bin_request{});
   for (int g = 0; g < ngrids; ++g) {
     bin_request& r = reqs[(size_t)g];
     std::memset(&r, 0, sizeof r);
@@ -639,42 +654,27 @@ int bin_particles_multi(const bin_columns* coords, const bin_columns* attrs, int
     r.ops = grids[g].ops;
     r.out = grids[g].out;
   }
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  int st = validate_requests(reqs.data(), ngrids);
-  if (st) return st;
-  if (run_multi_fused(reqs.data(), ngrids, s, &st)) return st;
-  return run_batch(reqs.data(), ngrids, s, thread_hints());
+  return validate_requests(reqs.data(), ngrids);
 }
 
-int bin_graph_create(const bin_request* reqs, int32_t nreq, bin_graph** out) {
-  clear_error();
-  if (!out) return fail(BIN_ERR_INVALID_ARG, "graph is NULL");
-  *out = nullptr;
-  int st = validate_requests(reqs, nreq);
-  if (st) return st;
-  if (nreq == 0) return fail(BIN_ERR_INVALID_ARG, "a graph needs at least one request");
-  DeviceInfo dev;
-  st = device_info(&dev);
-  if (st) return st;
-  BatchPlan bp;
-  const PlanHints& hints = thread_hints();
-  st = plan_batch(reqs, nreq, dev, hints, nullptr, &bp);
-  if (st) return st;
-  if (!bp.global_reqs.empty())
-    return fail(BIN_ERR_UNSUPPORTED, "graphs do not take requests that need the global-atomic strategy");
+int copy_tables(const BatchPlan& bp, unsigned char* scratch) {
+  if (!bp.tables_bytes) return BIN_OK;
+  const hipError_t e = hipMemcpy(scratch + bp.tables_off, bp.tables.data(), bp.tables_bytes, hipMemcpyHostToDevice);
+  return e == hipSuccess ? BIN_OK : hip_fail(e, "hipMemcpy(graph tables)");
+}
+
+// A graph that owns scratch_bytes of device memory: 'layout' fills it (and
+// uploads the tables), then 'launch' is captured on a private stream.
+int capture_graph(int device, size_t scratch_bytes, const std::function<int(unsigned char*)>& layout,
+                  const std::function<int(hipStream_t)>& launch, bin_graph** out) {
   bin_graph* g = new bin_graph;
-  g->device = dev.device;
-  hipError_t e = hipMalloc(&g->scratch, std::max<size_t>(bp.scratch_bytes, 256));
+  g->device = device;
+  hipError_t e = hipMalloc(&g->scratch, std::max<size_t>(scratch_bytes, 256));
   if (e != hipSuccess) {
     delete g;
     return hip_fail(e, "hipMalloc(graph scratch)");
   }
-  st = plan_batch(reqs, nreq, dev, hints, static_cast<unsigned char*>(g->scratch), &bp);
-  if (st == BIN_OK && bp.tables_bytes) {
-    e = hipMemcpy(static_cast<unsigned char*>(g->scratch) + bp.tables_off, bp.tables.data(), bp.tables_bytes,
-                  hipMemcpyHostToDevice);
-    if (e != hipSuccess) st = hip_fail(e, "hipMemcpy(graph tables)");
-  }
+  int st = layout(static_cast<unsigned char*>(g->scratch));
   hipStream_t cs = nullptr;
   if (st == BIN_OK) {
     e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
@@ -685,7 +685,7 @@ int bin_graph_create(const bin_request* reqs, int32_t nreq, bin_graph** out) {
     if (e != hipSuccess) st = hip_fail(e, "hipStreamBeginCapture");
   }
   if (st == BIN_OK) {
-    const int lst = launch_batch(bp, cs, nullptr);
+    const int lst = launch(cs);
     e = hipStreamEndCapture(cs, &g->graph);
     if (lst) st = lst;
     else if (e != hipSuccess) st = hip_fail(e, "hipStreamEndCapture");
@@ -704,6 +704,86 @@ int bin_graph_create(const bin_request* reqs, int32_t nreq, bin_graph** out) {
   }
   *out = g;
   return BIN_OK;
+}
+
+// The batched launch sequence of validated requests as a graph.
+int batch_graph(const bin_request* reqs, int nreq, bin_graph** out) {
+  DeviceInfo dev;
+  int st = device_info(&dev);
+  if (st) return st;
+  BatchPlan bp;
+  const PlanHints& hints = thread_hints();
+  st = plan_batch(reqs, nreq, dev, hints, nullptr, &bp);
+  if (st) return st;
+  if (!bp.global_reqs.empty())
+    return fail(BIN_ERR_UNSUPPORTED, "graphs do not take requests that need the global-atomic strategy");
+  return capture_graph(
+      dev.device, bp.scratch_bytes,
+      [&](unsigned char* scratch) {
+        const int lst = plan_batch(reqs, nreq, dev, hints, scratch, &bp);
+        return lst ? lst : copy_tables(bp, scratch);
+      },
+      [&](hipStream_t cs) { return launch_batch(bp, cs, nullptr); }, out);
+}
+
+}  // namespace
+}  // namespace binimpl
+
+using namespace binimpl;
+
+extern "C" {
+
+int bin_particles_batched(const bin_request* reqs, int32_t nreq, void* stream) {
+  clear_error();
+  return run_batch(reqs, nreq, static_cast<hipStream_t>(stream), thread_hints());
+}
+
+int bin_particles_multi(const bin_columns* coords, const bin_columns* attrs, int64_t n,
+                        const bin_grid_spec* grids, int32_t ngrids, void* stream) {
+  clear_error();
+  std::vector<bin_request> reqs;
+  int st = specs_to_requests(coords, attrs, n, grids, ngrids, &reqs);
+  if (st) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (run_multi_fused(reqs.data(), ngrids, s, &st)) return st;
+  return run_batch(reqs.data(), ngrids, s, thread_hints());
+}
+
+int bin_graph_create(const bin_request* reqs, int32_t nreq, bin_graph** out) {
+  clear_error();
+  if (!out) return fail(BIN_ERR_INVALID_ARG, "graph is NULL");
+  *out = nullptr;
+  int st = validate_requests(reqs, nreq);
+  if (st) return st;
+  if (nreq == 0) return fail(BIN_ERR_INVALID_ARG, "a graph needs at least one request");
+  return batch_graph(reqs, nreq, out);
+}
+
+int bin_graph_create_multi(const bin_columns* coords, const bin_columns* attrs, int64_t n,
+                           const bin_grid_spec* grids, int32_t ngrids, bin_graph** out) {
+  clear_error();
+  if (!out) return fail(BIN_ERR_INVALID_ARG, "graph is NULL");
+  *out = nullptr;
+  std::vector<bin_request> reqs;
+  int st = specs_to_requests(coords, attrs, n, grids, ngrids, &reqs);
+  if (st) return st;
+  if (ngrids == 0) return fail(BIN_ERR_INVALID_ARG, "a graph needs at least one grid");
+  DeviceInfo dev;
+  st = device_info(&dev);
+  if (st) return st;
+  MultiPlan mp;
+  if (!multi_plan(reqs.data(), ngrids, dev, &mp, &st)) {
+    if (st) return st;
+    return batch_graph(reqs.data(), ngrids, out);  // the specs run as one batch
+  }
+  const bk::MultiScatterArgs* dm = nullptr;
+  return capture_graph(
+      dev.device, mp.scratch_bytes(),
+      [&](unsigned char* scratch) {
+        const int lst = multi_layout(reqs.data(), ngrids, dev, scratch, &mp, &dm);
+        return lst ? lst : copy_tables(mp.bp, scratch);
+      },
+      [&](hipStream_t cs) { return multi_launch(mp, dm, cs, nullptr); }, out);
 }
 
 int bin_graph_launch(bin_graph* g, void* stream) {

@@ -148,6 +148,25 @@ def test_multi_grid_rejects_bad_specs_before_any_hip_call():
     assert L.bin_particles_multi(ctypes.byref(c), None, 10, None, -1, None) == B.BIN_ERR_INVALID_ARG
 
 
+def test_multi_grid_graph_rejects_bad_specs_before_any_hip_call():
+    """bin_graph_create_multi checks its specs as bin_particles_multi does,
+    and a NULL graph handle, before any HIP call (no GPU here)."""
+    a = good()
+    grid = dict(axes=(0, 2), bounds=(0.0, 1.0, 0.0, 1.0), nx=16, ny=8, ops=B.OPS_ALL, out=a["out"])
+    with pytest.raises(B.BinError) as ei:
+        B.BinGraph.multi(a["coords"], a["attrs"], 1000, [grid, dict(grid, ny=-3)], coord_dtype=B.BIN_F32,
+                         attr_dtype=B.BIN_F32)
+    assert ei.value.status == B.BIN_ERR_INVALID_ARG
+    assert "request 1" in B.last_error(), B.last_error()
+    L = B.lib()
+    c, keep = B.columns([F, F + 0x100], B.BIN_F32)
+    h = ctypes.c_void_p()
+    assert L.bin_graph_create_multi(ctypes.byref(c), None, 10, None, 0, None) == B.BIN_ERR_INVALID_ARG
+    assert L.bin_graph_create_multi(None, None, 10, None, 1, ctypes.byref(h)) == B.BIN_ERR_INVALID_ARG
+    assert L.bin_graph_create_multi(ctypes.byref(c), None, 10, None, 0, ctypes.byref(h)) == B.BIN_ERR_INVALID_ARG
+    assert not h.value
+
+
 def test_async_rejects_before_any_hip_call():
     args = good(nx=0)
     with pytest.raises(B.BinError) as ei:
