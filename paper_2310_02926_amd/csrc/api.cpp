@@ -262,6 +262,15 @@ int scratch_get(int dev, hipStream_t s, size_t bytes, void** out) {
   return BIN_OK;
 }
 
+int scratch_release(int dev, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  auto it = g_pools.find(pool_key(dev, s));
+  if (it == g_pools.end() || !it->second.ptr) return BIN_OK;
+  const hipError_t e = hipFreeAsync(it->second.ptr, s);  // after the stream's work that used it
+  g_pools.erase(it);
+  return e == hipSuccess ? BIN_OK : hip_fail(e, "hipFreeAsync(scratch)");
+}
+
 int release_all_scratch() {
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");

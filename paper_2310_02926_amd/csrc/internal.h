@@ -54,6 +54,8 @@ int device_info(DeviceInfo* info);
 
 // scratch pools
 int scratch_get(int dev, hipStream_t s, size_t bytes, void** out);
+// Give the pool of (dev, s) back, in s's order.
+int scratch_release(int dev, hipStream_t s);
 int release_all_scratch();
 // Asynchronous mode: copy(stage) enqueues the deep copy on src into a
 // staging buffer of at least 'bytes'; bin(stage) enqueues the binning on bs,

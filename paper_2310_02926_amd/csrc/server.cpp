@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "server_admit.h"
 
 using namespace binimpl;
 
@@ -39,9 +40,6 @@ double ms_between(clk::time_point a, clk::time_point b) {
 
 size_t al256(size_t v) { return (v + 255) & ~size_t(255); }
 
-// Bytes the library's per-stream scratch pool holds after serving a call
-// that needs 'bytes' (its allocation rounds up and never goes below 1 MiB).
-size_t pool_bytes_for(size_t bytes) { return bytes ? std::max(al256(bytes), size_t(1) << 20) : 0; }
 
 enum ReqState { Q_WAITING = 0, Q_RUNNING = 1, Q_DONE = 2 };
 
@@ -252,48 +250,46 @@ bool dispatch_one(binsrv* s, std::unique_lock<std::mutex>& lk) {
       break;
     }
   if (!sl || s->queue.empty()) return false;
-  // Candidates in arrival order while their grids and (estimated) scratch fit.
-  std::vector<uint64_t> batch;
-  size_t grids = 0, est = 0;
-  const size_t base = committed(s) - sl->scratch_reserved;
-  for (size_t i = 0; i < s->queue.size() && (int)batch.size() < s->cfg.max_batch; ++i) {
-    SrvReq& q = s->reqs[s->queue[i]];
-    const size_t scratch = std::max(sl->scratch_reserved, pool_bytes_for(est + q.scratch_est));
-    if (base + grids + q.out_bytes + scratch > s->cfg.budget_bytes) break;
-    grids += q.out_bytes;
-    est += q.scratch_est;
-    batch.push_back(q.ticket);
+  // The admission rule (server_admit.h) over the head of the queue; the
+  // exact scratch of a candidate batch comes from the plan that will run it.
+  const size_t nq = std::min(s->queue.size(), (size_t)std::max(s->cfg.max_batch, 1));
+  std::vector<size_t> out_bytes(nq), scratch_est(nq);
+  for (size_t i = 0; i < nq; ++i) {
+    const SrvReq& q = s->reqs[s->queue[i]];
+    out_bytes[i] = q.out_bytes;
+    scratch_est[i] = q.scratch_est;
   }
-  if (batch.empty()) return false;  // wait for running work or released grids
-  // The scratch of the batch as it will run; drop members from the tail
-  // until it fits the budget too.
-  std::vector<bin_request> brs;
-  size_t reserve = 0;
-  for (;;) {
-    brs.clear();
-    grids = 0;
-    for (uint64_t t : batch) {
-      brs.push_back(as_bin_request(s->reqs[t]));
-      grids += s->reqs[t].out_bytes;
-    }
-    int st = BIN_OK;
-    const size_t need = exact_scratch(brs, &st);
-    if (st) {  // cannot be planned: fail the head request alone
-      if (batch.size() > 1) {
-        batch.resize(1);
-        continue;
+  auto exact = [&](size_t take, int* st) {
+    std::vector<bin_request> brs;
+    for (size_t i = 0; i < take; ++i) brs.push_back(as_bin_request(s->reqs[s->queue[i]]));
+    return exact_scratch(brs, st);
+  };
+  AdmitDecision d = admit(out_bytes.data(), scratch_est.data(), nq, committed(s) - sl->scratch_reserved,
+                          sl->scratch_reserved, s->cfg.budget_bytes, (size_t)s->cfg.max_batch, exact);
+  if (d.take == 0) {
+    // The scratch pools of idle slots may be what keeps the head out: they
+    // are given back (in their streams' order) and the head tried again.
+    bool freed = false;
+    for (auto& o : s->slots)
+      if (!o->busy && o->scratch_reserved) {
+        (void)scratch_release(s->cfg.device, o->stream);
+        o->scratch_reserved = 0;
+        freed = true;
       }
-      SrvReq& q = s->reqs[batch[0]];
-      s->queue.pop_front();
-      fail_request(s, q, st);
-      s->cv_done.notify_all();
-      return true;
-    }
-    reserve = std::max(sl->scratch_reserved, pool_bytes_for(need));
-    if (base + grids + reserve <= s->cfg.budget_bytes) break;
-    if (batch.size() == 1) return false;  // fits once more memory is free
-    batch.resize(batch.size() / 2);
+    if (freed)
+      d = admit(out_bytes.data(), scratch_est.data(), nq, committed(s), 0, s->cfg.budget_bytes,
+                (size_t)s->cfg.max_batch, exact);
+    if (d.take == 0) return false;  // wait for running work or released grids
   }
+  if (d.status) {  // cannot be planned: fail the head request alone
+    SrvReq& q = s->reqs[s->queue.front()];
+    s->queue.pop_front();
+    fail_request(s, q, d.status);
+    s->cv_done.notify_all();
+    return true;
+  }
+  std::vector<uint64_t> batch(s->queue.begin(), s->queue.begin() + (std::ptrdiff_t)d.take);
+  const size_t reserve = d.reserve;
   // Commit: the slot, its scratch reservation, the members' grid bytes.
   for (size_t i = 0; i < batch.size(); ++i) s->queue.pop_front();
   sl->busy = true;
