@@ -213,19 +213,50 @@ struct Tile {
 
   __device__ static void count(unsigned char* smem, int b) { atomicAdd(reinterpret_cast<uint32_t*>(smem) + b, 1u); }
 
+  // Plain binary32 sum: S' = fl(S + v) by a 4-byte compare-and-swap (on
+  // gfx950 a float add in LDS runs at a fraction of the rate of the integer
+  // operations; the swap and its read are two of those).  'seen' is the
+  // word as last read; a failed swap returns the current word.
+  __device__ static void plain_update(uint32_t* p, uint32_t seen, float v) {
+    for (;;) {
+      const uint32_t want = __float_as_uint(__uint_as_float(seen) + v);
+      if (__hip_atomic_compare_exchange_strong(p, &seen, want, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP))
+        return;
+    }
+  }
+
+  // Compensated binary32 sum (TwoSum): a bin's running sum S and its
+  // compensation C share one 8-byte word, low half S, high half C, and are
+  // updated together by compare-and-swap: S' = fl(S + v), C' = fl(C + e)
+  // with e the exact rounding error of S + v.  'seen' is the word as last
+  // read; a failed swap returns the current word and the update is redone
+  // on it, so every attempt that fails lets another one succeed.
+  __device__ static void comp_update(unsigned long long* p, unsigned long long seen, float v) {
+    for (;;) {
+      const float s = __uint_as_float((uint32_t)seen);
+      const float c = __uint_as_float((uint32_t)(seen >> 32));
+      const float ns = s + v;
+      const float nc = c + two_sum_err(s, v, ns);
+      const unsigned long long want =
+          (unsigned long long)__float_as_uint(ns) | ((unsigned long long)__float_as_uint(nc) << 32);
+      if (__hip_atomic_compare_exchange_strong(p, &seen, want, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP))
+        return;
+    }
+  }
+
   __device__ static void add(unsigned char* smem, const TileLayout& L, int j, int b, AT v) {
     if (L.want_sum) {
       unsigned char* base = smem + L.lds_sum_off[j];
       if constexpr (PREC == PREC_F64) {
         atomicAdd(reinterpret_cast<double*>(base) + b, (double)v);
       } else if constexpr (PREC == PREC_PLAIN) {
-        atomicAdd(reinterpret_cast<float*>(base) + b, (float)v);
-      } else {  // TwoSum: the returning add gives the value the sum held
-        float* S = reinterpret_cast<float*>(base);
-        const float fv = (float)v;
-        const float old = atomicAdd(S + b, fv);
-        const float e = two_sum_err(old, fv, old + fv);
-        if (e != 0.0f) atomicAdd(S + L.tb + b, e);
+        uint32_t* P = reinterpret_cast<uint32_t*>(base) + b;
+        plain_update(P, __hip_atomic_load(P, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP), (float)v);
+      } else {
+        unsigned long long* P = reinterpret_cast<unsigned long long*>(base) + b;
+        comp_update(P, __hip_atomic_load(P, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP), (float)v);
       }
     }
     // min/max keys only move one way, so a value that does not beat the key
@@ -257,21 +288,23 @@ struct Tile {
         for (int u = 0; u < R; ++u)
           if (lb[u] >= 0) atomicAdd(reinterpret_cast<double*>(base) + lb[u], (double)v[u]);
       } else if constexpr (PREC == PREC_PLAIN) {
+        uint32_t* P = reinterpret_cast<uint32_t*>(base);
+        uint32_t seen[R];
 #pragma unroll
         for (int u = 0; u < R; ++u)
-          if (lb[u] >= 0) atomicAdd(reinterpret_cast<float*>(base) + lb[u], (float)v[u]);
+          seen[u] = lb[u] >= 0 ? __hip_atomic_load(P + lb[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0u;
+#pragma unroll
+        for (int u = 0; u < R; ++u)
+          if (lb[u] >= 0) plain_update(P + lb[u], seen[u], (float)v[u]);
       } else {
-        float* S = reinterpret_cast<float*>(base);
-        float old[R];
+        unsigned long long* P = reinterpret_cast<unsigned long long*>(base);
+        unsigned long long seen[R];
 #pragma unroll
-        for (int u = 0; u < R; ++u) old[u] = lb[u] >= 0 ? atomicAdd(S + lb[u], (float)v[u]) : 0.0f;
+        for (int u = 0; u < R; ++u)
+          seen[u] = lb[u] >= 0 ? __hip_atomic_load(P + lb[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0ull;
 #pragma unroll
-        for (int u = 0; u < R; ++u) {
-          if (lb[u] < 0) continue;
-          const float fv = (float)v[u];
-          const float e = two_sum_err(old[u], fv, old[u] + fv);
-          if (e != 0.0f) atomicAdd(S + L.tb + lb[u], e);
-        }
+        for (int u = 0; u < R; ++u)
+          if (lb[u] >= 0) comp_update(P + lb[u], seen[u], (float)v[u]);
       }
     }
     if (L.want_min || L.want_max) {
@@ -312,8 +345,8 @@ struct Tile {
     if constexpr (PREC == PREC_F64) return reinterpret_cast<const double*>(base)[b];
     else if constexpr (PREC == PREC_PLAIN) return (double)reinterpret_cast<const float*>(base)[b];
     else {
-      const float* S = reinterpret_cast<const float*>(base);
-      return (double)S[b] + (double)S[L.tb + b];
+      const float* SC = reinterpret_cast<const float*>(base) + 2 * b;
+      return (double)SC[0] + (double)SC[1];
     }
   }
   __device__ static K min_get(const unsigned char* smem, const TileLayout& L, int j, int b) {

@@ -727,7 +727,9 @@ __device__ __forceinline__ void part_bin_body(const PartArgs& a, int item) {
       const uint32_t start = rs - (incl - len);  // record = start + q for q in the lane's run
       // R windows of 64 records at a time: all their loads are issued before
       // the first LDS update, so R gathers per wave are in flight.
-      constexpr int R = sizeof(AT) == 8 ? 4 : 8;
+      // (4 with f64 values, or with the compensated sum's 8-byte words in
+      // flight, to stay within the registers of a 1024-thread workgroup)
+      constexpr int R = (sizeof(AT) == 8 || PREC == PREC_COMP) ? 4 : 8;
       for (uint32_t wb = 0; 64 * (sub + wpg * wb) < total; wb += R) {
         uint32_t rec[R];
         int lb[R];
