@@ -485,12 +485,17 @@ def run_multi(args):
                           out=B.alloc_outputs(cols, side, side, 31, dev)))
     stream = torch.cuda.Stream()
 
+    # both sides marshalled once, as a simulation binning every step would
+    multi = B.Multi(cols, cols, n, grids)
+    alone = B.Batch([dict(coords=cols, attrs=cols, n=n, axes=g["axes"], bounds=g["bounds"], nx=side, ny=side,
+                          ops=31, out=g["out"]) for g in grids])
+
     def fused():
-        B.bin_particles_multi(cols, cols, n, grids, stream=stream)
+        multi.launch(stream)
 
     def separate():
-        for g in grids:
-            B.bin_particles(cols, cols, n, g["axes"], g["bounds"], side, side, 31, g["out"], stream=stream)
+        for i in range(alone.n):
+            alone.launch_one(i, stream)
     graph = B.BinGraph.multi(cols, cols, n, grids)  # the per-step replay of the same call
     for _ in range(args.warmup):
         fused()

@@ -412,6 +412,23 @@ def bin_particles_multi(coords, attrs, n: int, grids: Sequence[Dict], stream=Non
                                     len(grids), _stream_handle(stream)))
 
 
+class Multi:
+    """A multi-grid call (bin_particles_multi) marshalled once and enqueued
+    many times, as a simulation does every step."""
+
+    def __init__(self, coords, attrs, n: int, grids: Sequence[Dict], coord_dtype=None, attr_dtype=None):
+        self._c, self._ck = columns(coords, coord_dtype)
+        self._a, self._ak = columns(attrs, attr_dtype) if attrs else (None, None)
+        self._arr, self._keep = grid_specs(grids)
+        self.n = n
+        self.ngrids = len(grids)
+
+    def launch(self, stream=None) -> None:
+        check(lib().bin_particles_multi(ctypes.byref(self._c),
+                                        ctypes.byref(self._a) if self._a is not None else None, self.n, self._arr,
+                                        self.ngrids, _stream_handle(stream)))
+
+
 class Batch:
     """Requests marshalled once and enqueued many times, as one batch
     (bin_particles_batched) or one request at a time (bin_particles)."""

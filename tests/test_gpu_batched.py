@@ -244,6 +244,22 @@ def test_multi_grid_nine_planes_ten_variables():
         for key in ("sum", "avg"):
             for x, y in zip(got[key], a[key]):
                 assert np.allclose(x, y, rtol=1e-12, atol=1e-9, equal_nan=True), (g, key)
+    # the same call marshalled once (binding.Multi) and enqueued twice
+    before = [_to_np(grid["out"]) for grid in grids]
+    for grid in grids:
+        for key, val in grid["out"].items():
+            for t in (val if isinstance(val, list) else [val]):
+                t.fill_(7)
+    m = B.Multi(cols, cols, tab.n, grids)
+    m.launch()
+    m.launch()
+    torch.cuda.synchronize()
+    for g, (grid, b) in enumerate(zip(grids, before)):
+        got = _to_np(grid["out"])
+        assert np.array_equal(got["count"], b["count"]), g
+        for key in ("min", "max"):
+            for x, y in zip(got[key], b[key]):
+                assert np.array_equal(x.view(np.int32), y.view(np.int32)), (g, key)
 
 
 _TUNE_CHILD = r'''
