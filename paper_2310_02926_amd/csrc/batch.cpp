@@ -51,8 +51,6 @@ struct LdsGroup {
   int prec = 0;
   std::vector<int> idx;
   std::vector<bk::LdsArgs> args;
-  size_t lds_bytes = 0;
-  int block = 512;
   bk::LdsBatch b{};
   size_t desc_off = 0, map_slot_off = 0, map_merge_off = 0;
   std::vector<uint32_t> map_slot, map_merge;
@@ -163,14 +161,7 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
     g.args.resize(R);
     // The group's scatter shape; staged values sized for the largest request.
     const int ppt = g.ppt, nt = g.nt;
-    size_t bin_lds = 16;
-    int bin_block = 256;
     size_t asz = g.af64 ? 8 : 4;
-    for (int r = 0; r < R; ++r) {
-      const Prepared& p = bp->preps[g.idx[r]];
-      bin_lds = std::max(bin_lds, p.pcfg.bin_lds);
-      bin_block = std::max(bin_block, p.pcfg.bin_block);
-    }
     const size_t S = (size_t)nt * ppt;
     // Per request: tile counters, record stage (with quad padding) and
     // values, then its staged rows of the run table; the launch takes the
@@ -187,8 +178,6 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
     g.cfg.scatter_threads = nt;
     g.cfg.quads = g.quads ? 1 : 0;
     g.cfg.scatter_lds = scatter_lds;
-    g.cfg.bin_lds = bin_lds;
-    g.cfg.bin_block = bin_block;
     if (scatter_lds + 256 > dev.lds_per_block)
       return fail(BIN_ERR_UNSUPPORTED, "batched scatter stage does not fit LDS");
     // Per-request scratch: tile totals, sub-chunk run tables, records,
@@ -222,11 +211,24 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
     g.map_walk.clear();
     g.map_item.clear();
     g.map_tile.clear();
+    // Tile-binning classes by the LDS of each request's tile: a quarter of
+    // a CU's LDS or less runs in 256-thread workgroups (four per CU), half
+    // or less in 512-thread ones (two per CU), larger tiles in 1024-thread
+    // ones.  Every CU then holds 16 waves either way, but small tiles have
+    // several work items in flight per CU, so one item's chain of dependent
+    // loads (its item record, its run table, its first records) and its
+    // result stores overlap another's binning: on batches of many small
+    // requests an item's fixed cost is several times its per-record cost.
+    std::vector<uint32_t> cls_items[3];
+    size_t cls_lds[3] = {0, 0, 0};
     for (int r = 0; r < R; ++r) {
       const bk::PartArgs& a = g.args[r];
       for (int w = 0; w < a.nwg; ++w) g.map_wg.push_back(((uint32_t)r << 16) | (uint32_t)w);
       for (int b = 0; b < (a.ntiles + 15) / 16; ++b) g.map_walk.push_back(((uint32_t)r << 16) | (uint32_t)b);
-      for (int i = 0; i < a.max_items; ++i) g.map_item.push_back(((uint32_t)r << 16) | (uint32_t)i);
+      const size_t tl = bp->preps[g.idx[r]].pcfg.bin_lds;
+      const int q = 4 * tl <= dev.lds_per_cu ? 0 : 2 * tl <= dev.lds_per_cu ? 1 : 2;
+      cls_lds[q] = std::max(cls_lds[q], tl);
+      for (int i = 0; i < a.max_items; ++i) cls_items[q].push_back(((uint32_t)r << 16) | (uint32_t)i);
       for (int b = 0; b < a.merge_blocks; ++b) g.map_tile.push_back(((uint32_t)r << 16) | (uint32_t)b);
       if (a.nwg > 65536 || a.max_items > 65536 || a.ntiles > 65536)
         return fail(BIN_ERR_UNSUPPORTED, "request too large for a batch block map");
@@ -238,16 +240,19 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
     // share of every request; 0xFFFFFFFF pads to a whole round.  (Runs of
     // 8 beat 1, 4 and 32 on the 256-request batch and the nine-plane
     // multi-grid call.)
-    {
+    for (int q = 0; q < 3; ++q) {
       const size_t C = 8, round = 8 * C;
-      const size_t nat = g.map_item.size(), npad = (nat + round - 1) / round * round;
-      std::vector<uint32_t> xm(npad);
+      const std::vector<uint32_t>& it = cls_items[q];
+      const size_t nat = it.size(), npad = (nat + round - 1) / round * round;
+      g.b.cls_first[q] = (int32_t)g.map_item.size();
+      g.b.cls_block[q] = 256 << q;
+      g.b.cls_lds[q] = (int32_t)cls_lds[q];
       for (size_t b = 0; b < npad; ++b) {
         const size_t i = b / round * round + (b % 8) * C + (b / 8) % C;
-        xm[b] = i < nat ? g.map_item[i] : 0xFFFFFFFFu;
+        g.map_item.push_back(i < nat ? it[i] : 0xFFFFFFFFu);
       }
-      g.map_item.swap(xm);
     }
+    g.b.cls_first[3] = (int32_t)g.map_item.size();
     g.b.n_wg_blocks = (int32_t)g.map_wg.size();
     g.b.n_walk_blocks = (int32_t)g.map_walk.size();
     g.b.n_item_blocks = (int32_t)g.map_item.size();
@@ -258,21 +263,34 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
     const int R = (int)g.idx.size();
     if (R > 65535) return fail(BIN_ERR_UNSUPPORTED, "a batch group holds at most 65535 requests");
     g.args.resize(R);
-    g.lds_bytes = 16;
-    g.block = 512;
     g.map_slot.clear();
     g.map_merge.clear();
+    // Classes by the LDS of each request's grid, as for the tile binning: a
+    // quarter of a CU's LDS or less in 512-thread workgroups (four per CU;
+    // the kernel's registers allow 32 waves), half or less and larger ones
+    // in 1024-thread workgroups (two or one per CU).  A large grid no
+    // longer holds every small request of the batch to one workgroup per CU.
+    std::vector<uint32_t> cls_slots[3];
+    size_t cls_lds[3] = {0, 0, 0};
     for (int r = 0; r < R; ++r) {
       const Prepared& p = bp->preps[g.idx[r]];
       bk::LdsArgs a = p.lds;
       a.partial = a.nslots > 1 ? take((size_t)a.lay.slot_bytes * a.nslots) : nullptr;
       g.args[r] = a;
-      g.lds_bytes = std::max(g.lds_bytes, p.cfg.lds_bytes);
-      g.block = std::max(g.block, p.cfg.block);
-      for (int s = 0; s < a.nslots; ++s) g.map_slot.push_back(((uint32_t)r << 16) | (uint32_t)s);
+      const size_t gl = p.cfg.lds_bytes;
+      const int q = 4 * gl <= dev.lds_per_cu ? 0 : 2 * gl <= dev.lds_per_cu ? 1 : 2;
+      cls_lds[q] = std::max(cls_lds[q], gl);
+      for (int s = 0; s < a.nslots; ++s) cls_slots[q].push_back(((uint32_t)r << 16) | (uint32_t)s);
       if (a.nslots > 1)
         for (int64_t c = 0; c < cdiv(a.nbins, 64); ++c) g.map_merge.push_back(((uint32_t)r << 16) | (uint32_t)c);
     }
+    for (int q = 0; q < 3; ++q) {
+      g.b.cls_first[q] = (int32_t)g.map_slot.size();
+      g.b.cls_block[q] = q == 0 ? 512 : 1024;
+      g.b.cls_lds[q] = (int32_t)cls_lds[q];
+      g.map_slot.insert(g.map_slot.end(), cls_slots[q].begin(), cls_slots[q].end());
+    }
+    g.b.cls_first[3] = (int32_t)g.map_slot.size();
     g.b.nreq = R;
     g.b.n_slot_blocks = (int32_t)g.map_slot.size();
     g.b.n_merge_blocks = (int32_t)g.map_merge.size();
@@ -333,7 +351,7 @@ int launch_batch(const BatchPlan& bp, hipStream_t s, bk::KTimer* tm) {
     if (e != hipSuccess) return hip_fail(e, "launch batched partition kernels");
   }
   for (const auto& g : bp.lds) {
-    hipError_t e = bk::launch_lds_batch(g.b, g.cf64, g.af64, g.prec, g.lds_bytes, g.block, s, tm);
+    hipError_t e = bk::launch_lds_batch(g.b, g.cf64, g.af64, g.prec, s, tm);
     if (e != hipSuccess) return hip_fail(e, "launch batched LDS kernels");
   }
   return BIN_OK;

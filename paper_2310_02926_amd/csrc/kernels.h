@@ -124,8 +124,14 @@ struct LdsArgs {
 struct LdsBatch {
   const LdsArgs* descs;
   const uint32_t* map_slot;   // binning blocks (index = workgroup slice)
-  const uint32_t* map_merge;  // merge blocks (index = 256-bin chunk)
+  const uint32_t* map_merge;  // merge blocks (index = 64-bin chunk)
   int32_t nreq, n_slot_blocks, n_merge_blocks, pad;
+  // The binning blocks run as up to three launches, one per class of grid
+  // LDS: class c is map_slot[cls_first[c], cls_first[c + 1]) with
+  // cls_block[c] threads and cls_lds[c] bytes of LDS per workgroup.
+  int32_t cls_first[4];
+  int32_t cls_block[3];
+  int32_t cls_lds[3];
 };
 
 // ---- partition strategy --------------------------------------------------
@@ -179,6 +185,12 @@ struct PartBatch {
   const uint32_t* map_item;  // binning blocks (index = work item)
   const uint32_t* map_tile;  // merge blocks (index = merge workgroup of the request)
   int32_t nreq, n_wg_blocks, n_walk_blocks, n_item_blocks, n_tile_blocks;
+  // The binning blocks run as up to three launches, one per class of tile
+  // LDS: class c is map_item[cls_first[c], cls_first[c + 1]) with
+  // cls_block[c] threads and cls_lds[c] bytes of LDS per workgroup.
+  int32_t cls_first[4];
+  int32_t cls_block[3];
+  int32_t cls_lds[3];
 };
 
 // ---- several grids over one table: the fused scatter -----------------------
@@ -248,8 +260,7 @@ hipError_t launch_bin_global(const BinArgs& a, bool coord_f64, bool attr_f64, in
                              hipStream_t s, KTimer* tm);
 hipError_t launch_bin_lds(const LdsArgs& a, bool coord_f64, bool attr_f64, int prec, const LaunchCfg& c,
                           hipStream_t s, KTimer* tm);
-hipError_t launch_lds_batch(const LdsBatch& b, bool coord_f64, bool attr_f64, int prec, size_t lds_bytes, int block,
-                            hipStream_t s, KTimer* tm);
+hipError_t launch_lds_batch(const LdsBatch& b, bool coord_f64, bool attr_f64, int prec, hipStream_t s, KTimer* tm);
 hipError_t launch_init(const InitArgs& a, int grid, hipStream_t s, KTimer* tm);
 hipError_t launch_finalize(const FinArgs& a, int grid, hipStream_t s, KTimer* tm);
 hipError_t launch_partition(const PartArgs& a, bool coord_f64, bool attr_f64, int prec, const PartCfg& c,

@@ -196,12 +196,14 @@ static hipError_t launch_lds_t(const LdsArgs& a, const LaunchCfg& c, hipStream_t
 }
 
 template <typename CT, typename AT, int PREC>
-static hipError_t launch_lds_batch_t(const LdsBatch& b, size_t lds_bytes, int block, hipStream_t s, KTimer* tm) {
+static hipError_t launch_lds_batch_t(const LdsBatch& b, hipStream_t s, KTimer* tm) {
   hipError_t e;
-  if (b.n_slot_blocks > 0) {
+  for (int q = 0; q < 3; ++q) {
+    const int nb = b.cls_first[q + 1] - b.cls_first[q];
+    if (nb <= 0) continue;
     if (tm) tm->begin(s);
-    hipLaunchKernelGGL((bin_lds_batched<CT, AT, PREC>), dim3(b.n_slot_blocks), dim3(block), lds_bytes, s, b.descs,
-                       b.map_slot);
+    hipLaunchKernelGGL((bin_lds_batched<CT, AT, PREC>), dim3(nb), dim3(b.cls_block[q]), (size_t)b.cls_lds[q], s,
+                       b.descs, b.map_slot + b.cls_first[q]);
     if (tm) tm->end("bin_lds_kernel", s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
@@ -241,9 +243,8 @@ hipError_t launch_bin_lds(const LdsArgs& a, bool coord_f64, bool attr_f64, int p
   BK_DISPATCH(launch_lds_t, a, c, s, tm)
 }
 
-hipError_t launch_lds_batch(const LdsBatch& b, bool coord_f64, bool attr_f64, int prec, size_t lds_bytes, int block,
-                            hipStream_t s, KTimer* tm) {
-  BK_DISPATCH(launch_lds_batch_t, b, lds_bytes, block, s, tm)
+hipError_t launch_lds_batch(const LdsBatch& b, bool coord_f64, bool attr_f64, int prec, hipStream_t s, KTimer* tm) {
+  BK_DISPATCH(launch_lds_batch_t, b, s, tm)
 }
 #undef BK_DISPATCH
 

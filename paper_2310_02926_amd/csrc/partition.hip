@@ -903,12 +903,15 @@ static hipError_t launch_part_batch_t(const PartBatch& b, const PartCfg& c, hipS
   }
   BK_LAUNCH("part_items_walk_kernel", part_items_walk_batched, b.n_walk_blocks, 1024, 0, b.descs, b.map_walk);
   BK_LAUNCH("part_items_kernel", part_items_batched, b.nreq, 1024, 0, b.descs);
-  if (c.quads)
-    BK_LAUNCH("part_bin_kernel", (part_bin_batched<AT, PREC, true>), b.n_item_blocks, c.bin_block, c.bin_lds, b.descs,
-              b.map_item);
-  else
-    BK_LAUNCH("part_bin_kernel", (part_bin_batched<AT, PREC, false>), b.n_item_blocks, c.bin_block, c.bin_lds,
-              b.descs, b.map_item);
+  for (int q = 0; q < 3; ++q) {
+    const int nb = b.cls_first[q + 1] - b.cls_first[q];
+    if (c.quads)
+      BK_LAUNCH("part_bin_kernel", (part_bin_batched<AT, PREC, true>), nb, b.cls_block[q], b.cls_lds[q], b.descs,
+                b.map_item + b.cls_first[q]);
+    else
+      BK_LAUNCH("part_bin_kernel", (part_bin_batched<AT, PREC, false>), nb, b.cls_block[q], b.cls_lds[q], b.descs,
+                b.map_item + b.cls_first[q]);
+  }
   BK_LAUNCH("part_merge_kernel", (part_merge_batched<AT, PREC>), b.n_tile_blocks, 1024, 0, b.descs, b.map_tile);
   return hipSuccess;
 }
