@@ -10,8 +10,10 @@
 // and gather form their plans chose.  Every request keeps its own
 // scratch (records, run table, counts, items, partial slots); the groups
 // share device tables of descriptors and block maps, uploaded once, and
-// each group runs one table-driven launch per stage for all its requests.
-// Requests that need the global-atomic strategy run one by one.
+// each group runs one table-driven launch per stage for all its requests
+// (the binning stage as up to three launches, by the LDS of each request's
+// tile or grid).  Requests that need the global-atomic strategy run one by
+// one.
 #include <algorithm>
 #include <cstring>
 #include <functional>

@@ -119,6 +119,37 @@ def test_batched_mixed_dtypes_and_strategies():
     _check_vs_oracle(reqs, wss, "global fallback")
 
 
+def test_batched_lds_classes():
+    """Members whose tiles (tile binning) or whole grids (LDS strategy) take
+    up to a quarter, up to a half and more than half of a CU's LDS run as
+    separate launches of their own workgroup size; every result equals the
+    oracle and the same request run alone."""
+    import re
+    from paper_2310_02926_amd import binding as B
+    _case("batched LDS classes")
+    A = B.OPS_ALL
+    specs = [synth.InstanceSpec(200_000, 1024, 4, A, 11), synth.InstanceSpec(150_000, 1024, 2, A, 12),
+             synth.InstanceSpec(300_000, 256, 2, A, 13), synth.InstanceSpec(300_000, 256, 1, A, 14),
+             synth.InstanceSpec(80_000, 32, 1, A, 15), synth.InstanceSpec(100_000, 64, 1, A, 16),
+             synth.InstanceSpec(80_000, 48, 3, A, 17)]
+    wss = [synth.instance(sp) for sp in specs]
+    reqs = _requests(wss)
+    arr, keep = B.request_array(reqs)
+    props = torch.cuda.get_device_properties(0)
+    cu_lds = getattr(props, "shared_memory_per_multiprocessor", 0) or 163840
+    seen = {"partition": set(), "lds": set()}
+    for i in range(len(reqs)):
+        d = B.bin_describe_plan(arr[i])
+        kind = d.split()[0]
+        size = int(re.search(r"bin_lds=(\d+)" if kind == "partition" else r"\blds=(\d+)", d).group(1))
+        seen[kind].add(0 if 4 * size <= cu_lds else 1 if 2 * size <= cu_lds else 2)
+    assert seen == {"partition": {0, 1, 2}, "lds": {0, 1, 2}}, seen
+    B.bin_particles_batched(reqs)
+    torch.cuda.synchronize()
+    _check_vs_oracle(reqs, wss, "classes")
+    _same_as_alone(reqs, wss, "classes")
+
+
 def test_batched_edge_requests():
     from paper_2310_02926_amd import binding as B
     _case("batched edge requests")
