@@ -622,9 +622,14 @@ def time_region(call, stream, steps):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
+    h0 = time.perf_counter()
     for _ in range(steps):
         call()
     e1.record(stream)
+    # host time to enqueue the region: a region whose device time exceeds
+    # the sum of its calls' own times by far while this is small waited on
+    # the device; one where this is close to the device time was host-bound
+    time_region.host_ms = (time.perf_counter() - h0) * 1e3
     stream.synchronize()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1)
@@ -717,7 +722,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="hotspot",
                     choices=["hotspot", "gmm", "uniform", "nd3", "batched", "served", "insitu", "multi"])
     ap.add_argument("--prec", default="default", choices=["default", "comp", "plain", "f64"])
@@ -762,9 +767,10 @@ def main():
             B.bin_particles_nd(coords, attrs, ws.n, nd_axes, nd_bounds, nd_dims, ops, out, stream=stream)
     else:
         out = B.alloc_outputs(attrs, ws.nx, ws.ny, ops, dev)
+        prepared = B.Call(coords, attrs, ws.n, ws.axes, ws.bounds, ws.nx, ws.ny, ops, out)
 
         def call():
-            B.bin_particles(coords, attrs, ws.n, ws.axes, ws.bounds, ws.nx, ws.ny, ops, out, stream=stream)
+            prepared.launch(stream)
     torch.cuda.synchronize()
 
     if args.copy_calibration:
@@ -789,6 +795,7 @@ def main():
     # Timed region 1: exactly `steps` whole calls, bracketed by events on the
     # launch stream with the device synchronised on both sides.
     ms_step = time_region(call, stream, args.steps) / args.steps
+    host_ms_step = time_region.host_ms / args.steps
     # Region 2: the same calls one by one (an event pair around each), for
     # the distribution of the time per call.
     each = np.asarray(time_each(call, stream, args.steps))
@@ -801,7 +808,8 @@ def main():
     rep = B.bin_timing_report()
     dominant = max(rep, key=lambda k: rep[k][1])
     launches, kern_ms = rep[dominant]
-    log(f"timed {args.steps} steps: {ms_step:.4f} ms/step (median {np.median(each):.4f}); kernels (avg ms): "
+    log(f"timed {args.steps} steps: {ms_step:.4f} ms/step (median {np.median(each):.4f}, host enqueue "
+        f"{host_ms_step:.4f} ms/step); kernels (avg ms): "
         + ", ".join(f"{k}={v[1] / max(v[0], 1):.4f}" for k, v in sorted(rep.items(), key=lambda kv: -kv[1][1])))
     copy_gbs = stream_copy_GBs(dev, stream)
     log(f"stream copy {copy_gbs:.0f} GB/s")
@@ -852,6 +860,7 @@ def main():
         },
         "per_call_ms": {"median": round(float(np.median(each)), 5), "p10": round(float(np.percentile(each, 10)), 5),
                         "p90": round(float(np.percentile(each, 90)), 5), "calls": int(each.size)},
+        "host_enqueue_ms_per_step": round(host_ms_step, 5),
         "kernels_ms_avg": {k: round(v[1] / max(v[0], 1), 5) for k, v in rep.items()},
         "whole_call": {
             "algorithmic_bytes": ins + outs,

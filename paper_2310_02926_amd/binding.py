@@ -240,6 +240,25 @@ def bin_particles(coords, attrs, n: int, axes, bounds, nx: int, ny: int, ops: in
     check(st)
 
 
+class Call:
+    """One request (bin_particles) marshalled once and enqueued many times,
+    as a simulation bins its particles every step: each launch passes the
+    prepared records and only the stream handle is looked up again."""
+
+    def __init__(self, coords, attrs, n: int, axes, bounds, nx: int, ny: int, ops: int, out: Dict,
+                 coord_dtype=None, attr_dtype=None):
+        self._c, self._ck = columns(coords, coord_dtype)
+        self._a, self._ak = columns(attrs, attr_dtype) if attrs is not None else (None, None)
+        self._o, self._ok = output(out.get("count"), out.get("sum"), out.get("min"), out.get("max"), out.get("avg"))
+        self._args = (ctypes.byref(self._c), ctypes.byref(self._a) if self._a is not None else None, n,
+                      (c_int32 * 2)(*axes), (c_double * 4)(*bounds) if bounds is not None else None, nx, ny, ops,
+                      ctypes.byref(self._o))
+        self._fn = lib().bin_particles
+
+    def launch(self, stream=None) -> None:
+        check(self._fn(*self._args, _stream_handle(stream)))
+
+
 def bin_particles_noalloc(coords, attrs, n: int, axes, bounds, nx: int, ny: int, ops: int, out: Dict,
                           stream=None, coord_dtype=None, attr_dtype=None) -> None:
     """bin_particles with the library's scratch in its fixed per-GPU array

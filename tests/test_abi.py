@@ -108,6 +108,18 @@ def test_bin_particles_rejects_before_any_hip_call():
         assert ei.value.status == B.BIN_ERR_INVALID_ARG
 
 
+def test_prepared_call_passes_the_same_arguments():
+    # A request marshalled once (binding.Call) reaches the same checks with
+    # the same arguments as bin_particles, launch after launch.
+    for over, frag in ((dict(nx=0), "nx, ny"), (dict(axes=(0, 3)), "axes[1]"), (dict(ops=0), "no reduction"),
+                       (dict(bounds=(0.0, 1.0, 2.0, 1.0)), "lo < hi")):
+        call = B.Call(**good(**over))
+        for _ in range(2):
+            with pytest.raises(B.BinError) as ei:
+                call.launch(stream=0)
+            assert ei.value.status == B.BIN_ERR_INVALID_ARG and frag in B.last_error(), B.last_error()
+
+
 def test_plain_sum_outputs_may_be_4_byte_aligned():
     out = {"count": F, "sum": [F + 4, F], "min": [F, F], "max": [F, F], "avg": [F + 4, F]}
     assert validate(out=out, ops=B.OPS_ALL | B.PREC_PLAIN) == B.BIN_OK

@@ -436,3 +436,27 @@ def test_plan_without_gpu_matches_device_plan():
         out = B.alloc_outputs(attrs, side, side, 31, "cuda")
         req, keep = B.request(coords, attrs, n, (0, 1), (0.0, 1.0, 0.0, 1.0), side, side, 31, out)
         assert B.bin_describe_plan(req) == B.bin_describe_plan_on(req, cus, lds, lds), (n, side, k)
+
+
+def test_prepared_call_repeats_match_oracle():
+    """A request marshalled once (binding.Call) and launched several times
+    into the same outputs gives the oracle's result each time, as when a
+    simulation bins every step."""
+    from paper_2310_02926_amd import binding as B
+    _case("prepared call, three launches, gmm f32 k=4 512x512")
+    ws = synth.gmm_f32(n=300_000, seed=5, nx=512, ny=512, k=4)
+    coords, attrs = G.to_device(ws)
+    out = B.alloc_outputs(attrs, ws.nx, ws.ny, ws.ops, coords[0].device)
+    call = B.Call(coords, attrs, ws.n, ws.axes, ws.bounds, ws.nx, ws.ny, ws.ops, out)
+    ref = G.oracle(ws)
+    s = torch.cuda.Stream()
+    for step in range(3):
+        for t in [out["count"]] + [x for key in ("sum", "min", "max", "avg") for x in out.get(key, [])]:
+            t.fill_(7)
+        torch.cuda.synchronize()
+        call.launch(s)
+        s.synchronize()
+        got = {"count": out["count"].cpu().numpy().view(np.uint32).astype(np.int64)}
+        for key in ("sum", "min", "max", "avg"):
+            got[key] = [t.cpu().numpy() for t in out[key]]
+        G.assert_parity(got, ref, ws.ops, what=f"prepared call launch {step}")
