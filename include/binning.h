@@ -218,9 +218,9 @@ int bin_validate_nd(const bin_columns* coords, const bin_columns* attrs, int64_t
  * table-driven launch per stage (scatter, work items, tile binning, merge;
  * or whole-grid LDS binning and merge) for all its requests, a block map
  * listing each block's request and index.  The tile binning and the
- * whole-grid binning split into up to three launches by the LDS each
- * request's tile or grid takes, so that small tiles run several workgroups
- * per compute unit next to requests with large ones.  Each result equals
+ * whole-grid binning split into up to four and three launches by the LDS
+ * each request's tile or grid takes, so that small tiles run several
+ * workgroups per compute unit next to requests with large ones.  Each result equals
  * what bin_particles gives for the same request, within the sum tolerance;
  * counts, min and max are identical.  Requests must not share output
  * buffers.  The request array is read during the call only.  Enqueues and

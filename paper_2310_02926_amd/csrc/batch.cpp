@@ -11,7 +11,7 @@
 // scratch (records, run table, counts, items, partial slots); the groups
 // share device tables of descriptors and block maps, uploaded once, and
 // each group runs one table-driven launch per stage for all its requests
-// (the binning stage as up to three launches, by the LDS of each request's
+// (the binning stage as up to four launches, by the LDS of each request's
 // tile or grid).  Requests that need the global-atomic strategy run one by
 // one.
 #include <algorithm>
@@ -213,22 +213,23 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
     g.map_walk.clear();
     g.map_item.clear();
     g.map_tile.clear();
-    // Tile-binning classes by the LDS of each request's tile: a quarter of
-    // a CU's LDS or less runs in 256-thread workgroups (four per CU), half
-    // or less in 512-thread ones (two per CU), larger tiles in 1024-thread
-    // ones.  Every CU then holds 16 waves either way, but small tiles have
-    // several work items in flight per CU, so one item's chain of dependent
-    // loads (its item record, its run table, its first records) and its
-    // result stores overlap another's binning: on batches of many small
-    // requests an item's fixed cost is several times its per-record cost.
-    std::vector<uint32_t> cls_items[3];
-    size_t cls_lds[3] = {0, 0, 0};
+    // Tile-binning classes by the LDS of each request's tile: an eighth of
+    // a CU's LDS or less runs in 128-thread workgroups (eight per CU), a
+    // quarter or less in 256-thread ones (four per CU), half or less in
+    // 512-thread ones (two per CU), larger tiles in 1024-thread ones.  Every
+    // CU then holds 16 waves either way, but small tiles have several work
+    // items in flight per CU, so one item's chain of dependent loads (its
+    // item record, its run table, its first records) and its result stores
+    // overlap another's binning: on batches of many small requests an
+    // item's fixed cost is several times its per-record cost.
+    std::vector<uint32_t> cls_items[4];
+    size_t cls_lds[4] = {0, 0, 0, 0};
     for (int r = 0; r < R; ++r) {
       const bk::PartArgs& a = g.args[r];
       for (int w = 0; w < a.nwg; ++w) g.map_wg.push_back(((uint32_t)r << 16) | (uint32_t)w);
       for (int b = 0; b < (a.ntiles + 15) / 16; ++b) g.map_walk.push_back(((uint32_t)r << 16) | (uint32_t)b);
       const size_t tl = bp->preps[g.idx[r]].pcfg.bin_lds;
-      const int q = 4 * tl <= dev.lds_per_cu ? 0 : 2 * tl <= dev.lds_per_cu ? 1 : 2;
+      const int q = 8 * tl <= dev.lds_per_cu ? 0 : 4 * tl <= dev.lds_per_cu ? 1 : 2 * tl <= dev.lds_per_cu ? 2 : 3;
       cls_lds[q] = std::max(cls_lds[q], tl);
       for (int i = 0; i < a.max_items; ++i) cls_items[q].push_back(((uint32_t)r << 16) | (uint32_t)i);
       for (int b = 0; b < a.merge_blocks; ++b) g.map_tile.push_back(((uint32_t)r << 16) | (uint32_t)b);
@@ -242,19 +243,19 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
     // share of every request; 0xFFFFFFFF pads to a whole round.  (Runs of
     // 8 beat 1, 4 and 32 on the 256-request batch and the nine-plane
     // multi-grid call.)
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < 4; ++q) {
       const size_t C = 8, round = 8 * C;
       const std::vector<uint32_t>& it = cls_items[q];
       const size_t nat = it.size(), npad = (nat + round - 1) / round * round;
       g.b.cls_first[q] = (int32_t)g.map_item.size();
-      g.b.cls_block[q] = 256 << q;
+      g.b.cls_block[q] = 128 << q;
       g.b.cls_lds[q] = (int32_t)cls_lds[q];
       for (size_t b = 0; b < npad; ++b) {
         const size_t i = b / round * round + (b % 8) * C + (b / 8) % C;
         g.map_item.push_back(i < nat ? it[i] : 0xFFFFFFFFu);
       }
     }
-    g.b.cls_first[3] = (int32_t)g.map_item.size();
+    g.b.cls_first[4] = (int32_t)g.map_item.size();
     g.b.n_wg_blocks = (int32_t)g.map_wg.size();
     g.b.n_walk_blocks = (int32_t)g.map_walk.size();
     g.b.n_item_blocks = (int32_t)g.map_item.size();

@@ -185,12 +185,12 @@ struct PartBatch {
   const uint32_t* map_item;  // binning blocks (index = work item)
   const uint32_t* map_tile;  // merge blocks (index = merge workgroup of the request)
   int32_t nreq, n_wg_blocks, n_walk_blocks, n_item_blocks, n_tile_blocks;
-  // The binning blocks run as up to three launches, one per class of tile
+  // The binning blocks run as up to four launches, one per class of tile
   // LDS: class c is map_item[cls_first[c], cls_first[c + 1]) with
   // cls_block[c] threads and cls_lds[c] bytes of LDS per workgroup.
-  int32_t cls_first[4];
-  int32_t cls_block[3];
-  int32_t cls_lds[3];
+  int32_t cls_first[5];
+  int32_t cls_block[4];
+  int32_t cls_lds[4];
 };
 
 // ---- several grids over one table: the fused scatter -----------------------

@@ -903,7 +903,7 @@ static hipError_t launch_part_batch_t(const PartBatch& b, const PartCfg& c, hipS
   }
   BK_LAUNCH("part_items_walk_kernel", part_items_walk_batched, b.n_walk_blocks, 1024, 0, b.descs, b.map_walk);
   BK_LAUNCH("part_items_kernel", part_items_batched, b.nreq, 1024, 0, b.descs);
-  for (int q = 0; q < 3; ++q) {
+  for (int q = 0; q < 4; ++q) {
     const int nb = b.cls_first[q + 1] - b.cls_first[q];
     if (c.quads)
       BK_LAUNCH("part_bin_kernel", (part_bin_batched<AT, PREC, true>), nb, b.cls_block[q], b.cls_lds[q], b.descs,

@@ -120,15 +120,17 @@ def test_batched_mixed_dtypes_and_strategies():
 
 
 def test_batched_lds_classes():
-    """Members whose tiles (tile binning) or whole grids (LDS strategy) take
-    up to a quarter, up to a half and more than half of a CU's LDS run as
-    separate launches of their own workgroup size; every result equals the
-    oracle and the same request run alone."""
+    """Members whose tiles (tile binning: up to an eighth, a quarter, a half
+    and more of a CU's LDS) or whole grids (LDS strategy: up to a quarter, a
+    half and more) fall in different classes run as separate launches of
+    their own workgroup size; every result equals the oracle and the same
+    request run alone."""
     import re
     from paper_2310_02926_amd import binding as B
     _case("batched LDS classes")
     A = B.OPS_ALL
     specs = [synth.InstanceSpec(200_000, 1024, 4, A, 11), synth.InstanceSpec(150_000, 1024, 2, A, 12),
+             synth.InstanceSpec(300_000, 512, 4, A, 18),
              synth.InstanceSpec(300_000, 256, 2, A, 13), synth.InstanceSpec(300_000, 256, 1, A, 14),
              synth.InstanceSpec(80_000, 32, 1, A, 15), synth.InstanceSpec(100_000, 64, 1, A, 16),
              synth.InstanceSpec(80_000, 48, 3, A, 17)]
@@ -142,8 +144,9 @@ def test_batched_lds_classes():
         d = B.bin_describe_plan(arr[i])
         kind = d.split()[0]
         size = int(re.search(r"bin_lds=(\d+)" if kind == "partition" else r"\blds=(\d+)", d).group(1))
-        seen[kind].add(0 if 4 * size <= cu_lds else 1 if 2 * size <= cu_lds else 2)
-    assert seen == {"partition": {0, 1, 2}, "lds": {0, 1, 2}}, seen
+        shares = (8, 4, 2) if kind == "partition" else (4, 2)
+        seen[kind].add(next((c for c, f in enumerate(shares) if f * size <= cu_lds), len(shares)))
+    assert seen == {"partition": {0, 1, 2, 3}, "lds": {0, 1, 2}}, seen
     B.bin_particles_batched(reqs)
     torch.cuda.synchronize()
     _check_vs_oracle(reqs, wss, "classes")
