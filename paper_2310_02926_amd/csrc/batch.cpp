@@ -278,6 +278,15 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
     for (int r = 0; r < R; ++r) {
       const Prepared& p = bp->preps[g.idx[r]];
       bk::LdsArgs a = p.lds;
+      // Slices twice as long as the request's own plan: that plan sized
+      // them to fill the device alone, while a batch shares it.  Half the
+      // partial slots to write and merge; on the 256-request batch the
+      // merge went from 0.16 to 0.07 ms, and four times as long made the
+      // binning's tail cost more than the merge saved.
+      if (a.nslots > 1) {
+        a.chunk = (a.chunk * 2 + 63) / 64 * 64;
+        a.nslots = (int32_t)cdiv(std::max<int64_t>(a.n, 1), a.chunk);
+      }
       a.partial = a.nslots > 1 ? take((size_t)a.lay.slot_bytes * a.nslots) : nullptr;
       g.args[r] = a;
       const size_t gl = p.cfg.lds_bytes;
