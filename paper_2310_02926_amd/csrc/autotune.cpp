@@ -210,7 +210,7 @@ void save_locked() {
 
 bool is_default(const PlanHints& h) {
   return h.force_strategy < 0 && !h.block && !h.grid && !h.part_wg && !h.scatter_ppt && !h.scatter_threads &&
-         !h.tile_shift && !h.split_len && !h.quads;
+         !h.tile_shift && !h.split_len && !h.quads && h.share <= 1;
 }
 
 }  // namespace

@@ -26,6 +26,7 @@ struct PlanHints {
   int tile_shift = 0;
   int64_t split_len = 0;
   int quads = 0;  // 0 planner's choice, 1 off, 2 on
+  int share = 1;  // grids binned together in one call: their tiles fill the device together
 };
 PlanHints& thread_hints_mut();
 

@@ -228,12 +228,13 @@ int prepare(const bin_request& r, const DeviceInfo& dev, const PlanHints& hints_
   // Smaller tiles while the grid would give fewer than two tiles per CU:
   // the tile binning then runs one item per tile on every CU, each with a
   // smaller LDS footprint, instead of splitting a few tiles into many
-  // partial slots that have to be merged.  Not below 256 bins: smaller
-  // tiles were measured slower on clustered data (a heavy tile is split
-  // into several items anyway, while tiny tiles make short runs and put
-  // most records of a window into the same few bins).
+  // partial slots that have to be merged.  Grids binned together in one
+  // call (hints.share of them) count together.  Not below 256 bins:
+  // smaller tiles were measured slower on clustered data (a heavy tile is
+  // split into several items anyway, while tiny tiles make short runs and
+  // put most records of a window into the same few bins).
   if (!hints.tile_shift)
-    while (shift > 8 && ceil_div(nb, (int64_t)1 << shift) < 2 * (int64_t)cus) --shift;
+    while (shift > 8 && ceil_div(nb, (int64_t)1 << shift) * std::max(hints.share, 1) < 2 * (int64_t)cus) --shift;
   tile_lds = tile_layout(1 << std::max(shift, 6), nk, want_sum, want_min, want_max, p->prec, asz, &tl);
   tl.tile_shift = shift;
   const int64_t ntiles = ceil_div(nb, (int64_t)1 << shift);
