@@ -631,6 +631,12 @@ __device__ __forceinline__ void part_bin_body(const PartArgs& a, int item) {
       constexpr int R = sizeof(AT) == 8 ? 1 : 2;
       constexpr int N = 4 * R;
       for (uint32_t wb = 0; 64 * (sub + wpg * wb) < total; wb += R) {
+        // The wave raises its issue priority while it maps its windows and
+        // issues their loads, and drops it again for the LDS updates: a wave
+        // about to issue gathers goes ahead of waves that only wait on the
+        // LDS, so more loads are in flight (2.5% off this kernel on the
+        // 2^27-particle 2048-square hotspot).
+        __builtin_amdgcn_s_setprio(3);
         uint32_t quad[R];
   #pragma unroll
         for (int u = 0; u < R; ++u) {
@@ -673,6 +679,7 @@ __device__ __forceinline__ void part_bin_body(const PartArgs& a, int item) {
   #pragma unroll
             for (int u = 0; u < R; ++u) ld_quad<AT>(a.rec_val[jj], quad[u], v[jj] + 4 * u);
           }
+        __builtin_amdgcn_s_setprio(0);
   #pragma unroll
         for (int e = 0; e < N; ++e)
           if (lb[e] >= 0) TL::count(smem, lb[e]);
@@ -731,6 +738,7 @@ __device__ __forceinline__ void part_bin_body(const PartArgs& a, int item) {
       // flight, to stay within the registers of a 1024-thread workgroup)
       constexpr int R = (sizeof(AT) == 8 || PREC == PREC_COMP) ? 4 : 8;
       for (uint32_t wb = 0; 64 * (sub + wpg * wb) < total; wb += R) {
+        __builtin_amdgcn_s_setprio(3);  // as in the quad gather: loads first
         uint32_t rec[R];
         int lb[R];
   #pragma unroll
@@ -769,6 +777,7 @@ __device__ __forceinline__ void part_bin_body(const PartArgs& a, int item) {
   #pragma unroll
             for (int u = 0; u < R; ++u) v[jj][u] = rec[u] != 0xFFFFFFFFu ? ld_keep<AT>(a.rec_val[jj], rec[u]) : AT(0);
           }
+        __builtin_amdgcn_s_setprio(0);
   #pragma unroll
         for (int u = 0; u < R; ++u)
           if (lb[u] >= 0) TL::count(smem, lb[u]);
