@@ -35,6 +35,25 @@ size_t al256(size_t v) { return (v + 255) & ~size_t(255); }
 size_t al16(size_t v) { return (v + 15) & ~size_t(15); }
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// The classes of a group's binning launches run one after another, so a
+// class with fewer blocks than the device has CUs would leave most of it
+// idle for its launch: its blocks join the next larger non-empty class
+// instead, whose workgroups are larger and whose LDS covers theirs.  (The
+// largest non-empty class keeps its own launch.)  A batch of a few requests
+// the server gathered then runs as one or two launches, as a batch of
+// hundreds runs as one per class.
+void merge_small_classes(std::vector<uint32_t>* cls, size_t* lds, int ncls, size_t min_blocks) {
+  for (int q = 0; q + 1 < ncls; ++q) {
+    if (cls[q].empty() || cls[q].size() >= min_blocks) continue;
+    int up = q + 1;
+    while (up < ncls && cls[up].empty()) ++up;
+    if (up == ncls) continue;
+    cls[up].insert(cls[up].end(), cls[q].begin(), cls[q].end());
+    lds[up] = std::max(lds[up], lds[q]);
+    cls[q].clear();
+  }
+}
+
 struct PartGroup {
   bool cf64 = false, af64 = false;
   int prec = 0;
@@ -247,6 +266,7 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
     // share of every request; 0xFFFFFFFF pads to a whole round.  (Runs of
     // 8 beat 1, 4 and 32 on the 256-request batch and the nine-plane
     // multi-grid call.)
+    merge_small_classes(cls_items, cls_lds, 4, (size_t)dev.cus);
     for (int q = 0; q < 4; ++q) {
       const size_t C = 8, round = 8 * C;
       const std::vector<uint32_t>& it = cls_items[q];
@@ -279,15 +299,20 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
     // longer holds every small request of the batch to one workgroup per CU.
     std::vector<uint32_t> cls_slots[3];
     size_t cls_lds[3] = {0, 0, 0};
+    // Slices twice as long as each request's own plan when the group's
+    // slices would still fill the device twice over: those plans size them
+    // to fill the device alone, while a large batch shares it.  Half the
+    // partial slots to write and merge; on the 256-request batch the merge
+    // went from 0.16 to 0.07 ms, and four times as long made the binning's
+    // tail cost more than the merge saved.  A small batch (a few requests
+    // the server gathered) keeps its requests' own slices and parallelism.
+    int64_t group_slots = 0;
+    for (int r = 0; r < R; ++r) group_slots += bp->preps[g.idx[r]].lds.nslots;
+    const bool longer = group_slots >= 4 * (int64_t)dev.cus;
     for (int r = 0; r < R; ++r) {
       const Prepared& p = bp->preps[g.idx[r]];
       bk::LdsArgs a = p.lds;
-      // Slices twice as long as the request's own plan: that plan sized
-      // them to fill the device alone, while a batch shares it.  Half the
-      // partial slots to write and merge; on the 256-request batch the
-      // merge went from 0.16 to 0.07 ms, and four times as long made the
-      // binning's tail cost more than the merge saved.
-      if (a.nslots > 1) {
+      if (longer && a.nslots > 1) {
         a.chunk = (a.chunk * 2 + 63) / 64 * 64;
         a.nslots = (int32_t)cdiv(std::max<int64_t>(a.n, 1), a.chunk);
       }
@@ -300,6 +325,7 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
       if (a.nslots > 1)
         for (int64_t c = 0; c < cdiv(a.nbins, 64); ++c) g.map_merge.push_back(((uint32_t)r << 16) | (uint32_t)c);
     }
+    merge_small_classes(cls_slots, cls_lds, 3, (size_t)dev.cus);
     for (int q = 0; q < 3; ++q) {
       g.b.cls_first[q] = (int32_t)g.map_slot.size();
       g.b.cls_block[q] = q == 0 ? 512 : 1024;

@@ -133,7 +133,9 @@ def test_batched_lds_classes():
              synth.InstanceSpec(300_000, 512, 4, A, 18),
              synth.InstanceSpec(300_000, 256, 2, A, 13), synth.InstanceSpec(300_000, 256, 1, A, 14),
              synth.InstanceSpec(80_000, 32, 1, A, 15), synth.InstanceSpec(100_000, 64, 1, A, 16),
-             synth.InstanceSpec(80_000, 48, 3, A, 17)]
+             synth.InstanceSpec(80_000, 48, 3, A, 17),
+             # a whole grid its own plan bins in two slices
+             synth.InstanceSpec(20_000, 32, 2, A, 19)]
     wss = [synth.instance(sp) for sp in specs]
     reqs = _requests(wss)
     arr, keep = B.request_array(reqs)
