@@ -526,13 +526,25 @@ class Server:
     def submit(self, coords, attrs, n, axes, bounds, nx, ny, ops, producer_stream=None) -> int:
         """Queue a request; ``producer_stream`` (a torch stream or handle)
         is the stream whose queued work writes the columns, if any."""
+        return self.submit_prepared(self.prepare(coords, attrs, n, axes, bounds, nx, ny, ops, producer_stream))
+
+    @staticmethod
+    def prepare(coords, attrs, n, axes, bounds, nx, ny, ops, producer_stream=None):
+        """A request marshalled once (the arguments of submit), for
+        submit_prepared: a caller that submits the same columns every step
+        pays the marshalling once."""
         c, ck = columns(coords)
         a, ak = columns(attrs) if attrs else (Columns(None, 0, BIN_F32), None)
         ps = None if producer_stream is None else _stream_handle(producer_stream)
         req = ServerRequest(c, a, n, (c_int32 * 2)(*axes), (c_double * 4)(*bounds), nx, ny, ops, ps)
+        return req, (coords, attrs, ck, ak, (nx, ny, ops, len(attrs or [])))
+
+    def submit_prepared(self, prepared) -> int:
+        """Queue a request made by prepare()."""
+        req, keep = prepared
         t = c_uint64()
         check(lib().binsrv_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
-        self._keep[t.value] = (coords, attrs, ck, ak, (nx, ny, ops, len(attrs or [])))
+        self._keep[t.value] = keep
         return int(t.value)
 
     def wait(self, ticket: int, timeout_s: Optional[float] = None) -> Result:

@@ -81,6 +81,27 @@ def test_server_results_equal_alone_and_oracle():
         srv.destroy()
 
 
+def test_server_prepared_requests_submitted_again():
+    """A request marshalled once (Server.prepare) and submitted three times
+    gives three results equal to the oracle's."""
+    from paper_2310_02926_amd import binding as B
+    _case("server: one prepared request submitted three times")
+    ws = synth.instance(synth.batch_specs(1, seed=33, n_lo=5e4, n_hi=2e5)[0])
+    c, a = G.to_device(ws)
+    srv = B.Server(budget_bytes=1 << 30, n_slots=2, max_batch=8)
+    try:
+        prep = srv.prepare(c, a, ws.n, ws.axes, ws.bounds, ws.nx, ws.ny, ws.ops)
+        tickets = [srv.submit_prepared(prep) for _ in range(3)]
+        ref = G.oracle(ws)
+        for t in tickets:
+            res = srv.wait(t, timeout_s=60)
+            assert res.status == B.BIN_OK
+            G.assert_parity(srv.fetch(t, res), ref, ws.ops, what=f"prepared ticket {t}")
+            srv.release(t)
+    finally:
+        srv.destroy()
+
+
 def test_server_budget_admission_and_errors():
     from paper_2310_02926_amd import binding as B
     _case("server: tight budget")
