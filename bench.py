@@ -55,7 +55,7 @@ def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2310_02926_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        if (f.endswith((".hip", ".h")) and f not in ("internal.h", "server_admit.h")) or f == "plan.cpp":
+        if (f.endswith((".hip", ".h")) and f not in ("internal.h", "server_admit.h", "batch_classes.h")) or f == "plan.cpp":
             h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -25,6 +25,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "batch_classes.h"
 #include "internal.h"
 
 namespace binimpl {
@@ -34,25 +35,6 @@ namespace {
 size_t al256(size_t v) { return (v + 255) & ~size_t(255); }
 size_t al16(size_t v) { return (v + 15) & ~size_t(15); }
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
-
-// The classes of a group's binning launches run one after another, so a
-// class with fewer blocks than the device has CUs would leave most of it
-// idle for its launch: its blocks join the next larger non-empty class
-// instead, whose workgroups are larger and whose LDS covers theirs.  (The
-// largest non-empty class keeps its own launch.)  A batch of a few requests
-// the server gathered then runs as one or two launches, as a batch of
-// hundreds runs as one per class.
-void merge_small_classes(std::vector<uint32_t>* cls, size_t* lds, int ncls, size_t min_blocks) {
-  for (int q = 0; q + 1 < ncls; ++q) {
-    if (cls[q].empty() || cls[q].size() >= min_blocks) continue;
-    int up = q + 1;
-    while (up < ncls && cls[up].empty()) ++up;
-    if (up == ncls) continue;
-    cls[up].insert(cls[up].end(), cls[q].begin(), cls[q].end());
-    lds[up] = std::max(lds[up], lds[q]);
-    cls[q].clear();
-  }
-}
 
 struct PartGroup {
   bool cf64 = false, af64 = false;
@@ -252,7 +234,8 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
       for (int w = 0; w < a.nwg; ++w) g.map_wg.push_back(((uint32_t)r << 16) | (uint32_t)w);
       for (int b = 0; b < (a.ntiles + 15) / 16; ++b) g.map_walk.push_back(((uint32_t)r << 16) | (uint32_t)b);
       const size_t tl = bp->preps[g.idx[r]].pcfg.bin_lds;
-      const int q = 8 * tl <= dev.lds_per_cu ? 0 : 4 * tl <= dev.lds_per_cu ? 1 : 2 * tl <= dev.lds_per_cu ? 2 : 3;
+      static const int kTileShares[3] = {8, 4, 2};
+      const int q = lds_class(tl, dev.lds_per_cu, kTileShares, 3);
       cls_lds[q] = std::max(cls_lds[q], tl);
       for (int i = 0; i < a.max_items; ++i) cls_items[q].push_back(((uint32_t)r << 16) | (uint32_t)i);
       for (int b = 0; b < a.merge_blocks; ++b) g.map_tile.push_back(((uint32_t)r << 16) | (uint32_t)b);
@@ -319,7 +302,8 @@ int plan_batch(const bin_request* reqs, int nreq, const DeviceInfo& dev, const P
       a.partial = a.nslots > 1 ? take((size_t)a.lay.slot_bytes * a.nslots) : nullptr;
       g.args[r] = a;
       const size_t gl = p.cfg.lds_bytes;
-      const int q = 4 * gl <= dev.lds_per_cu ? 0 : 2 * gl <= dev.lds_per_cu ? 1 : 2;
+      static const int kGridShares[2] = {4, 2};
+      const int q = lds_class(gl, dev.lds_per_cu, kGridShares, 2);
       cls_lds[q] = std::max(cls_lds[q], gl);
       for (int s = 0; s < a.nslots; ++s) cls_slots[q].push_back(((uint32_t)r << 16) | (uint32_t)s);
       if (a.nslots > 1)
